@@ -1,0 +1,219 @@
+"""ctypes wrapper of the plain C oracle ``amber_oracle.c`` (TEST INFRASTRUCTURE).
+
+Only tests, the smoke check and the benchmark's CPU-baseline leg use this.  The
+arithmetic lives in the C file and in ``thresholds.py``; this module only
+marshals numpy arrays.  Descriptor defaults (grid side, initial infected count)
+are derived here from their definitions, independently of the GPU library.
+
+Model statement followed: synchronous columnar updates (Sec. 3.4) of the three
+benchmark models of Sec. 5.1.2, reformulated on an L x L torus grid with
+counter-based Philox randomness; invariants of Sec. 5.1.3.
+"""
+import ctypes
+import math
+import os
+
+import numpy as np
+
+from . import thresholds
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+
+WEALTH, RANDOM_WALK, SIR = 0, 1, 2
+P_INIT_POS, P_MOVE, P_EPI, P_RECIPIENT = 0, 1, 2, 3
+
+_lib = None
+
+_u32 = ctypes.c_uint32
+_i32 = ctypes.c_int32
+_p = ctypes.c_void_p
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from . import build_oracle
+            build_oracle.build()
+        L = ctypes.CDLL(LIB_PATH)
+        L.orc_philox4x32_10.argtypes = [_p, _u32, _u32, _p]
+        L.orc_word.argtypes = [_u32] * 7
+        L.orc_word.restype = _u32
+        L.orc_recipient.argtypes = [_u32] * 5
+        L.orc_recipient.restype = _u32
+        L.orc_wealth_apply.argtypes = [_u32, _p, _p, _p]
+        L.orc_neighbour_infected.argtypes = [_u32, _p, _i32, _i32]
+        L.orc_neighbour_infected.restype = ctypes.c_uint64
+        L.orc_digest.argtypes = [_u32, _u32, _p, _p]
+        L.orc_digest.restype = ctypes.c_uint64
+        L.orc_invariants.argtypes = [_u32, _u32, _p, _p, _p, _p, _p]
+        L.orc_run_wealth.argtypes = [_u32, _i32, _u32, _u32, _u32, _u32, _p, ctypes.c_int]
+        L.orc_run_walk.argtypes = [_u32, _u32, _u32, _u32, _u32, _u32, _p, _p, ctypes.c_int]
+        L.orc_walk_agents.argtypes = [_u32, _p, _u32, _u32, _u32, _u32, _p, _p]
+        L.orc_run_sir.argtypes = [_u32, _u32, _u32, _u32, _u32, _p, _u32, _u32,
+                                  _u32, _u32, _p, _p, _p, ctypes.c_int]
+        for f in (L.orc_run_wealth, L.orc_run_walk, L.orc_walk_agents, L.orc_run_sir):
+            f.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return ctypes.c_void_p(a.ctypes.data) if a is not None else None
+
+
+# ------------------------------------------------------------------ defaults
+
+def grid_side(n: int) -> int:
+    """round(sqrt(n)) with halves rounded up, in integers: s = isqrt(n) and
+    L = s + 1 iff n > s^2 + s (i.e. sqrt(n) > s + 1/2)."""
+    s = math.isqrt(n)
+    return s + 1 if n > s * s + s else s
+
+
+def default_initial_infected(n: int) -> int:
+    """0.1% of the population, halves rounded up, at least one agent."""
+    return max(1, (n + 500) // 1000)
+
+
+# ------------------------------------------------------------------ random
+
+def philox(ctr, k0: int, k1: int):
+    c = np.array(ctr, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().orc_philox4x32_10(_ptr(c), k0, k1, _ptr(out))
+    return [int(v) for v in out]
+
+
+def word(seed, stream, purpose, words_per_agent, t, a, j):
+    return int(lib().orc_word(seed, stream, purpose, words_per_agent, t, a, j))
+
+
+def recipient(n, seed, stream, t, a):
+    return int(lib().orc_recipient(n, seed, stream, t, a))
+
+
+# ------------------------------------------------------------------ pieces
+
+def wealth_apply(w, recip):
+    """One synchronous transfer round with given recipients (donors: w > 0)."""
+    w = np.array(w, dtype=np.int32)
+    r = np.ascontiguousarray(recip, dtype=np.uint32)
+    scratch = np.zeros_like(w)
+    lib().orc_wealth_apply(len(w), _ptr(w), _ptr(r), _ptr(scratch))
+    return w
+
+
+def neighbour_infected(L, C, cx, cy):
+    C = np.ascontiguousarray(C, dtype=np.uint32).reshape(-1)
+    assert C.size == L * L
+    return int(lib().orc_neighbour_infected(L, _ptr(C), cx, cy))
+
+
+def digest(cols):
+    """Order-free 64-bit digest of a population given its columns in order."""
+    cols = [np.ascontiguousarray(c) for c in cols]
+    n = len(cols[0])
+    ptrs = (ctypes.c_void_p * len(cols))(*[c.ctypes.data for c in cols])
+    widths = np.array([c.dtype.itemsize for c in cols], dtype=np.uint32)
+    return int(lib().orc_digest(n, len(cols), ptrs, _ptr(widths)))
+
+
+class _Inv(ctypes.Structure):
+    _fields_ = [("wealth_sum", ctypes.c_int64), ("wealth_min", ctypes.c_int32),
+                ("n_s", ctypes.c_uint64), ("n_i", ctypes.c_uint64),
+                ("n_r", ctypes.c_uint64), ("out_of_bounds", ctypes.c_uint64)]
+
+
+def invariants(n, L=0, w=None, x=None, y=None, s=None):
+    out = _Inv()
+    lib().orc_invariants(n, L, _ptr(w), _ptr(x), _ptr(y), _ptr(s), ctypes.byref(out))
+    return {f: getattr(out, f) for f, _ in _Inv._fields_}
+
+
+# ------------------------------------------------------------------ runs
+
+class OracleRun:
+    """One simulation held on the host; ``step(k)`` advances steps t..t+k-1.
+
+    Parameters mirror the GPU descriptor: model, n, grid side L (0 = round
+    sqrt n), seed, stream, wealth_init, beta/gamma as num/den, initial
+    infected (0 = default)."""
+
+    def __init__(self, model, n, L=0, seed=0, stream=0, wealth_init=1,
+                 beta=(1, 20), gamma=(1, 100), initial_infected=0):
+        if n < 1:
+            raise ValueError("n must be >= 1")
+        self.model, self.n, self.seed, self.stream = model, n, seed, stream
+        self.t = 0
+        if model == WEALTH:
+            self.L = 0
+            self.w = np.zeros(n, dtype=np.int32)
+            rc = lib().orc_run_wealth(n, wealth_init, seed, stream, 0, 0, _ptr(self.w), 1)
+        elif model in (RANDOM_WALK, SIR):
+            self.L = L if L else grid_side(n)
+            self.x = np.zeros(n, dtype=np.int32)
+            self.y = np.zeros(n, dtype=np.int32)
+            if model == RANDOM_WALK:
+                rc = lib().orc_run_walk(n, self.L, seed, stream, 0, 0,
+                                        _ptr(self.x), _ptr(self.y), 1)
+            else:
+                self.i0 = initial_infected if initial_infected else default_initial_infected(n)
+                self.t_inf, self.k_sat = thresholds.infection_table(*beta)
+                self.t_inf = np.array(self.t_inf, dtype=np.uint32)
+                self.t_rec = thresholds.recovery_threshold(*gamma)
+                self.s = np.zeros(n, dtype=np.uint8)
+                rc = self._sir(0, 0, 1)
+        else:
+            raise ValueError("unknown model")
+        if rc != 0:
+            raise RuntimeError("oracle init failed")
+
+    def _sir(self, t0, k, do_init):
+        return lib().orc_run_sir(self.n, self.L, self.seed, self.stream, self.i0,
+                                 _ptr(self.t_inf), self.k_sat, self.t_rec, t0, k,
+                                 _ptr(self.x), _ptr(self.y), _ptr(self.s), do_init)
+
+    def step(self, k=1):
+        if self.model == WEALTH:
+            rc = lib().orc_run_wealth(self.n, 0, self.seed, self.stream, self.t, k,
+                                      _ptr(self.w), 0)
+        elif self.model == RANDOM_WALK:
+            rc = lib().orc_run_walk(self.n, self.L, self.seed, self.stream, self.t, k,
+                                    _ptr(self.x), _ptr(self.y), 0)
+        else:
+            rc = self._sir(self.t, k, 0)
+        if rc != 0:
+            raise RuntimeError("oracle step failed")
+        self.t += k
+        return self
+
+    def columns(self):
+        if self.model == WEALTH:
+            return [self.w]
+        if self.model == RANDOM_WALK:
+            return [self.x, self.y]
+        return [self.x, self.y, self.s]
+
+    def digest(self):
+        return digest(self.columns())
+
+    def invariants(self):
+        if self.model == WEALTH:
+            return invariants(self.n, 0, w=self.w)
+        if self.model == RANDOM_WALK:
+            return invariants(self.n, self.L, x=self.x, y=self.y)
+        return invariants(self.n, self.L, x=self.x, y=self.y, s=self.s)
+
+
+def walk_agents(ids, L, seed, stream, n_steps):
+    """Positions after n_steps of the listed random-walk agents, each replayed
+    alone from its initial position."""
+    ids = np.ascontiguousarray(ids, dtype=np.uint32)
+    x = np.zeros(len(ids), dtype=np.int32)
+    y = np.zeros(len(ids), dtype=np.int32)
+    rc = lib().orc_walk_agents(len(ids), _ptr(ids), L, seed, stream, n_steps, _ptr(x), _ptr(y))
+    if rc != 0:
+        raise RuntimeError("oracle walk_agents failed")
+    return x, y
