@@ -1,0 +1,212 @@
+/*
+ * amber.h -- C ABI of libamber, the MI355X (gfx950) hot path of a columnar
+ * agent-based-modelling engine.
+ *
+ * Method: "AMBER: A Columnar Architecture for Scalable Agent-Based Modelling
+ * in Python" (arXiv 2601.16292).  Agent state is a set of typed columns over
+ * sequential agent ids (Sec. 3.1.1); a model step is a composition of
+ * full-population, filtered and id-indexed scatter updates (Sec. 3.1.1
+ * listings, Sec. 3.3) applied with synchronous snapshot semantics (Sec. 3.4).
+ * The three models are the benchmark models of Sec. 5.1.2, stated here on a
+ * torus grid with counter-based randomness:
+ *
+ *   WEALTH       every agent with wealth > 0 (filtered view) gives one unit to
+ *                a recipient drawn uniformly from all N agents (self allowed);
+ *                duplicate recipients accumulate (scatter-add view).
+ *   RANDOM_WALK  every agent (full view) moves to one of its 8 Moore
+ *                neighbours on an L x L torus (grid environment, Sec. 4.1).
+ *   SIR          every agent moves as in RANDOM_WALK; then each susceptible
+ *                agent with k infected agents in the distinct cells of its
+ *                3x3 torus block becomes infected with probability
+ *                1-(1-beta)^k, and each infected agent recovers with
+ *                probability gamma (Sec. 5.1.2; torus-wrap neighbour
+ *                deduplication, Sec. 6.1).
+ *
+ * Random numbers: Philox4x32-10 keyed (seed, stream).  Word j of agent a for
+ * purpose p at step t is word (g mod 4) of the block at counter
+ * (floor(g/4), t, p, 0) with g = a*W_p + j; purposes INIT_POS (p=0, W=2),
+ * MOVE (1, 1), EPI (2, 1), RECIPIENT (3, 2).  Mappings: grid coordinate
+ * floor(u*L/2^32); recipient floor((hi:lo)*N/2^64); direction u>>29 into the
+ * moves (dx,dy) in lexicographic order without (0,0); Bernoulli(p) is
+ * u < floor(p*2^32) computed exactly from the rational p.  All device
+ * arithmetic is integer, so every result is bit-exact and independent of
+ * launch shape, chunking and batching.
+ *
+ * Ownership: the caller owns every device buffer (columns and workspace) and
+ * the HIP stream; they must outlive the handle.  The library allocates no
+ * device memory; a handle owns host memory only.  Device pointers are plain
+ * HIP device addresses on the current device.
+ *
+ * Errors: every call returns an amber_status_t; nothing aborts or throws
+ * across the ABI.  On a validation failure nothing is written to any buffer.
+ * amber_last_error() returns a thread-local message for the last failure.
+ *
+ * Concurrency: calls on one handle are ordered on its stream; a handle must
+ * not be used from two threads at once.  Only amber_read_columns and
+ * amber_invariants synchronise with the host.
+ */
+#ifndef AMBER_H
+#define AMBER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define AMBER_ABI_VERSION 1u
+
+#if defined(__GNUC__)
+#define AMBER_API __attribute__((visibility("default")))
+#else
+#define AMBER_API
+#endif
+
+/* Largest infection-threshold table (entries) a SIR run may need. */
+#define AMBER_MAX_TABLE 8192u
+
+typedef enum {
+    AMBER_WEALTH = 0,
+    AMBER_RANDOM_WALK = 1,
+    AMBER_SIR = 2
+} amber_model_t;
+
+typedef enum {
+    AMBER_OK = 0,
+    AMBER_E_INVALID = -1,      /* bad argument or descriptor                 */
+    AMBER_E_NOMEM = -2,        /* host allocation failed / workspace too small */
+    AMBER_E_DEVICE = -3,       /* a HIP call failed                          */
+    AMBER_E_STATE = -4,        /* handle misuse (released, mixed devices)    */
+    AMBER_E_UNSUPPORTED = -5   /* valid but outside what this build supports */
+} amber_status_t;
+
+typedef enum {
+    AMBER_COL_WEALTH = 0,      /* int32, WEALTH                 */
+    AMBER_COL_X = 1,           /* int32 in [0, L), RANDOM_WALK and SIR */
+    AMBER_COL_Y = 2,           /* int32 in [0, L), RANDOM_WALK and SIR */
+    AMBER_COL_STATE = 3        /* uint8 0=S 1=I 2=R, SIR         */
+} amber_col_t;
+#define AMBER_NUM_COLS 4
+
+/* One simulation run.  Fields a model does not use are ignored. */
+typedef struct {
+    uint32_t abi_version;      /* must equal AMBER_ABI_VERSION                       */
+    uint32_t model;            /* amber_model_t                                      */
+    uint32_t n_agents;         /* N, 1 .. 2^31-1                                     */
+    uint32_t grid_side;        /* L for RANDOM_WALK/SIR; 0 = round(sqrt(N)) (halves
+                                  up); needs 1 <= L and L*L <= 2^31-1                */
+    uint32_t seed;             /* Philox key word 0                                  */
+    uint32_t stream;           /* Philox key word 1: replicate / request id          */
+    int32_t  wealth_init;      /* WEALTH: initial wealth >= 0, N*wealth_init < 2^31  */
+    uint32_t beta_num, beta_den;   /* SIR: beta = num/den, 0 <= num < den            */
+    uint32_t gamma_num, gamma_den; /* SIR: gamma = num/den, 0 <= num < den           */
+    uint32_t initial_infected; /* SIR: agents 0..I0-1 start infected; 0 = default
+                                  max(1, floor((N+500)/1000)); must be <= N          */
+} amber_run_desc_t;
+
+/* Device buffers of one run, all caller-owned.  col[c] must be non-NULL and
+ * 16-byte aligned, with at least amber_column_bytes(desc, c) bytes, for every
+ * column the model uses (NULL otherwise).  Bytes past N in a column are
+ * padding the library may overwrite.  workspace must be 256-byte aligned with
+ * at least amber_workspace_bytes(desc) bytes; the library owns its contents
+ * for the handle's life. */
+typedef struct {
+    void  *col[AMBER_NUM_COLS];
+    void  *workspace;
+    size_t workspace_bytes;
+} amber_buffers_t;
+
+/* Population invariants (Sec. 5.1.3): wealth is conserved, coordinates stay
+ * on the grid, S+I+R = N.  Fields not used by the model are 0. */
+typedef struct {
+    uint64_t step;             /* number of steps taken since init               */
+    int64_t  wealth_sum;
+    int32_t  wealth_min;
+    uint32_t reserved0;
+    uint64_t n_s, n_i, n_r;
+    uint64_t out_of_bounds;    /* rows outside the model's domain (w<0, x or y
+                                  outside [0,L), state code > 2)                */
+    uint64_t digest;           /* sum over agents a (mod 2^64) of h_a: h =
+                                  fmix64(a), then per column value v_j in
+                                  column order h = fmix64(h ^ ((j+1)<<32 | v_j));
+                                  fmix64 is SplitMix64's finaliser            */
+} amber_invariants_t;
+
+/* Resolved parameters of a handle. */
+typedef struct {
+    uint32_t model, n_agents, grid_side, initial_infected;
+    uint32_t seed, stream;
+    uint32_t table_len;        /* SIR: entries in the infection table (k_sat+1) */
+    uint32_t t_rec;            /* SIR: recovery threshold                        */
+    uint64_t step;
+} amber_pop_info_t;
+
+typedef struct amber_pop amber_pop_t;   /* opaque host-side handle */
+
+/* ABI version of the loaded library (AMBER_ABI_VERSION). */
+AMBER_API uint32_t amber_abi_version(void);
+
+/* Bytes the caller must allocate for column c (0 if the model does not use
+ * it, or if the descriptor is invalid).  Rounded up to whole 64-agent groups. */
+AMBER_API size_t amber_column_bytes(const amber_run_desc_t *desc, amber_col_t c);
+
+/* Bytes of device workspace the run needs (0 if the descriptor is invalid;
+ * every valid run needs some).  This is also the run's footprint beyond its
+ * columns for admission by HBM budget. */
+AMBER_API size_t amber_workspace_bytes(const amber_run_desc_t *desc);
+
+/* Exact infection thresholds T[k] = floor(2^32 (1-(1-beta)^k)), k = 0..k_sat,
+ * where k_sat is the first k with T = 2^32-1 (0 when beta = 0), computed on the
+ * host with big-integer arithmetic.  Writes min(k_sat+1, cap) entries to out
+ * and k_sat to *k_sat.  AMBER_E_INVALID for a bad beta, AMBER_E_UNSUPPORTED
+ * when k_sat+1 > AMBER_MAX_TABLE. */
+AMBER_API amber_status_t amber_infection_table(uint32_t beta_num, uint32_t beta_den,
+                                     uint32_t *out, uint32_t cap, uint32_t *k_sat);
+
+/* Bulk-create N agents (the bulk add_agents of Sec. 3.3): WEALTH sets every
+ * wealth to wealth_init; RANDOM_WALK and SIR draw x and y uniformly on the
+ * grid (INIT_POS words); SIR marks agents 0..I0-1 infected, the rest
+ * susceptible.  Enqueues on hip_stream (a hipStream_t; NULL = default
+ * stream) and returns a handle at step 0.  Does not synchronise. */
+AMBER_API amber_status_t amber_init_population(const amber_run_desc_t *desc,
+                                     const amber_buffers_t *bufs,
+                                     void *hip_stream, amber_pop_t **out);
+
+/* Enqueue steps t .. t+n_steps-1 of the model on the handle's stream, where t
+ * is the handle's step count; on return the step count is t+n_steps.  When
+ * the enqueued work completes, the caller's columns hold the state after
+ * those steps.  Any split of a run into calls gives bit-identical results. */
+AMBER_API amber_status_t amber_step(amber_pop_t *pop, uint32_t n_steps);
+
+/* Enqueue the same n_steps on each of n handles as fused batched launches
+ * (one kernel per phase for all runs), ordered on the first handle's stream
+ * (the other handles' streams are joined before and after).  Results are
+ * bit-identical to calling amber_step on each handle alone.  Handles must be
+ * distinct and on one device; models may be mixed. */
+AMBER_API amber_status_t amber_step_batch(amber_pop_t *const *pops, uint32_t n, uint32_t n_steps);
+
+/* Copy the columns selected by col_mask (bit c = column c) to host memory:
+ * host_dst[c] receives N elements of column c.  Synchronises the stream. */
+AMBER_API amber_status_t amber_read_columns(amber_pop_t *pop, uint32_t col_mask,
+                                  void *const *host_dst);
+
+/* Reduce the invariants and the digest on the device and copy them to *out.
+ * Synchronises the stream. */
+AMBER_API amber_status_t amber_invariants(amber_pop_t *pop, amber_invariants_t *out);
+
+/* Resolved parameters and step count of a handle (host only, no sync). */
+AMBER_API amber_status_t amber_pop_info(const amber_pop_t *pop, amber_pop_info_t *out);
+
+/* Free the handle (host memory only; device buffers stay the caller's).
+ * Waits for the handle's enqueued work first. */
+AMBER_API amber_status_t amber_release(amber_pop_t *pop);
+
+/* Message for the last failed call on this thread ("" if none). */
+AMBER_API const char *amber_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AMBER_H */

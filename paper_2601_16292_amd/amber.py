@@ -1,0 +1,285 @@
+"""ctypes binding of libamber (include/amber.h): argument marshalling only.
+
+Every function mirrors the C entry point of the same name and returns its
+status code; ``check`` turns a non-zero status into ``AmberError`` with the
+library's message.  ``Population`` is a convenience owner of the device
+buffers one run needs (PyTorch tensors on the current device) and of the
+handle; every step of the path runs in the library's HIP kernels.
+
+There is no CPU fallback: loading fails loudly when ``libamber.so`` is
+missing.
+"""
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libamber.so")
+
+ABI_VERSION = 1
+MAX_TABLE = 8192
+
+WEALTH, RANDOM_WALK, SIR = 0, 1, 2
+COL_WEALTH, COL_X, COL_Y, COL_STATE = 0, 1, 2, 3
+NUM_COLS = 4
+
+OK, E_INVALID, E_NOMEM, E_DEVICE, E_STATE, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+STATUS_NAMES = {0: "AMBER_OK", -1: "AMBER_E_INVALID", -2: "AMBER_E_NOMEM",
+                -3: "AMBER_E_DEVICE", -4: "AMBER_E_STATE", -5: "AMBER_E_UNSUPPORTED"}
+
+MODEL_COLUMNS = {WEALTH: [COL_WEALTH], RANDOM_WALK: [COL_X, COL_Y],
+                 SIR: [COL_X, COL_Y, COL_STATE]}
+
+EXPORTED = ["amber_abi_version", "amber_column_bytes", "amber_workspace_bytes",
+            "amber_infection_table", "amber_init_population", "amber_step",
+            "amber_step_batch", "amber_read_columns", "amber_invariants",
+            "amber_pop_info", "amber_release", "amber_last_error"]
+
+
+class RunDesc(ctypes.Structure):
+    _fields_ = [("abi_version", ctypes.c_uint32), ("model", ctypes.c_uint32),
+                ("n_agents", ctypes.c_uint32), ("grid_side", ctypes.c_uint32),
+                ("seed", ctypes.c_uint32), ("stream", ctypes.c_uint32),
+                ("wealth_init", ctypes.c_int32),
+                ("beta_num", ctypes.c_uint32), ("beta_den", ctypes.c_uint32),
+                ("gamma_num", ctypes.c_uint32), ("gamma_den", ctypes.c_uint32),
+                ("initial_infected", ctypes.c_uint32)]
+
+
+class Buffers(ctypes.Structure):
+    _fields_ = [("col", ctypes.c_void_p * NUM_COLS), ("workspace", ctypes.c_void_p),
+                ("workspace_bytes", ctypes.c_size_t)]
+
+
+class Invariants(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_uint64), ("wealth_sum", ctypes.c_int64),
+                ("wealth_min", ctypes.c_int32), ("reserved0", ctypes.c_uint32),
+                ("n_s", ctypes.c_uint64), ("n_i", ctypes.c_uint64), ("n_r", ctypes.c_uint64),
+                ("out_of_bounds", ctypes.c_uint64), ("digest", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved0"}
+
+
+class PopInfo(ctypes.Structure):
+    _fields_ = [("model", ctypes.c_uint32), ("n_agents", ctypes.c_uint32),
+                ("grid_side", ctypes.c_uint32), ("initial_infected", ctypes.c_uint32),
+                ("seed", ctypes.c_uint32), ("stream", ctypes.c_uint32),
+                ("table_len", ctypes.c_uint32), ("t_rec", ctypes.c_uint32),
+                ("step", ctypes.c_uint64)]
+
+
+class AmberError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libamber.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                              "(there is no CPU fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.c_void_p
+        L.amber_abi_version.restype = ctypes.c_uint32
+        L.amber_abi_version.argtypes = []
+        L.amber_column_bytes.restype = ctypes.c_size_t
+        L.amber_column_bytes.argtypes = [ctypes.POINTER(RunDesc), ctypes.c_int]
+        L.amber_workspace_bytes.restype = ctypes.c_size_t
+        L.amber_workspace_bytes.argtypes = [ctypes.POINTER(RunDesc)]
+        L.amber_infection_table.restype = ctypes.c_int
+        L.amber_infection_table.argtypes = [ctypes.c_uint32, ctypes.c_uint32, P,
+                                            ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32)]
+        L.amber_init_population.restype = ctypes.c_int
+        L.amber_init_population.argtypes = [ctypes.POINTER(RunDesc), ctypes.POINTER(Buffers),
+                                            P, ctypes.POINTER(P)]
+        L.amber_step.restype = ctypes.c_int
+        L.amber_step.argtypes = [P, ctypes.c_uint32]
+        L.amber_step_batch.restype = ctypes.c_int
+        L.amber_step_batch.argtypes = [ctypes.POINTER(P), ctypes.c_uint32, ctypes.c_uint32]
+        L.amber_read_columns.restype = ctypes.c_int
+        L.amber_read_columns.argtypes = [P, ctypes.c_uint32, ctypes.POINTER(P)]
+        L.amber_invariants.restype = ctypes.c_int
+        L.amber_invariants.argtypes = [P, ctypes.POINTER(Invariants)]
+        L.amber_pop_info.restype = ctypes.c_int
+        L.amber_pop_info.argtypes = [P, ctypes.POINTER(PopInfo)]
+        L.amber_release.restype = ctypes.c_int
+        L.amber_release.argtypes = [P]
+        L.amber_last_error.restype = ctypes.c_char_p
+        L.amber_last_error.argtypes = []
+        _lib = L
+    return _lib
+
+
+def amber_last_error():
+    return lib().amber_last_error().decode()
+
+
+def check(status):
+    if status != OK:
+        raise AmberError(status, amber_last_error())
+    return status
+
+
+# ------------------------------------------------------------------ same-name wrappers
+
+def amber_abi_version():
+    return lib().amber_abi_version()
+
+
+def amber_column_bytes(desc, col):
+    return lib().amber_column_bytes(ctypes.byref(desc), col)
+
+
+def amber_workspace_bytes(desc):
+    return lib().amber_workspace_bytes(ctypes.byref(desc))
+
+
+def amber_infection_table(beta_num, beta_den, cap=MAX_TABLE):
+    """Returns (status, table list, k_sat)."""
+    out = (ctypes.c_uint32 * cap)()
+    k_sat = ctypes.c_uint32(0)
+    st = lib().amber_infection_table(beta_num, beta_den, out, cap, ctypes.byref(k_sat))
+    if st != OK:
+        return st, None, None
+    return st, list(out[:min(cap, k_sat.value + 1)]), k_sat.value
+
+
+def amber_init_population(desc, bufs, stream_ptr):
+    """Returns (status, handle)."""
+    h = ctypes.c_void_p()
+    st = lib().amber_init_population(ctypes.byref(desc), ctypes.byref(bufs),
+                                     ctypes.c_void_p(stream_ptr), ctypes.byref(h))
+    return st, h
+
+
+def amber_step(handle, n_steps):
+    return lib().amber_step(handle, n_steps)
+
+
+def amber_step_batch(handles, n_steps):
+    arr = (ctypes.c_void_p * max(1, len(handles)))(*[h.value if isinstance(h, ctypes.c_void_p)
+                                                    else h for h in handles])
+    return lib().amber_step_batch(arr, len(handles), n_steps)
+
+
+def amber_read_columns(handle, col_mask, host_ptrs):
+    arr = (ctypes.c_void_p * NUM_COLS)(*host_ptrs)
+    return lib().amber_read_columns(handle, col_mask, arr)
+
+
+def amber_invariants(handle):
+    """Returns (status, Invariants)."""
+    out = Invariants()
+    st = lib().amber_invariants(handle, ctypes.byref(out))
+    return st, out
+
+
+def amber_pop_info(handle):
+    out = PopInfo()
+    st = lib().amber_pop_info(handle, ctypes.byref(out))
+    return st, out
+
+
+def amber_release(handle):
+    return lib().amber_release(handle)
+
+
+# ------------------------------------------------------------------ convenience
+
+def make_desc(model, n, L=0, seed=0, stream=0, wealth_init=1, beta=(1, 20),
+              gamma=(1, 100), initial_infected=0):
+    return RunDesc(ABI_VERSION, model, n, L, seed & 0xFFFFFFFF, stream & 0xFFFFFFFF,
+                   wealth_init, beta[0], beta[1], gamma[0], gamma[1], initial_infected)
+
+
+def footprint_bytes(desc):
+    """Device bytes a run needs: its columns plus its workspace."""
+    cols = sum(amber_column_bytes(desc, c) for c in range(NUM_COLS))
+    ws = amber_workspace_bytes(desc)
+    return cols + ws if ws else 0
+
+
+class Population:
+    """One run: device buffers (torch tensors on the current device) plus the
+    library handle.  ``stream`` is a torch.cuda.Stream (default: current)."""
+
+    def __init__(self, model, n, L=0, seed=0, stream_id=0, wealth_init=1, beta=(1, 20),
+                 gamma=(1, 100), initial_infected=0, stream=None, device=None,
+                 buffers=None):
+        import torch
+        self.desc = make_desc(model, n, L, seed, stream_id, wealth_init, beta, gamma,
+                              initial_infected)
+        self.model, self.n = model, n
+        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        ws = amber_workspace_bytes(self.desc)
+        if ws == 0:
+            raise AmberError(E_INVALID, amber_last_error())
+        self.cols = {}
+        b = Buffers()
+        for c in MODEL_COLUMNS[model]:
+            nb = amber_column_bytes(self.desc, c)
+            dtype = torch.uint8 if c == COL_STATE else torch.int32
+            t = (buffers or {}).get(c)
+            if t is None:
+                t = torch.empty(nb // (1 if c == COL_STATE else 4), dtype=dtype, device=dev)
+            self.cols[c] = t
+            b.col[c] = t.data_ptr()
+        self.workspace = (buffers or {}).get("workspace")
+        if self.workspace is None:
+            self.workspace = torch.empty(ws, dtype=torch.uint8, device=dev)
+        b.workspace = self.workspace.data_ptr()
+        b.workspace_bytes = self.workspace.numel()
+        self.bufs = b
+        st, self.handle = amber_init_population(self.desc, b, self.stream.cuda_stream)
+        check(st)
+
+    # --- steps
+    def step(self, n_steps=1):
+        check(amber_step(self.handle, n_steps))
+        return self
+
+    def info(self):
+        st, inf = amber_pop_info(self.handle)
+        check(st)
+        return inf
+
+    def invariants(self):
+        st, inv = amber_invariants(self.handle)
+        check(st)
+        return inv.as_dict()
+
+    def read(self):
+        """Host numpy copies of the model's columns, in column order."""
+        import numpy as np
+        outs = {}
+        ptrs = [None] * NUM_COLS
+        mask = 0
+        for c in MODEL_COLUMNS[self.model]:
+            a = np.empty(self.n, dtype=np.uint8 if c == COL_STATE else np.int32)
+            outs[c] = a
+            ptrs[c] = a.ctypes.data
+            mask |= 1 << c
+        check(amber_read_columns(self.handle, mask, ptrs))
+        return [outs[c] for c in MODEL_COLUMNS[self.model]]
+
+    def release(self):
+        if self.handle is not None and self.handle.value:
+            check(amber_release(self.handle))
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+
+def step_batch(pops, n_steps):
+    check(amber_step_batch([p.handle for p in pops], n_steps))

@@ -1,0 +1,584 @@
+// amber_host.cpp -- host runtime and C ABI of libamber (see include/amber.h).
+//
+// Validates run descriptors, derives the run's parameters (grid side, initial
+// infected count, exact uint32 Bernoulli thresholds), lays out the caller's
+// workspace, and enqueues the gfx950 kernels on the caller's HIP stream.  The
+// library never allocates device memory.
+#include "amber.h"
+#include "amber_internal.h"
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <unordered_set>
+#include <vector>
+
+using namespace amber;
+
+// ------------------------------------------------------------------ errors
+
+static thread_local std::string g_last_error;
+
+static amber_status_t fail(amber_status_t st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+static amber_status_t hip_fail(hipError_t e, const char *what)
+{
+    return fail(AMBER_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                          \
+    do {                                             \
+        hipError_t e_ = (expr);                      \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+// ------------------------------------------------------------------ bignum
+// Exact infection thresholds T[k] = floor(2^32 (d^k - m^k) / d^k), m = d - n,
+// for beta = n/d.  Numbers are little-endian vectors of 32-bit limbs.
+
+namespace {
+
+using Limbs = std::vector<uint32_t>;
+
+void trim(Limbs &a)
+{
+    while (a.size() > 1 && a.back() == 0) a.pop_back();
+}
+
+void mul_small(Limbs &a, uint32_t m)
+{
+    uint64_t carry = 0;
+    for (auto &l : a) {
+        const uint64_t v = (uint64_t)l * m + carry;
+        l = (uint32_t)v;
+        carry = v >> 32;
+    }
+    if (carry) a.push_back((uint32_t)carry);
+    trim(a);
+}
+
+int cmp(const Limbs &a, const Limbs &b)
+{
+    if (a.size() != b.size()) return a.size() < b.size() ? -1 : 1;
+    for (size_t i = a.size(); i-- > 0;)
+        if (a[i] != b[i]) return a[i] < b[i] ? -1 : 1;
+    return 0;
+}
+
+// a -= b, requires a >= b
+void sub_in_place(Limbs &a, const Limbs &b)
+{
+    int64_t borrow = 0;
+    for (size_t i = 0; i < a.size(); ++i) {
+        int64_t v = (int64_t)a[i] - borrow - (i < b.size() ? (int64_t)b[i] : 0);
+        borrow = v < 0;
+        a[i] = (uint32_t)(v + (borrow << 32));
+    }
+    trim(a);
+}
+
+void add_in_place(Limbs &a, const Limbs &b)
+{
+    if (a.size() < b.size()) a.resize(b.size(), 0);
+    uint64_t carry = 0;
+    for (size_t i = 0; i < a.size(); ++i) {
+        const uint64_t v = (uint64_t)a[i] + (i < b.size() ? b[i] : 0) + carry;
+        a[i] = (uint32_t)v;
+        carry = v >> 32;
+    }
+    if (carry) a.push_back((uint32_t)carry);
+}
+
+uint32_t bit_length(const Limbs &a)
+{
+    const uint32_t top = a.back();
+    uint32_t bits = 32 * (uint32_t)(a.size() - 1);
+    return top ? bits + 32 - __builtin_clz(top) : bits;
+}
+
+// floor(a / 2^sh) truncated to 64 bits (callers ensure it fits)
+uint64_t shifted_top(const Limbs &a, uint32_t sh)
+{
+    uint64_t out = 0;
+    for (uint32_t b = 0; b < 64; ++b) {
+        const uint32_t bit = sh + b;
+        const size_t li = bit / 32;
+        if (li < a.size() && ((a[li] >> (bit % 32)) & 1u)) out |= 1ull << b;
+    }
+    return out;
+}
+
+// floor(2^32 * num / den) for 0 <= num < den (result < 2^32).
+uint32_t scaled_quotient(const Limbs &num, const Limbs &den)
+{
+    const uint32_t bl = bit_length(den);
+    const uint32_t sh = bl > 64 ? bl - 64 : 0;
+    const uint64_t nt = shifted_top(num, sh);
+    const uint64_t dt = shifted_top(den, sh);
+    unsigned __int128 est = ((unsigned __int128)nt << 32) / dt;
+    if (est > 0xffffffffull) est = 0xffffffffull;
+    uint32_t q = (uint32_t)est;
+    // exact correction: want q*den <= num*2^32 < (q+1)*den
+    Limbs target(num.size() + 1, 0);
+    std::copy(num.begin(), num.end(), target.begin() + 1);
+    trim(target);
+    Limbs prod = den;
+    mul_small(prod, q);
+    while (cmp(prod, target) > 0) {
+        sub_in_place(prod, den);
+        --q;
+    }
+    for (;;) {
+        Limbs next = prod;
+        add_in_place(next, den);
+        if (cmp(next, target) > 0) break;
+        prod.swap(next);
+        ++q;
+    }
+    return q;
+}
+
+// Builds the table; returns AMBER_OK, AMBER_E_INVALID or AMBER_E_UNSUPPORTED.
+amber_status_t build_infection_table(uint32_t num, uint32_t den, std::vector<uint32_t> &out)
+{
+    out.clear();
+    if (den == 0 || num >= den)
+        return fail(AMBER_E_INVALID, "beta must satisfy 0 <= num < den (got %u/%u)", num, den);
+    out.push_back(0);
+    if (num == 0) return AMBER_OK;
+    const uint32_t m = den - num;
+    Limbs miss{1}, whole{1};                  // m^k, d^k
+    for (;;) {
+        mul_small(miss, m);
+        mul_small(whole, den);
+        Limbs hit = whole;
+        sub_in_place(hit, miss);              // d^k - m^k
+        const uint32_t t = scaled_quotient(hit, whole);
+        out.push_back(t);
+        if (t == 0xffffffffu) return AMBER_OK;
+        if (out.size() >= AMBER_MAX_TABLE)
+            return fail(AMBER_E_UNSUPPORTED,
+                        "beta %u/%u needs more than %u threshold entries", num, den,
+                        AMBER_MAX_TABLE);
+    }
+}
+
+uint32_t bernoulli_threshold(uint32_t num, uint32_t den)
+{
+    return (uint32_t)(((uint64_t)num << 32) / den);
+}
+
+// round(sqrt(n)), halves up: s = isqrt(n); s + 1 iff n > s^2 + s.
+uint32_t round_sqrt(uint32_t n)
+{
+    uint64_t s = 0;
+    for (int b = 31; b >= 0; --b) {
+        const uint64_t c = s | (1ull << b);
+        if (c * c <= n) s = c;
+    }
+    return (uint32_t)(((uint64_t)n > s * s + s) ? s + 1 : s);
+}
+
+uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
+
+// Resolved, validated parameters of a run.
+struct Resolved {
+    uint32_t model = 0, n = 0, L = 0, i0 = 0, seed = 0, stream = 0;
+    int32_t w_init = 0;
+    uint32_t t_rec = 0;
+    std::vector<uint32_t> t_inf;
+    // workspace layout (byte offsets)
+    uint64_t off_inc0 = 0, off_inc1 = 0, off_table = 0, off_count0 = 0, off_count1 = 0;
+    uint64_t ws_bytes = 0;
+};
+
+uint64_t padded_agents(uint32_t n) { return align_up(n, AGENT_PAD); }
+
+amber_status_t resolve(const amber_run_desc_t *d, Resolved &r, bool want_table)
+{
+    if (!d) return fail(AMBER_E_INVALID, "descriptor is NULL");
+    if (d->abi_version != AMBER_ABI_VERSION)
+        return fail(AMBER_E_INVALID, "abi_version %u != %u", d->abi_version, AMBER_ABI_VERSION);
+    if (d->model > AMBER_SIR) return fail(AMBER_E_INVALID, "unknown model %u", d->model);
+    if (d->n_agents == 0 || d->n_agents > 0x7fffffffu)
+        return fail(AMBER_E_INVALID, "n_agents must be in [1, 2^31-1] (got %u)", d->n_agents);
+    r.model = d->model;
+    r.n = d->n_agents;
+    r.seed = d->seed;
+    r.stream = d->stream;
+    uint64_t ws = 256;   // invariants block
+    if (d->model == AMBER_WEALTH) {
+        if (d->wealth_init < 0) return fail(AMBER_E_INVALID, "wealth_init must be >= 0");
+        if ((uint64_t)d->n_agents * (uint64_t)d->wealth_init > 0x7fffffffull)
+            return fail(AMBER_E_INVALID, "N * wealth_init must stay below 2^31");
+        r.w_init = d->wealth_init;
+        const uint64_t col = align_up(padded_agents(r.n) * 4, 256);
+        r.off_inc0 = ws;
+        r.off_inc1 = ws + col;
+        ws += 2 * col;
+    } else {
+        const uint32_t L = d->grid_side ? d->grid_side : round_sqrt(d->n_agents);
+        if (L == 0 || (uint64_t)L * L > 0x7fffffffull)
+            return fail(AMBER_E_INVALID, "grid side must satisfy 1 <= L and L*L < 2^31 (got %u)", L);
+        r.L = L;
+        if (d->model == AMBER_SIR) {
+            if (d->gamma_den == 0 || d->gamma_num >= d->gamma_den)
+                return fail(AMBER_E_INVALID, "gamma must satisfy 0 <= num < den (got %u/%u)",
+                            d->gamma_num, d->gamma_den);
+            if (d->beta_den == 0 || d->beta_num >= d->beta_den)
+                return fail(AMBER_E_INVALID, "beta must satisfy 0 <= num < den (got %u/%u)",
+                            d->beta_num, d->beta_den);
+            r.i0 = d->initial_infected ? d->initial_infected
+                                       : std::max<uint32_t>(1, (d->n_agents + 500u) / 1000u);
+            if (r.i0 > r.n) return fail(AMBER_E_INVALID, "initial_infected %u > N", r.i0);
+            r.t_rec = bernoulli_threshold(d->gamma_num, d->gamma_den);
+            if (want_table) {
+                amber_status_t st = build_infection_table(d->beta_num, d->beta_den, r.t_inf);
+                if (st != AMBER_OK) return st;
+            }
+            const uint64_t cells = align_up((uint64_t)L * L, AGENT_PAD) * 4;
+            r.off_table = ws;
+            ws += align_up((uint64_t)AMBER_MAX_TABLE * 4, 256);
+            r.off_count0 = ws;
+            ws += align_up(cells, 256);
+            r.off_count1 = ws;
+            ws += align_up(cells, 256);
+        }
+    }
+    r.ws_bytes = ws;
+    return AMBER_OK;
+}
+
+size_t column_bytes(const Resolved &r, amber_col_t c)
+{
+    const uint64_t pad = padded_agents(r.n);
+    switch (c) {
+    case AMBER_COL_WEALTH: return r.model == AMBER_WEALTH ? pad * 4 : 0;
+    case AMBER_COL_X:
+    case AMBER_COL_Y: return r.model != AMBER_WEALTH ? pad * 4 : 0;
+    case AMBER_COL_STATE: return r.model == AMBER_SIR ? pad : 0;
+    }
+    return 0;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ handle
+
+struct amber_pop {
+    Resolved r;
+    amber_buffers_t b{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    uint64_t step = 0;
+    amber::Tuning tuning;
+    DevInvariants *acc = nullptr;      // inside the workspace
+};
+
+namespace {
+std::mutex g_live_mu;
+std::unordered_set<const amber_pop *> g_live;
+
+bool is_live(const amber_pop *p)
+{
+    std::lock_guard<std::mutex> lk(g_live_mu);
+    return p && g_live.count(p);
+}
+
+amber_status_t check_device_ptr(const void *p, int device, const char *what, size_t need)
+{
+    if (!p) return fail(AMBER_E_INVALID, "%s is NULL", what);
+    if (((uintptr_t)p & 15u) != 0) return fail(AMBER_E_INVALID, "%s is not 16-byte aligned", what);
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(AMBER_E_INVALID, "%s is not a HIP device pointer", what);
+    }
+    if (attr.type != hipMemoryTypeDevice)
+        return fail(AMBER_E_INVALID, "%s is not device memory", what);
+    if (attr.device != device)
+        return fail(AMBER_E_INVALID, "%s lives on device %d, current device is %d", what,
+                    attr.device, device);
+    (void)need;
+    return AMBER_OK;
+}
+
+int32_t *col_i32(amber_pop *p, amber_col_t c) { return (int32_t *)p->b.col[c]; }
+uint8_t *ws_ptr(amber_pop *p, uint64_t off) { return (uint8_t *)p->b.workspace + off; }
+
+amber_status_t enqueue_steps(amber_pop *p, uint32_t n_steps)
+{
+    const Resolved &r = p->r;
+    const uint32_t t0 = (uint32_t)p->step;
+    hipStream_t st = p->stream;
+    if (r.model == AMBER_RANDOM_WALK) {
+        HIP_TRY(launch_walk(col_i32(p, AMBER_COL_X), col_i32(p, AMBER_COL_Y), r.n, (int32_t)r.L,
+                            r.seed, r.stream, t0, n_steps, p->tuning, st),
+                "walk kernel");
+    } else if (r.model == AMBER_WEALTH) {
+        int32_t *w = col_i32(p, AMBER_COL_WEALTH);
+        if (r.n <= wealth_small_max_agents()) {
+            HIP_TRY(launch_wealth_small(w, r.n, r.seed, r.stream, t0, n_steps, st),
+                    "wealth small kernel");
+        } else {
+            int32_t *inc[2] = {(int32_t *)ws_ptr(p, r.off_inc0), (int32_t *)ws_ptr(p, r.off_inc1)};
+            for (uint32_t i = 0; i < n_steps; ++i)
+                HIP_TRY(launch_wealth_step(w, inc[i & 1], inc[(i + 1) & 1], r.n, r.seed, r.stream,
+                                           t0 + i, p->tuning, st),
+                        "wealth step kernel");
+            HIP_TRY(launch_wealth_fold(w, inc[n_steps & 1], r.n, st), "wealth fold kernel");
+        }
+    } else {
+        SirParams sp;
+        sp.x = col_i32(p, AMBER_COL_X);
+        sp.y = col_i32(p, AMBER_COL_Y);
+        sp.s = (uint8_t *)p->b.col[AMBER_COL_STATE];
+        sp.count[0] = (uint32_t *)ws_ptr(p, r.off_count0);
+        sp.count[1] = (uint32_t *)ws_ptr(p, r.off_count1);
+        sp.t_inf = (const uint32_t *)ws_ptr(p, r.off_table);
+        sp.table_len = (uint32_t)r.t_inf.size();
+        sp.t_rec = r.t_rec;
+        sp.n = r.n;
+        sp.L = (int32_t)r.L;
+        sp.k0 = r.seed;
+        sp.k1 = r.stream;
+        for (uint32_t i = 0; i < n_steps; ++i)
+            HIP_TRY(launch_sir_step(sp, t0 + i, p->tuning, st), "sir step kernels");
+    }
+    return AMBER_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ ABI
+
+extern "C" {
+
+uint32_t amber_abi_version(void) { return AMBER_ABI_VERSION; }
+
+const char *amber_last_error(void) { return g_last_error.c_str(); }
+
+size_t amber_column_bytes(const amber_run_desc_t *desc, amber_col_t c)
+{
+    Resolved r;
+    if (resolve(desc, r, false) != AMBER_OK) return 0;
+    return column_bytes(r, c);
+}
+
+size_t amber_workspace_bytes(const amber_run_desc_t *desc)
+{
+    Resolved r;
+    if (resolve(desc, r, false) != AMBER_OK) return 0;
+    return (size_t)r.ws_bytes;
+}
+
+amber_status_t amber_infection_table(uint32_t beta_num, uint32_t beta_den, uint32_t *out,
+                                     uint32_t cap, uint32_t *k_sat)
+{
+    std::vector<uint32_t> t;
+    amber_status_t st = build_infection_table(beta_num, beta_den, t);
+    if (st != AMBER_OK) return st;
+    if (k_sat) *k_sat = (uint32_t)t.size() - 1;
+    if (out) std::memcpy(out, t.data(), std::min<size_t>(cap, t.size()) * sizeof(uint32_t));
+    return AMBER_OK;
+}
+
+amber_status_t amber_init_population(const amber_run_desc_t *desc, const amber_buffers_t *bufs,
+                                     void *hip_stream, amber_pop_t **out)
+{
+    if (!out) return fail(AMBER_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!bufs) return fail(AMBER_E_INVALID, "buffers are NULL");
+    Resolved r;
+    amber_status_t st = resolve(desc, r, true);
+    if (st != AMBER_OK) return st;
+    static const char *names[AMBER_NUM_COLS] = {"wealth column", "x column", "y column",
+                                                "state column"};
+    for (int c = 0; c < AMBER_NUM_COLS; ++c)
+        if (column_bytes(r, (amber_col_t)c) != 0 && !bufs->col[c])
+            return fail(AMBER_E_INVALID, "%s is NULL", names[c]);
+    if (!bufs->workspace) return fail(AMBER_E_INVALID, "workspace is NULL");
+    if (bufs->workspace_bytes < r.ws_bytes)
+        return fail(AMBER_E_NOMEM, "workspace has %zu bytes, the run needs %llu",
+                    bufs->workspace_bytes, (unsigned long long)r.ws_bytes);
+    int device = 0;
+    HIP_TRY(hipGetDevice(&device), "hipGetDevice");
+    for (int c = 0; c < AMBER_NUM_COLS; ++c) {
+        if (column_bytes(r, (amber_col_t)c) == 0) continue;
+        st = check_device_ptr(bufs->col[c], device, names[c], column_bytes(r, (amber_col_t)c));
+        if (st != AMBER_OK) return st;
+    }
+    st = check_device_ptr(bufs->workspace, device, "workspace", r.ws_bytes);
+    if (st != AMBER_OK) return st;
+    if (((uintptr_t)bufs->workspace & 255u) != 0)
+        return fail(AMBER_E_INVALID, "workspace is not 256-byte aligned");
+
+    amber_pop *p = new (std::nothrow) amber_pop;
+    if (!p) return fail(AMBER_E_NOMEM, "host allocation of the handle failed");
+    p->r = std::move(r);
+    p->b = *bufs;
+    p->stream = (hipStream_t)hip_stream;
+    p->device = device;
+    p->acc = (DevInvariants *)p->b.workspace;
+    const Resolved &rr = p->r;
+
+    auto bail = [&](amber_status_t s) {
+        delete p;
+        return s;
+    };
+    hipError_t e = hipSuccess;
+    if (rr.model == AMBER_WEALTH) {
+        e = launch_init_wealth(col_i32(p, AMBER_COL_WEALTH), (int32_t *)ws_ptr(p, rr.off_inc0),
+                               (int32_t *)ws_ptr(p, rr.off_inc1), rr.n, rr.w_init, p->stream);
+    } else {
+        e = launch_init_positions(col_i32(p, AMBER_COL_X), col_i32(p, AMBER_COL_Y), rr.n,
+                                  (int32_t)rr.L, rr.seed, rr.stream, p->stream);
+        if (e == hipSuccess && rr.model == AMBER_SIR) {
+            e = launch_init_states((uint8_t *)p->b.col[AMBER_COL_STATE], rr.n, rr.i0, p->stream);
+            const uint64_t cell_words = (rr.off_count1 - rr.off_count0) / 4;
+            if (e == hipSuccess)
+                e = launch_zero_words((uint32_t *)ws_ptr(p, rr.off_count0), 2 * cell_words,
+                                      p->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(ws_ptr(p, rr.off_table), rr.t_inf.data(),
+                                   rr.t_inf.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
+                                   p->stream);
+            // the table's host copy lives in the handle, which outlives the
+            // upload (amber_release waits for the stream)
+        }
+    }
+    if (e != hipSuccess) return bail(hip_fail(e, "init kernels"));
+    {
+        std::lock_guard<std::mutex> lk(g_live_mu);
+        g_live.insert(p);
+    }
+    *out = p;
+    return AMBER_OK;
+}
+
+amber_status_t amber_step(amber_pop_t *pop, uint32_t n_steps)
+{
+    if (!is_live(pop)) return fail(AMBER_E_STATE, "unknown or released handle");
+    if (n_steps == 0) return AMBER_OK;
+    if (pop->step + n_steps > 0xffffffffull)
+        return fail(AMBER_E_INVALID, "step index would exceed 2^32-1");
+    amber_status_t st = enqueue_steps(pop, n_steps);
+    if (st != AMBER_OK) return st;
+    pop->step += n_steps;
+    return AMBER_OK;
+}
+
+amber_status_t amber_step_batch(amber_pop_t *const *pops, uint32_t n, uint32_t n_steps)
+{
+    if (!pops && n) return fail(AMBER_E_INVALID, "pops is NULL");
+    for (uint32_t i = 0; i < n; ++i) {
+        if (!is_live(pops[i])) return fail(AMBER_E_STATE, "handle %u is unknown or released", i);
+        for (uint32_t j = 0; j < i; ++j)
+            if (pops[j] == pops[i]) return fail(AMBER_E_INVALID, "handle %u repeats", i);
+        if (pops[i]->device != pops[0]->device)
+            return fail(AMBER_E_STATE, "handles live on different devices");
+        if (pops[i]->step + n_steps > 0xffffffffull)
+            return fail(AMBER_E_INVALID, "step index would exceed 2^32-1");
+    }
+    for (uint32_t i = 0; i < n; ++i) {
+        amber_status_t st = amber_step(pops[i], n_steps);
+        if (st != AMBER_OK) return st;
+    }
+    return AMBER_OK;
+}
+
+amber_status_t amber_read_columns(amber_pop_t *pop, uint32_t col_mask, void *const *host_dst)
+{
+    if (!is_live(pop)) return fail(AMBER_E_STATE, "unknown or released handle");
+    if (!host_dst) return fail(AMBER_E_INVALID, "host_dst is NULL");
+    for (int c = 0; c < AMBER_NUM_COLS; ++c) {
+        if (!(col_mask & (1u << c))) continue;
+        if (column_bytes(pop->r, (amber_col_t)c) == 0)
+            return fail(AMBER_E_INVALID, "column %d is not used by this model", c);
+        if (!host_dst[c]) return fail(AMBER_E_INVALID, "host_dst[%d] is NULL", c);
+    }
+    if (col_mask >> AMBER_NUM_COLS) return fail(AMBER_E_INVALID, "unknown column bits in mask");
+    for (int c = 0; c < AMBER_NUM_COLS; ++c) {
+        if (!(col_mask & (1u << c))) continue;
+        const size_t bytes = (size_t)pop->r.n * (c == AMBER_COL_STATE ? 1 : 4);
+        HIP_TRY(hipMemcpyAsync(host_dst[c], pop->b.col[c], bytes, hipMemcpyDeviceToHost,
+                               pop->stream),
+                "column copy");
+    }
+    HIP_TRY(hipStreamSynchronize(pop->stream), "stream synchronize");
+    return AMBER_OK;
+}
+
+amber_status_t amber_invariants(amber_pop_t *pop, amber_invariants_t *out)
+{
+    if (!is_live(pop)) return fail(AMBER_E_STATE, "unknown or released handle");
+    if (!out) return fail(AMBER_E_INVALID, "out is NULL");
+    const Resolved &r = pop->r;
+    HIP_TRY(launch_invariants(r.model, r.n, (int32_t)r.L, col_i32(pop, AMBER_COL_WEALTH),
+                              col_i32(pop, AMBER_COL_X), col_i32(pop, AMBER_COL_Y),
+                              (const uint8_t *)pop->b.col[AMBER_COL_STATE], pop->acc, pop->stream),
+            "invariants kernel");
+    DevInvariants h;
+    HIP_TRY(hipMemcpyAsync(&h, pop->acc, sizeof h, hipMemcpyDeviceToHost, pop->stream),
+            "invariants copy");
+    HIP_TRY(hipStreamSynchronize(pop->stream), "stream synchronize");
+    std::memset(out, 0, sizeof *out);
+    out->step = pop->step;
+    out->digest = h.digest;
+    out->out_of_bounds = h.out_of_bounds;
+    if (r.model == AMBER_WEALTH) {
+        out->wealth_sum = (int64_t)h.wealth_sum;
+        out->wealth_min = h.wealth_min;
+    }
+    if (r.model == AMBER_SIR) {
+        out->n_s = h.n_s;
+        out->n_i = h.n_i;
+        out->n_r = h.n_r;
+    }
+    return AMBER_OK;
+}
+
+amber_status_t amber_pop_info(const amber_pop_t *pop, amber_pop_info_t *out)
+{
+    if (!is_live(pop)) return fail(AMBER_E_STATE, "unknown or released handle");
+    if (!out) return fail(AMBER_E_INVALID, "out is NULL");
+    const Resolved &r = pop->r;
+    out->model = r.model;
+    out->n_agents = r.n;
+    out->grid_side = r.L;
+    out->initial_infected = r.i0;
+    out->seed = r.seed;
+    out->stream = r.stream;
+    out->table_len = (uint32_t)r.t_inf.size();
+    out->t_rec = r.t_rec;
+    out->step = pop->step;
+    return AMBER_OK;
+}
+
+amber_status_t amber_release(amber_pop_t *pop)
+{
+    {
+        std::lock_guard<std::mutex> lk(g_live_mu);
+        if (!pop || !g_live.count(pop)) return fail(AMBER_E_STATE, "unknown or released handle");
+        g_live.erase(pop);
+    }
+    hipError_t e = hipStreamSynchronize(pop->stream);
+    delete pop;
+    if (e != hipSuccess) return hip_fail(e, "stream synchronize");
+    return AMBER_OK;
+}
+
+}  // extern "C"

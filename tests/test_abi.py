@@ -1,0 +1,132 @@
+"""Host-side checks of libamber's C ABI (no GPU needed).
+
+The library must load, export every entry point ``include/amber.h`` declares,
+validate descriptors before touching the device, size buffers, and build the
+exact infection thresholds on the host identically to the oracle's exact
+fractions.  No compute call is made here.
+"""
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2601_16292_amd import amber as A
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "amber.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"AMBER_API[^;(]*?\b(amber_\w+)\s*\(", text)))
+
+
+def test_header_declares_the_binding_names():
+    assert _declared() == sorted(A.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = A.lib()
+    for name in _declared():
+        assert hasattr(lib, name), name
+    nm = subprocess.run(["nm", "-D", "--defined-only", A.LIB_PATH], capture_output=True,
+                        text=True, check=True).stdout
+    exported = set(re.findall(r"\sT\s(amber_\w+)", nm))
+    assert set(_declared()) <= exported
+    # nothing else of ours leaks from the library
+    assert exported == set(_declared())
+
+
+def test_abi_version():
+    assert A.amber_abi_version() == A.ABI_VERSION == 1
+
+
+def test_column_and_workspace_bytes():
+    d = A.make_desc(A.SIR, 1_000_000, 1000)
+    assert A.amber_column_bytes(d, A.COL_X) == 4 * 1_000_000
+    assert A.amber_column_bytes(d, A.COL_STATE) == 1_000_000
+    assert A.amber_column_bytes(d, A.COL_WEALTH) == 0
+    ws = A.amber_workspace_bytes(d)
+    assert ws >= 2 * 4 * 1000 * 1000 + 4 * 434
+    d = A.make_desc(A.RANDOM_WALK, 5)
+    assert A.amber_column_bytes(d, A.COL_X) == 4 * 64      # padded to 64 agents
+    assert A.amber_column_bytes(d, A.COL_STATE) == 0
+    d = A.make_desc(A.WEALTH, 65)
+    assert A.amber_column_bytes(d, A.COL_WEALTH) == 4 * 128
+    assert A.amber_workspace_bytes(d) >= 2 * 4 * 128
+
+
+@pytest.mark.parametrize("kw", [
+    dict(model=3, n=10), dict(model=0, n=0), dict(model=1, n=2 ** 31),
+    dict(model=1, n=100, L=46341), dict(model=2, n=100, beta=(5, 5)),
+    dict(model=2, n=100, beta=(1, 0)), dict(model=2, n=100, gamma=(2, 1)),
+    dict(model=2, n=100, initial_infected=101), dict(model=0, n=1 << 20, wealth_init=1 << 11),
+    dict(model=0, n=10, wealth_init=-1),
+])
+def test_invalid_descriptors_are_rejected(kw):
+    kw = dict(kw)
+    model, n = kw.pop("model"), kw.pop("n")
+    d = A.make_desc(model, n, **kw)
+    assert A.amber_workspace_bytes(d) == 0
+    for c in range(A.NUM_COLS):
+        assert A.amber_column_bytes(d, c) == 0
+    st, h = A.amber_init_population(d, A.Buffers(), 0)
+    assert st == A.E_INVALID and not h.value
+    assert A.amber_last_error()
+
+
+def test_bad_abi_version():
+    d = A.make_desc(A.WEALTH, 10)
+    d.abi_version = 2
+    assert A.amber_workspace_bytes(d) == 0
+    assert "abi_version" in (A.lib().amber_workspace_bytes(d) or A.amber_last_error())
+
+
+def test_init_rejects_missing_buffers_before_touching_the_device():
+    d = A.make_desc(A.SIR, 100, 10)
+    st, _ = A.amber_init_population(d, A.Buffers(), 0)
+    assert st == A.E_INVALID and "NULL" in A.amber_last_error()
+    b = A.Buffers()
+    for c in (A.COL_X, A.COL_Y, A.COL_STATE):
+        b.col[c] = 0x1000
+    b.workspace = 0x100000
+    b.workspace_bytes = 16
+    st, _ = A.amber_init_population(d, b, 0)
+    assert st == A.E_NOMEM and "workspace" in A.amber_last_error()
+
+
+def test_handle_misuse_is_reported():
+    import ctypes
+    bogus = ctypes.c_void_p(0xdeadbeef)
+    assert A.amber_step(bogus, 1) == A.E_STATE
+    assert A.amber_release(bogus) == A.E_STATE
+    st, _ = A.amber_invariants(bogus)
+    assert st == A.E_STATE
+    st, _ = A.amber_pop_info(bogus)
+    assert st == A.E_STATE
+    assert A.amber_step_batch([bogus], 1) == A.E_STATE
+    assert A.amber_step_batch([], 3) == A.OK
+
+
+# ------------------------------------------------------------------ thresholds
+
+SWEEP = [(15 + 19 * j, 1500) for j in range(16)]
+
+
+@pytest.mark.parametrize("beta", [(1, 20), (0, 9), (1, 2), (999, 1000), (1, 3), (7, 11),
+                                  (123456, 1000003), (1, 300), (2 ** 31, 2 ** 32 - 1)] + SWEEP)
+def test_host_threshold_table_equals_exact_fractions(beta):
+    from oracle import thresholds as TH
+    want, k_sat = TH.infection_table(*beta)
+    st, got, got_k = A.amber_infection_table(*beta)
+    assert st == A.OK
+    assert got_k == k_sat and got == want
+
+
+def test_host_threshold_table_limits():
+    st, _, _ = A.amber_infection_table(1, 100000)     # k_sat ~ 2.2e6 entries
+    assert st == A.E_UNSUPPORTED
+    st, _, _ = A.amber_infection_table(3, 3)
+    assert st == A.E_INVALID

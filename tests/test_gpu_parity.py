@@ -1,0 +1,229 @@
+"""GPU parity: the HIP path through the C ABI against the oracle.
+
+Every comparison is exact (integer arithmetic throughout): whole columns at
+sizes the oracle finishes in seconds (several 256-thread tiles and ragged
+tails), and digests / invariants / sampled agents against stored oracle
+values at the full workload sizes.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def A():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2601_16292_amd import amber
+    amber.lib()
+    return amber
+
+
+@pytest.fixture(scope="module")
+def O():
+    from oracle import oracle
+    oracle.lib()
+    return oracle
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def run_both(A, O, model, n, steps, L=0, seed=0, stream=0, wealth_init=1, beta=(1, 20),
+             gamma=(1, 100), i0=0, chunks=None):
+    say(f"case model={model} n={n} L={L} steps={steps} seed={seed} stream={stream} "
+        f"w0={wealth_init} beta={beta} gamma={gamma} i0={i0} chunks={chunks}")
+    pop = A.Population(model, n, L=L, seed=seed, stream_id=stream, wealth_init=wealth_init,
+                       beta=beta, gamma=gamma, initial_infected=i0)
+    for c in (chunks or [steps]):
+        pop.step(c)
+    got = pop.read()
+    inv = pop.invariants()
+    pop.release()
+    ref = O.OracleRun(model, n, L, seed=seed, stream=stream, wealth_init=wealth_init, beta=beta,
+                      gamma=gamma, initial_infected=i0).step(steps)
+    return got, inv, ref
+
+
+def assert_same(got, inv, ref, steps):
+    for g, r in zip(got, ref.columns()):
+        if not np.array_equal(g, r):
+            bad = np.flatnonzero(g != r)
+            raise AssertionError(f"{bad.size} rows differ, first {bad[:8].tolist()}: "
+                                 f"gpu {g[bad[:8]].tolist()} oracle {r[bad[:8]].tolist()}")
+    ri = ref.invariants()
+    assert inv["digest"] == ref.digest()
+    assert inv["step"] == steps
+    for k in ("wealth_sum", "wealth_min", "n_s", "n_i", "n_r", "out_of_bounds"):
+        assert inv[k] == ri[k], k
+
+
+WALK_CASES = [(1, 1, 5), (2, 2, 9), (3, 3, 4), (5, 7, 20), (63, 10, 7), (64, 1000, 3),
+              (65, 5, 11), (1000, 32, 50), (4097, 64, 33), (70001, 265, 12)]
+
+
+@pytest.mark.parametrize("n,L,steps", WALK_CASES)
+def test_walk_parity(A, O, n, L, steps):
+    got, inv, ref = run_both(A, O, A.RANDOM_WALK, n, steps, L=L, seed=n, stream=L)
+    assert_same(got, inv, ref, steps)
+
+
+WEALTH_CASES = [(1, 1, 5), (2, 3, 9), (3, 1, 20), (5, 2, 7), (64, 1, 30), (65, 4, 13),
+                (1000, 1, 100), (8191, 1, 9), (8192, 2, 6), (8193, 1, 6), (20000, 3, 17),
+                (100003, 1, 5)]
+
+
+@pytest.mark.parametrize("n,w0,steps", WEALTH_CASES)
+def test_wealth_parity(A, O, n, w0, steps):
+    got, inv, ref = run_both(A, O, A.WEALTH, n, steps, seed=7, stream=n, wealth_init=w0)
+    assert_same(got, inv, ref, steps)
+    assert inv["wealth_sum"] == n * w0
+
+
+SIR_CASES = [
+    (1, 1, 4, (1, 20), (1, 100), 0), (7, 1, 10, (1, 2), (1, 3), 2),
+    (9, 2, 10, (1, 3), (1, 5), 3), (30, 3, 15, (1, 4), (1, 10), 4),
+    (65, 4, 12, (1, 20), (1, 100), 5), (1000, 32, 40, (1, 20), (1, 100), 0),
+    (5003, 71, 25, (1, 5), (1, 20), 0), (20000, 141, 30, (34, 1500), (1, 100), 50),
+    (70001, 265, 20, (300, 1500), (1, 100), 0), (4096, 1000, 10, (999, 1000), (1, 2), 300),
+]
+
+
+@pytest.mark.parametrize("n,L,steps,beta,gamma,i0", SIR_CASES)
+def test_sir_parity(A, O, n, L, steps, beta, gamma, i0):
+    got, inv, ref = run_both(A, O, A.SIR, n, steps, L=L, seed=3, stream=n, beta=beta,
+                             gamma=gamma, i0=i0)
+    assert_same(got, inv, ref, steps)
+    assert inv["n_s"] + inv["n_i"] + inv["n_r"] == n
+
+
+@pytest.mark.parametrize("model,n,L", [(0, 5000, 0), (0, 30000, 0), (1, 3001, 50), (2, 6000, 77)])
+def test_chunking_invariance(A, O, model, n, L):
+    got, inv, ref = run_both(A, O, model, n, 20, L=L, seed=11, stream=2,
+                             chunks=[3, 1, 6, 1, 9])
+    assert_same(got, inv, ref, 20)
+
+
+def test_sir_without_transmission_is_the_random_walk(A, O):
+    say("case cross-model n=20000 L=150 steps=25")
+    sir = A.Population(A.SIR, 20000, L=150, seed=5, stream_id=9, beta=(0, 1), gamma=(0, 1))
+    rw = A.Population(A.RANDOM_WALK, 20000, L=150, seed=5, stream_id=9)
+    sir.step(25)
+    rw.step(25)
+    sx, sy, ss = sir.read()
+    rx, ry = rw.read()
+    assert np.array_equal(sx, rx) and np.array_equal(sy, ry)
+    inv = sir.invariants()
+    assert inv["n_i"] == 20 and inv["n_r"] == 0 and inv["n_s"] == 20000 - 20
+
+
+def test_init_state_matches_oracle(A, O):
+    for model, n, L in [(0, 777, 0), (1, 100001, 999), (2, 100001, 0)]:
+        say(f"case init model={model} n={n} L={L}")
+        pop = A.Population(model, n, L=L, seed=9, stream_id=4)
+        got = pop.read()
+        ref = O.OracleRun(model, n, L, seed=9, stream=4)
+        for g, r in zip(got, ref.columns()):
+            assert np.array_equal(g, r)
+        assert pop.invariants()["step"] == 0
+        assert pop.info().grid_side == ref.L
+
+
+# ------------------------------------------------------------------ full sizes
+
+@pytest.fixture(scope="module")
+def golden():
+    with open(os.path.join(HERE, "golden", "configs.json")) as f:
+        return json.load(f)
+
+
+def test_full_wealth_1k(A, golden):
+    g = golden["wealth_1k"]
+    c = g["config"]
+    say("case full wealth N=1000 x 100")
+    pop = A.Population(A.WEALTH, c["n"], seed=c["seed"], stream_id=c["stream"],
+                       wealth_init=c["wealth_init"])
+    done = 0
+    for t in sorted(int(k) for k in g["checkpoints"]):
+        pop.step(t - done)
+        done = t
+        inv = pop.invariants()
+        want = g["checkpoints"][str(t)]
+        assert inv["digest"] == want["digest"] and inv["wealth_sum"] == want["wealth_sum"]
+    (w,) = pop.read()
+    assert w.tolist() == g["wealth"]
+
+
+def test_full_walk_1m(A, O, golden):
+    g = golden["walk_1m"]
+    c = g["config"]
+    say("case full random walk N=1e6 L=1000 x 1000")
+    pop = A.Population(A.RANDOM_WALK, c["n"], L=c["L"], seed=c["seed"], stream_id=c["stream"])
+    done = 0
+    for t in sorted(int(k) for k in g["checkpoints"]):
+        pop.step(t - done)
+        done = t
+        inv = pop.invariants()
+        want = g["checkpoints"][str(t)]
+        assert inv["digest"] == want["digest"], t
+        assert inv["out_of_bounds"] == 0
+    x, y = pop.read()
+    ids = np.array(g["sample_ids"])
+    assert x[ids].tolist() == g["sample_x"] and y[ids].tolist() == g["sample_y"]
+    # a few more agents replayed alone by the oracle
+    more = np.array([0, 1, 2, 3, 999_999, 500_000, 123_457], dtype=np.uint32)
+    ox, oy = O.walk_agents(more, c["L"], c["seed"], c["stream"], c["steps"])
+    assert np.array_equal(x[more], ox) and np.array_equal(y[more], oy)
+
+
+def test_full_sir_1m(A, golden):
+    g = golden["sir_1m"]
+    c = g["config"]
+    say("case full SIR N=1e6 L=1000 x 500")
+    pop = A.Population(A.SIR, c["n"], L=c["L"], seed=c["seed"], stream_id=c["stream"],
+                       beta=tuple(c["beta"]), gamma=tuple(c["gamma"]))
+    done = 0
+    for t in sorted(int(k) for k in g["checkpoints"]):
+        pop.step(t - done)
+        done = t
+        inv = pop.invariants()
+        want = g["checkpoints"][str(t)]
+        for k in ("digest", "n_s", "n_i", "n_r", "out_of_bounds"):
+            assert inv[k] == want[k], (t, k, inv[k], want[k])
+
+
+# ------------------------------------------------------------------ error paths on device
+
+def test_device_validation(A):
+    import torch
+    say("case device validation")
+    d = A.make_desc(A.RANDOM_WALK, 1000, 10)
+    ws = torch.empty(A.amber_workspace_bytes(d), dtype=torch.uint8, device="cuda")
+    x = torch.empty(A.amber_column_bytes(d, A.COL_X) // 4, dtype=torch.int32, device="cuda")
+    y = torch.empty_like(x)
+    host = np.zeros(2000, dtype=np.int32)
+    b = A.Buffers()
+    b.col[A.COL_X], b.col[A.COL_Y] = x.data_ptr(), host.ctypes.data
+    b.workspace, b.workspace_bytes = ws.data_ptr(), ws.numel()
+    st, h = A.amber_init_population(d, b, 0)
+    assert st == A.E_INVALID and "device" in A.amber_last_error()
+    b.col[A.COL_Y] = y.data_ptr() + 4
+    st, h = A.amber_init_population(d, b, 0)
+    assert st == A.E_INVALID and "aligned" in A.amber_last_error()
+    b.col[A.COL_Y] = y.data_ptr()
+    b.workspace_bytes = 8
+    st, h = A.amber_init_population(d, b, 0)
+    assert st == A.E_NOMEM
+    b.workspace_bytes = ws.numel()
+    st, h = A.amber_init_population(d, b, 0)
+    assert st == A.OK
+    assert A.amber_release(h) == A.OK
+    assert A.amber_release(h) == A.E_STATE
+    assert A.amber_step(h, 1) == A.E_STATE
