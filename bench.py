@@ -1,0 +1,348 @@
+"""Benchmark of the columnar ABM hot path on one MI355X.
+
+Workload (the metric's headline case): grid SIR with N = 1e6 agents on a
+1000 x 1000 torus, beta = 1/20, gamma = 1/100, 0.1% initially infected,
+key (0, 0); 500 steps in total = W untimed warm-up steps followed by K timed
+steps (defaults W = 20, K = 480).  One bench step = one model step of the whole
+population (move, cell binning, neighbour count, transitions), all on the GPU.
+
+Prints ONE JSON line: agent-steps/s over the K timed steps, the roofline of the
+dominant kernel (algorithmic bytes per launch / average launch time, HIP events
+on the library's stream), the CPU oracle timed on a bounded sample, and extra
+lines for the wealth and random-walk models.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extra]
+                  [--no-sweep] [--serve N [--serve-scale S] [--serve-plain]]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, vendor figure
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2601_16292_amd", "csrc", f)
+                  for f in ("amber_device.hip",)]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_sha():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+# ------------------------------------------------------------------ algorithmic bytes
+
+def sir_step_bytes(n, L, infected):
+    """Algorithmic bytes of one SIR step with `infected` agents infected at its
+    start: positions read and written (16 B/agent), state read and written
+    (2 B/agent), the L*L count grid cleared once and read once (8 B/cell) and
+    one 8-B read-modify-write per infected agent."""
+    return 18 * n + 8 * L * L + 8 * infected
+
+
+def wealth_step_bytes(n, donors):
+    """Wealth read and written (8 B per agent) plus one 8-B RMW per donor."""
+    return 8 * n + 8 * donors
+
+
+# ------------------------------------------------------------------ timing helpers
+
+def timed_steps(torch, pop, steps, chunk):
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(pop.stream)
+    done = 0
+    while done < steps:
+        c = min(chunk or steps, steps - done)
+        pop.step(c)
+        done += c
+    ev1.record(pop.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return max(wall, ev0.elapsed_time(ev1) / 1e3)
+
+
+def sir_bench(torch, A, W, K, chunk, form):
+    from paper_2601_16292_amd import workloads as WL
+    c = WL.SIR_1M
+
+    def mk():
+        p = A.Population(A.SIR, c["n"], L=c["L"], seed=c["seed"], stream_id=c["stream"],
+                         beta=c["beta"], gamma=c["gamma"])
+        p.tune(sir_form=form)
+        return p
+
+    pop = mk()
+    pop.step(W)
+    secs = timed_steps(torch, pop, K, chunk)
+    inv = pop.invariants()
+    pop.release()
+
+    # instrumented replay of the same steps: per-kernel launch times
+    pop = mk()
+    pop.step(W)
+    torch.cuda.synchronize()
+    pop.profile(True)
+    done = 0
+    while done < K:
+        cc = min(chunk or K, K - done)
+        pop.step(cc)
+        done += cc
+    times = pop.kernel_times()
+    pop.release()
+
+    # infected count at the start of every timed step (for the atomics' bytes)
+    pop = mk()
+    pop.step(W)
+    infected = []
+    for _ in range(K):
+        infected.append(pop.invariants()["n_i"])
+        pop.step(1)
+    pop.release()
+    return secs, inv, times, infected
+
+
+def roofline_for(times, bytes_per_kernel_total, traffic):
+    """Dominant kernel = largest total device time among those we can price."""
+    best = None
+    for name, (launches, total_ms) in times.items():
+        if name not in bytes_per_kernel_total or launches == 0:
+            continue
+        if best is None or total_ms > best[2]:
+            best = (name, launches, total_ms)
+    if best is None:
+        return None
+    name, launches, total_ms = best
+    avg_s = total_ms / launches / 1e3
+    bytes_per_launch = bytes_per_kernel_total[name] / launches
+    achieved = bytes_per_launch / avg_s / 1e9
+    out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+           "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None, "kernel": name,
+           "avg_launch_us": round(avg_s * 1e6, 3),
+           "algorithmic_bytes_per_launch": int(bytes_per_launch)}
+    if traffic and traffic.get("kernel") == name:
+        out["traffic"] = traffic.get("bytes_per_launch")
+    return out
+
+
+def load_traffic():
+    """HBM traffic per launch from the committed rocprofv3 counter summary,
+    valid only if the kernel source has not changed since it was taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha") != kernel_source_sha():
+        return None
+    return t
+
+
+# ------------------------------------------------------------------ extras
+
+def wealth_bench(torch, A, n, W, K, chunk=0):
+    pop = A.Population(A.WEALTH, n, seed=0, stream_id=0, wealth_init=1)
+    pop.step(W)
+    secs = timed_steps(torch, pop, K, chunk)
+    inv = pop.invariants()
+    pop.release()
+    return secs, inv
+
+
+def walk_bench(torch, A, n, L, K):
+    pop = A.Population(A.RANDOM_WALK, n, L=L, seed=0, stream_id=0)
+    secs = timed_steps(torch, pop, K, 0)
+    inv = pop.invariants()
+    pop.release()
+    return secs, inv
+
+
+def cpu_baseline(budget_s):
+    """The oracle (single-threaded C), timed on the host on a bounded prefix of
+    the same SIR workload: steps 0, 1, 2, ... until the budget is spent."""
+    from oracle import oracle as O
+    from paper_2601_16292_amd import workloads as WL
+    c = WL.SIR_1M
+    r = O.OracleRun(O.SIR, c["n"], c["L"], seed=c["seed"], stream=c["stream"], beta=c["beta"],
+                    gamma=c["gamma"])
+    t0 = time.perf_counter()
+    steps = 0
+    while time.perf_counter() - t0 < budget_s and steps < c["steps"]:
+        r.step(1)
+        steps += 1
+    secs = time.perf_counter() - t0
+    return {"value": round(c["n"] * steps / secs, 1), "unit": "agent-steps/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"grid SIR N=1e6 L=1000, steps 0..{steps - 1} of 500 from init "
+                      f"({secs:.1f} s, single-threaded C oracle, -O2)",
+            "host_cpus": os.cpu_count()}
+
+
+# ------------------------------------------------------------------ main
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=480)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--chunk", type=int, default=0, help="steps per amber_step call (0 = all)")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--sir-form", choices=["auto", "pipelined", "persistent"], default="auto")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the 256-replicate sweep")
+    ap.add_argument("--serve", type=int, default=0,
+                    help="serve the first N requests of the 10,000-request stream (0 = skip)")
+    ap.add_argument("--serve-scale", type=float, default=1.0,
+                    help="arrival clock speed-up (1 = Poisson 50/s in real time)")
+    ap.add_argument("--serve-budget-gib", type=float, default=200.0)
+    ap.add_argument("--serve-chunk", type=int, default=50)
+    ap.add_argument("--serve-plain", action="store_true",
+                    help="also serve the stream FIFO one request at a time")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(runs and replicates are independent; see the sharding design notes). "
+              "Use --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    if args.warmup + args.steps > 0xFFFFFFFF or args.steps < 1:
+        sys.exit("bad --steps/--warmup")
+
+    import torch
+    from paper_2601_16292_amd import amber as A
+    A.lib()
+    if not torch.cuda.is_available():
+        sys.exit("bench.py needs a GPU")
+    torch.cuda.set_device(0)
+
+    n, L = 1_000_000, 1000
+    form = {"auto": 0, "pipelined": 1, "persistent": 2}[args.sir_form]
+    log(f"bench: SIR N={n} L={L} warmup={args.warmup} steps={args.steps} form={args.sir_form}")
+    secs, inv, times, infected = sir_bench(torch, A, args.warmup, args.steps, args.chunk, form)
+    value = n * args.steps / secs
+    log(f"bench: {value:.4g} agent-steps/s, {secs * 1e3 / args.steps:.4f} ms/step, kernels {times}")
+
+    # algorithmic bytes per launch of each SIR kernel over the timed steps
+    step_bytes = [sir_step_bytes(n, L, i_t) for i_t in infected]
+    priced = {}
+    if "sir_persistent" in times:
+        priced["sir_persistent"] = sum(step_bytes)          # every step in each launch
+    if "sir_body" in times:
+        priced["sir_body"] = sum(step_bytes[1:])            # one step per body launch
+    roof = roofline_for(times, priced, load_traffic())
+    if roof is not None:
+        roof["timed_region_GBs"] = round(sum(step_bytes) / secs / 1e9, 1)
+    kernels = {k: {"launches": v[0], "avg_us": round(v[1] / max(1, v[0]) * 1e3, 3)}
+               for k, v in times.items()}
+
+    out = {
+        "metric": "agent-steps/sec (1e6-agent SIR, wealth); sweep p50/p99 latency, batched vs plain",
+        "value": round(value, 1),
+        "unit": "agent-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(secs * 1e3 / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic (seeded Philox initial state; no dataset)",
+        "config": {"workload": "grid SIR, N=1e6 on a 1000x1000 torus, beta=1/20, gamma=1/100, "
+                               "0.1% initially infected, key (0,0), 500 steps",
+                   "n_agents": n, "grid_side": L, "timed_steps": f"{args.warmup}..{args.warmup + args.steps - 1}",
+                   "chunk": args.chunk or args.steps, "sir_form": args.sir_form},
+        "final_invariants": {k: inv[k] for k in ("step", "n_s", "n_i", "n_r", "digest")},
+        "kernels": kernels,
+        "roofline": roof,
+    }
+
+    if not args.no_extra:
+        extra = {}
+        s, winv = wealth_bench(torch, A, 1000, 0, 100)
+        extra["wealth_1k"] = {"value": round(1000 * 100 / s, 1), "unit": "agent-steps/s",
+                              "steps": 100, "ms_total": round(s * 1e3, 4),
+                              "wealth_sum": winv["wealth_sum"]}
+        s, winv = wealth_bench(torch, A, 1_000_000, 10, 200)
+        extra["wealth_1m"] = {"value": round(1e6 * 200 / s, 1), "unit": "agent-steps/s",
+                              "steps": 200, "ms_per_step": round(s * 1e3 / 200, 5),
+                              "wealth_sum": winv["wealth_sum"]}
+        if args.sir_form == "auto":
+            s2, _, t2, _ = sir_bench(torch, A, args.warmup, args.steps, args.chunk, 1)
+            extra["sir_1m_pipelined"] = {"value": round(n * args.steps / s2, 1),
+                                         "unit": "agent-steps/s",
+                                         "ms_per_step": round(s2 * 1e3 / args.steps, 5),
+                                         "kernels": {k: {"launches": v[0],
+                                                         "avg_us": round(v[1] / max(1, v[0]) * 1e3, 3)}
+                                                     for k, v in t2.items()}}
+        s, rinv = walk_bench(torch, A, 1_000_000, 1000, 1000)
+        extra["walk_1m"] = {"value": round(1e6 * 1000 / s, 1), "unit": "agent-steps/s",
+                            "steps": 1000, "ms_total": round(s * 1e3, 4),
+                            "out_of_bounds": rinv["out_of_bounds"]}
+        out["extra"] = extra
+        log(f"bench: extra {extra}")
+
+    if not args.no_sweep:
+        from paper_2601_16292_amd import sweep as SW, workloads as WL
+        runs = WL.sir_sweep()
+        log(f"bench: sweep of {len(runs)} SIR replicates, sum N = {sum(r['n'] for r in runs)}")
+        forms = {"plain": SW.run_plain(runs, torch), "batched": SW.run_batched(runs, torch),
+                 "batched_graph": SW.run_batched(runs, torch, graph=True)}
+        same = forms["plain"]["digests"] == forms["batched"]["digests"] == forms["batched_graph"]["digests"]
+        out["sweep"] = {k: {"value": round(v["value"], 1), "unit": "agent-steps/s",
+                            "seconds": round(v["seconds"], 4), "p50_s": round(v["p50_s"], 4),
+                            "p99_s": round(v["p99_s"], 4)} for k, v in forms.items()}
+        out["sweep"]["identical_outputs"] = bool(same)
+        out["sweep"]["workload"] = ("256 SIR replicates, N log-uniform in [1e3, 1e6], grid side "
+                                    "round(sqrt N), beta 16 values 0.01..0.2, gamma 1/100, 300 steps, "
+                                    "key (0, r); latency from sweep submission")
+        log(f"bench: sweep {out['sweep']}")
+
+    if args.serve:
+        from paper_2601_16292_amd import serve as SV, workloads as WL
+        reqs = WL.served_stream()[:args.serve]
+        log(f"bench: served stream of {len(reqs)} requests, time scale {args.serve_scale}")
+        served = SV.serve([dict(r) for r in reqs], budget_bytes=int(args.serve_budget_gib * 2**30),
+                          chunk=args.serve_chunk, time_scale=args.serve_scale, log=log)
+        entry = {"served": {k: served[k] for k in ("requests", "agent_steps", "seconds", "p50_s",
+                                                   "p99_s", "ticks")},
+                 "time_scale": args.serve_scale, "budget_gib": args.serve_budget_gib,
+                 "chunk": args.serve_chunk}
+        entry["served"]["value"] = round(served["value"], 1)
+        if args.serve_plain:
+            plain = SV.serve_plain([dict(r) for r in reqs], time_scale=args.serve_scale, log=log)
+            entry["plain"] = {k: plain[k] for k in ("requests", "agent_steps", "seconds", "p50_s",
+                                                    "p99_s")}
+            entry["plain"]["value"] = round(plain["value"], 1)
+            da = {r["id"]: r["digest"] for r in served["records"]}
+            db = {r["id"]: r["digest"] for r in plain["records"]}
+            entry["identical_outputs"] = da == db
+        out["serve"] = entry
+        log(f"bench: serve {entry}")
+
+    if not args.no_cpu:
+        log("bench: timing the CPU oracle")
+        out["cpu_baseline"] = cpu_baseline(args.cpu_budget)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

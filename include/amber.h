@@ -198,6 +198,42 @@ AMBER_API amber_status_t amber_invariants(amber_pop_t *pop, amber_invariants_t *
 /* Resolved parameters and step count of a handle (host only, no sync). */
 AMBER_API amber_status_t amber_pop_info(const amber_pop_t *pop, amber_pop_info_t *out);
 
+/* Launch-shape knobs.  They never change results (all arithmetic is integer
+ * and every random word is addressed by agent and step), only speed. */
+typedef struct {
+    uint32_t block;            /* threads per workgroup of the per-step kernels:
+                                  multiple of 64 in [64, 1024]; default 256       */
+    uint32_t sir_form;         /* 0 = automatic, 1 = pipelined (one kernel per
+                                  step), 2 = persistent (one cooperative kernel
+                                  per call, state in registers; fails with
+                                  AMBER_E_UNSUPPORTED when N does not fit)        */
+    uint32_t max_groups_per_thread; /* persistent form: largest number of 4-agent
+                                  groups a thread may hold (1, 2, 4, 8; 0 = 8)    */
+    uint32_t reserved;
+} amber_tuning_t;
+
+/* Set / get a handle's launch-shape knobs (host only). */
+AMBER_API amber_status_t amber_set_tuning(amber_pop_t *pop, const amber_tuning_t *t);
+AMBER_API amber_status_t amber_get_tuning(const amber_pop_t *pop, amber_tuning_t *t);
+
+/* Accumulated device time of one kernel of the path. */
+typedef struct {
+    char     name[40];
+    uint64_t launches;
+    double   total_ms;
+} amber_kernel_time_t;
+
+/* Measurement aid: while enabled, every kernel the handle enqueues is
+ * bracketed by HIP events on the handle's stream.  Enabling waits for the
+ * stream and clears the totals.  Off by default; results are unaffected. */
+AMBER_API amber_status_t amber_profile_enable(amber_pop_t *pop, int enable);
+
+/* Waits for the stream, folds the recorded events into per-kernel totals and
+ * copies min(cap, *count) entries to out; *count receives the number of
+ * distinct kernels seen. */
+AMBER_API amber_status_t amber_profile_read(amber_pop_t *pop, amber_kernel_time_t *out,
+                                            uint32_t cap, uint32_t *count);
+
 /* Free the handle (host memory only; device buffers stay the caller's).
  * Waits for the handle's enqueued work first. */
 AMBER_API amber_status_t amber_release(amber_pop_t *pop);

@@ -32,7 +32,9 @@ MODEL_COLUMNS = {WEALTH: [COL_WEALTH], RANDOM_WALK: [COL_X, COL_Y],
 EXPORTED = ["amber_abi_version", "amber_column_bytes", "amber_workspace_bytes",
             "amber_infection_table", "amber_init_population", "amber_step",
             "amber_step_batch", "amber_read_columns", "amber_invariants",
-            "amber_pop_info", "amber_release", "amber_last_error"]
+            "amber_pop_info", "amber_set_tuning", "amber_get_tuning",
+            "amber_profile_enable", "amber_profile_read",
+            "amber_release", "amber_last_error"]
 
 
 class RunDesc(ctypes.Structure):
@@ -68,6 +70,19 @@ class PopInfo(ctypes.Structure):
                 ("step", ctypes.c_uint64)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_uint32), ("sir_form", ctypes.c_uint32),
+                ("max_groups_per_thread", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+SIR_AUTO, SIR_PIPELINED, SIR_PERSISTENT = 0, 1, 2
+
+
+class KernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 40), ("launches", ctypes.c_uint64),
+                ("total_ms", ctypes.c_double)]
+
+
 class AmberError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
@@ -81,6 +96,12 @@ def lib():
     """Load libamber.so (raises if it has not been built)."""
     global _lib
     if _lib is None:
+        # Load PyTorch's HIP runtime first when it is installed, so that the
+        # library and torch share one runtime (and one notion of streams).
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                               "(there is no CPU fallback)")
@@ -108,6 +129,15 @@ def lib():
         L.amber_invariants.argtypes = [P, ctypes.POINTER(Invariants)]
         L.amber_pop_info.restype = ctypes.c_int
         L.amber_pop_info.argtypes = [P, ctypes.POINTER(PopInfo)]
+        L.amber_set_tuning.restype = ctypes.c_int
+        L.amber_set_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
+        L.amber_get_tuning.restype = ctypes.c_int
+        L.amber_get_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
+        L.amber_profile_enable.restype = ctypes.c_int
+        L.amber_profile_enable.argtypes = [P, ctypes.c_int]
+        L.amber_profile_read.restype = ctypes.c_int
+        L.amber_profile_read.argtypes = [P, ctypes.POINTER(KernelTime), ctypes.c_uint32,
+                                         ctypes.POINTER(ctypes.c_uint32)]
         L.amber_release.restype = ctypes.c_int
         L.amber_release.argtypes = [P]
         L.amber_last_error.restype = ctypes.c_char_p
@@ -184,6 +214,33 @@ def amber_pop_info(handle):
     out = PopInfo()
     st = lib().amber_pop_info(handle, ctypes.byref(out))
     return st, out
+
+
+def amber_set_tuning(handle, block=256, sir_form=SIR_AUTO, max_groups_per_thread=0):
+    t = Tuning(block, sir_form, max_groups_per_thread, 0)
+    return lib().amber_set_tuning(handle, ctypes.byref(t))
+
+
+def amber_get_tuning(handle):
+    """Returns (status, Tuning)."""
+    t = Tuning()
+    st = lib().amber_get_tuning(handle, ctypes.byref(t))
+    return st, t
+
+
+def amber_profile_enable(handle, enable):
+    return lib().amber_profile_enable(handle, 1 if enable else 0)
+
+
+def amber_profile_read(handle, cap=32):
+    """Returns (status, {kernel name: (launches, total_ms)})."""
+    out = (KernelTime * cap)()
+    count = ctypes.c_uint32(0)
+    st = lib().amber_profile_read(handle, out, cap, ctypes.byref(count))
+    if st != OK:
+        return st, None
+    return st, {out[i].name.decode(): (out[i].launches, out[i].total_ms)
+                for i in range(min(cap, count.value))}
 
 
 def amber_release(handle):
@@ -268,6 +325,19 @@ class Population:
             mask |= 1 << c
         check(amber_read_columns(self.handle, mask, ptrs))
         return [outs[c] for c in MODEL_COLUMNS[self.model]]
+
+    def tune(self, block=256, sir_form=SIR_AUTO, max_groups_per_thread=0):
+        check(amber_set_tuning(self.handle, block, sir_form, max_groups_per_thread))
+        return self
+
+    def profile(self, enable=True):
+        check(amber_profile_enable(self.handle, enable))
+        return self
+
+    def kernel_times(self):
+        st, t = amber_profile_read(self.handle)
+        check(st)
+        return t
 
     def release(self):
         if self.handle is not None and self.handle.value:

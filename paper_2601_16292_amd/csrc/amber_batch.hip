@@ -1,0 +1,145 @@
+// amber_batch.hip -- batched forms: many runs (replicates, sweep points,
+// served requests) of one model advance together, one launch per phase for a
+// whole chunk of runs instead of one launch per run.
+//
+// A chunk's run table travels in the kernel arguments (no device allocation):
+// run r owns workgroups [block_end[r-1], block_end[r]), and each workgroup
+// finds its run with a wavefront-uniform scan of block_end.  Every run keeps
+// its own descriptor, key and step index, and each of its agent groups runs
+// exactly the per-group body the single-run kernels use, so a run's result is
+// bit-identical alone or in any batch.
+#include "amber_device_common.h"
+
+namespace amber {
+
+// Run index of this workgroup and its block index within that run.
+__device__ __forceinline__ uint32_t batch_run(const uint32_t *block_end, uint32_t nruns,
+                                              uint32_t &local_block, uint32_t &run_blocks)
+{
+    uint32_t r = 0;
+    while (r + 1 < nruns && blockIdx.x >= block_end[r]) ++r;
+    const uint32_t first = r ? block_end[r - 1] : 0;
+    local_block = blockIdx.x - first;
+    run_blocks = block_end[r] - first;
+    return r;
+}
+
+// ------------------------------------------------------------------ random walk
+
+__global__ void k_walk_batch(WalkBatch b, uint32_t n_steps)
+{
+    uint32_t lb, nb;
+    const uint32_t r = batch_run(b.block_end, b.nruns, lb, nb);
+    const uint32_t q = lb * blockDim.x + threadIdx.x;
+    if (q < groups_of(b.n[r]))
+        walk_group((int4 *)b.x[r], (int4 *)b.y[r], q, b.L[r], b.k0[r], b.k1[r], b.t0[r], n_steps);
+}
+
+// ------------------------------------------------------------------ wealth
+
+// One workgroup per small run (state in LDS for every step).
+__global__ __launch_bounds__(WEALTH_SMALL_THREADS) void k_wealth_small_batch(WealthSmallBatch b,
+                                                                             uint32_t n_steps)
+{
+    __shared__ int32_t sw[WEALTH_SMALL_MAX];
+    __shared__ int32_t sinc[WEALTH_SMALL_MAX];
+    const uint32_t r = blockIdx.x;
+    wealth_small_run(b.w[r], sw, sinc, b.n[r], b.k0[r], b.k1[r], b.t0[r], n_steps);
+}
+
+// Step i of the call for every large run of the chunk.
+__global__ void k_wealth_step_batch(WealthBatch b, uint32_t i)
+{
+    uint32_t lb, nb;
+    const uint32_t r = batch_run(b.block_end, b.nruns, lb, nb);
+    const uint32_t q = lb * blockDim.x + threadIdx.x;
+    if (q < groups_of(b.n[r]))
+        wealth_step_group((int4 *)b.base[r], (int4 *)b.inc[i & 1][r], b.inc[(i + 1) & 1][r], q,
+                          b.n[r], b.k0[r], b.k1[r], b.t0[r] + i);
+}
+
+__global__ void k_wealth_fold_batch(WealthBatch b, uint32_t parity)
+{
+    uint32_t lb, nb;
+    const uint32_t r = batch_run(b.block_end, b.nruns, lb, nb);
+    const uint32_t q = lb * blockDim.x + threadIdx.x;
+    if (q < groups_of(b.n[r])) wealth_fold_group((int4 *)b.base[r], (int4 *)b.inc[parity][r], q);
+}
+
+// ------------------------------------------------------------------ SIR (pipelined)
+
+__global__ void k_sir_head_batch(SirBatch b)
+{
+    uint32_t lb, nb;
+    const uint32_t r = batch_run(b.block_end, b.nruns, lb, nb);
+    const SirParams &p = b.run[r];
+    const uint32_t q = lb * blockDim.x + threadIdx.x;
+    if (q < p.groups) sir_head_group(p, q, b.t0[r]);
+}
+
+__global__ void k_sir_body_batch(SirBatch b, uint32_t i)
+{
+    uint32_t lb, nb;
+    const uint32_t r = batch_run(b.block_end, b.nruns, lb, nb);
+    const SirParams &p = b.run[r];
+    const uint32_t t = b.t0[r] + i;
+    const uint32_t q = lb * blockDim.x + threadIdx.x;
+    zero_quads(grid_of(p, t + 1), p.quads, q, nb * blockDim.x);
+    if (q < p.groups) sir_body_group(p, q, t);
+}
+
+__global__ void k_sir_tail_batch(SirBatch b, uint32_t i)
+{
+    uint32_t lb, nb;
+    const uint32_t r = batch_run(b.block_end, b.nruns, lb, nb);
+    const SirParams &p = b.run[r];
+    const uint32_t t = b.t0[r] + i;
+    const uint32_t q = lb * blockDim.x + threadIdx.x;
+    zero_quads(grid_of(p, t + 2), p.quads, q, nb * blockDim.x);
+    if (q < p.groups) sir_tail_group(p, q, t);
+}
+
+// ------------------------------------------------------------------ launchers
+
+hipError_t launch_walk_batch(const WalkBatch &b, uint32_t n_steps, uint32_t block, hipStream_t st)
+{
+    const uint32_t blocks = b.block_end[b.nruns - 1];
+    hipLaunchKernelGGL(k_walk_batch, dim3(blocks), dim3(block), 0, st, b, n_steps);
+    return hipGetLastError();
+}
+
+hipError_t launch_wealth_small_batch(const WealthSmallBatch &b, uint32_t n_steps, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_wealth_small_batch, dim3(b.nruns), dim3(WEALTH_SMALL_THREADS), 0, st, b,
+                       n_steps);
+    return hipGetLastError();
+}
+
+hipError_t launch_wealth_batch(const WealthBatch &b, uint32_t n_steps, uint32_t block,
+                               hipStream_t st)
+{
+    const uint32_t blocks = b.block_end[b.nruns - 1];
+    for (uint32_t i = 0; i < n_steps; ++i) {
+        hipLaunchKernelGGL(k_wealth_step_batch, dim3(blocks), dim3(block), 0, st, b, i);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_wealth_fold_batch, dim3(blocks), dim3(block), 0, st, b, n_steps & 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_sir_batch(const SirBatch &b, uint32_t n_steps, uint32_t block, hipStream_t st)
+{
+    const uint32_t blocks = b.block_end[b.nruns - 1];
+    hipLaunchKernelGGL(k_sir_head_batch, dim3(blocks), dim3(block), 0, st, b);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    for (uint32_t i = 1; i < n_steps; ++i) {
+        hipLaunchKernelGGL(k_sir_body_batch, dim3(blocks), dim3(block), 0, st, b, i);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_sir_tail_batch, dim3(blocks), dim3(block), 0, st, b, n_steps - 1);
+    return hipGetLastError();
+}
+
+}  // namespace amber

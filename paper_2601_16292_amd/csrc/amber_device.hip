@@ -1,4 +1,5 @@
-// amber_device.hip -- gfx950 kernels of the columnar ABM hot path.
+// amber_device.hip -- gfx950 kernels of the columnar ABM hot path (one run
+// per launch).  The batched forms live in amber_batch.hip.
 //
 // Columns are structure-of-arrays (Sec. 3.1.1): int32 wealth, int32 x, int32 y,
 // uint8 state, each padded to whole 64-agent groups.  A thread owns 4
@@ -11,81 +12,13 @@
 // Everything is integer arithmetic; there is no dense contraction on this path
 // (no MFMA).  The kernels are bound by HBM (or cache) bandwidth, by integer
 // VALU throughput for Philox, and by atomic throughput for the scatter-adds.
-#include "amber_internal.h"
+#include "amber_device_common.h"
+
+#include <hip/hip_cooperative_groups.h>
+
+namespace cg = cooperative_groups;
 
 namespace amber {
-
-// ------------------------------------------------------------------ Philox
-// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  Multipliers and Weyl
-// key increments as published.  The key lives in SGPRs (wavefront-uniform);
-// each 32x32->64 product is one v_mad_u64_u32.
-constexpr uint32_t PHILOX_M0 = 0xD2511F53u;
-constexpr uint32_t PHILOX_M1 = 0xCD9E8D57u;
-constexpr uint32_t PHILOX_W0 = 0x9E3779B9u;
-constexpr uint32_t PHILOX_W1 = 0xBB67AE85u;
-
-__device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2,
-                                        uint32_t k0, uint32_t k1)
-{
-    uint32_t c3 = 0;
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        const uint64_t p0 = (uint64_t)PHILOX_M0 * c0;
-        const uint64_t p1 = (uint64_t)PHILOX_M1 * c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
-        c1 = (uint32_t)p1;
-        c3 = (uint32_t)p0;
-        c0 = n0;
-        c2 = n2;
-        k0 += PHILOX_W0;
-        k1 += PHILOX_W1;
-    }
-    return make_uint4(c0, c1, c2, c3);
-}
-
-// ------------------------------------------------------------------ mappings
-// Moore move from the top 3 bits of a word: index d selects (dx, dy) from the
-// 8 moves in lexicographic order without (0,0).  The tables hold dx+1 and
-// dy+1 as 2-bit fields at bit 2d.
-constexpr uint32_t MOVE_DX1 = (0u << 0) | (0u << 2) | (0u << 4) | (1u << 6) | (1u << 8) |
-                              (2u << 10) | (2u << 12) | (2u << 14);
-constexpr uint32_t MOVE_DY1 = (0u << 0) | (1u << 2) | (2u << 4) | (0u << 6) | (2u << 8) |
-                              (0u << 10) | (1u << 12) | (2u << 14);
-
-// Torus step of one coordinate in [0, L) by d in {-1, 0, 1}.
-__device__ __forceinline__ int32_t wrap_step(int32_t v, int32_t d, int32_t L)
-{
-    v += d;
-    v = (v < 0) ? v + L : v;
-    v = (v >= L) ? v - L : v;
-    return v;
-}
-
-__device__ __forceinline__ void moore_move(uint32_t u, int32_t L, int32_t &x, int32_t &y)
-{
-    const uint32_t sh = (u >> 28) & 14u;   // 2 * (u >> 29)
-    x = wrap_step(x, (int32_t)((MOVE_DX1 >> sh) & 3u) - 1, L);
-    y = wrap_step(y, (int32_t)((MOVE_DY1 >> sh) & 3u) - 1, L);
-}
-
-// floor(u * L / 2^32)
-__device__ __forceinline__ int32_t grid_coord(uint32_t u, int32_t L)
-{
-    return (int32_t)__umulhi(u, (uint32_t)L);
-}
-
-// floor((hi:lo) * n / 2^64) for n < 2^32.
-__device__ __forceinline__ uint32_t recipient(uint32_t hi, uint32_t lo, uint32_t n)
-{
-    const uint64_t lo_n = (uint64_t)lo * n;
-    const uint64_t mid = (uint64_t)hi * n + (lo_n >> 32);
-    return (uint32_t)(mid >> 32);
-}
-
-__host__ __device__ inline uint32_t div_up(uint32_t a, uint32_t b) { return (a + b - 1) / b; }
-__host__ __device__ inline uint32_t groups_of(uint32_t n) { return div_up(n, 4); }
-__host__ __device__ inline uint32_t padded_groups(uint32_t n) { return div_up(n, AGENT_PAD) * (AGENT_PAD / 4); }
 
 // ------------------------------------------------------------------ init
 
@@ -143,224 +76,106 @@ __global__ void k_walk(int4 *__restrict__ x, int4 *__restrict__ y, uint32_t grou
                        uint32_t k0, uint32_t k1, uint32_t t0, uint32_t n_steps)
 {
     const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= groups) return;
-    int4 X = x[q];
-    int4 Y = y[q];
-    for (uint32_t i = 0; i < n_steps; ++i) {
-        const uint4 r = philox(q, t0 + i, P_MOVE, k0, k1);
-        moore_move(r.x, L, X.x, Y.x);
-        moore_move(r.y, L, X.y, Y.y);
-        moore_move(r.z, L, X.z, Y.z);
-        moore_move(r.w, L, X.w, Y.w);
-    }
-    x[q] = X;
-    y[q] = Y;
+    if (q < groups) walk_group(x, y, q, L, k0, k1, t0, n_steps);
 }
 
 // ------------------------------------------------------------------ wealth
-// One synchronous transfer step.  The state of agent a is base[a] +
-// inc_cur[a]; the snapshot decides the donors (wealth > 0).  A donor's unit
-// leaves base in place (plain store, the thread owns the row) and lands in
-// inc_nxt[recipient] through an integer atomic add, so duplicates accumulate
-// in any order with an identical result.  inc_cur is cleared for reuse two
-// steps later.
+
 __global__ void k_wealth_step(int4 *__restrict__ base, int4 *__restrict__ inc_cur,
                               int32_t *__restrict__ inc_nxt, uint32_t groups, uint32_t n,
                               uint32_t k0, uint32_t k1, uint32_t t)
 {
     const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= groups) return;
-    const int4 B = base[q];
-    const int4 I = inc_cur[q];
-    const int32_t v0 = B.x + I.x, v1 = B.y + I.y, v2 = B.z + I.z, v3 = B.w + I.w;
-    const uint32_t a = 4 * q;
-    const bool d0 = v0 > 0 && a + 0 < n;
-    const bool d1 = v1 > 0 && a + 1 < n;
-    const bool d2 = v2 > 0 && a + 2 < n;
-    const bool d3 = v3 > 0 && a + 3 < n;
-    base[q] = make_int4(v0 - d0, v1 - d1, v2 - d2, v3 - d3);
-    inc_cur[q] = make_int4(0, 0, 0, 0);
-    if (d0 | d1) {
-        const uint4 r = philox(2 * q, t, P_RECIPIENT, k0, k1);
-        if (d0) atomicAdd(&inc_nxt[recipient(r.x, r.y, n)], 1);
-        if (d1) atomicAdd(&inc_nxt[recipient(r.z, r.w, n)], 1);
-    }
-    if (d2 | d3) {
-        const uint4 r = philox(2 * q + 1, t, P_RECIPIENT, k0, k1);
-        if (d2) atomicAdd(&inc_nxt[recipient(r.x, r.y, n)], 1);
-        if (d3) atomicAdd(&inc_nxt[recipient(r.z, r.w, n)], 1);
-    }
+    if (q < groups) wealth_step_group(base, inc_cur, inc_nxt, q, n, k0, k1, t);
 }
 
 __global__ void k_wealth_fold(int4 *__restrict__ base, int4 *__restrict__ inc, uint32_t groups)
 {
     const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= groups) return;
-    const int4 B = base[q];
-    const int4 I = inc[q];
-    base[q] = make_int4(B.x + I.x, B.y + I.y, B.z + I.z, B.w + I.w);
-    inc[q] = make_int4(0, 0, 0, 0);
+    if (q < groups) wealth_fold_group(base, inc, q);
 }
-
-// Small populations: one workgroup runs every step with the wealth column and
-// the increments in LDS; two barriers per step separate the donor/scatter
-// phase from the apply phase.  A thread owns agent pairs (one RECIPIENT
-// block per pair).
-constexpr uint32_t WEALTH_SMALL_THREADS = 1024;
-constexpr uint32_t WEALTH_SMALL_MAX = 8192;   // 2 x 32 KB of LDS
 
 __global__ __launch_bounds__(WEALTH_SMALL_THREADS) void k_wealth_small(
     int32_t *__restrict__ w, uint32_t n, uint32_t k0, uint32_t k1, uint32_t t0, uint32_t n_steps)
 {
     __shared__ int32_t sw[WEALTH_SMALL_MAX];
     __shared__ int32_t sinc[WEALTH_SMALL_MAX];
-    for (uint32_t a = threadIdx.x; a < n; a += blockDim.x) {
-        sw[a] = w[a];
-        sinc[a] = 0;
+    wealth_small_run(w, sw, sinc, n, k0, k1, t0, n_steps);
+}
+
+// head: move + bin(t)
+__global__ void k_sir_head(SirParams p, uint32_t t)
+{
+    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < p.groups) sir_head_group(p, q, t);
+}
+
+// body: transition(t-1), then move + bin(t); clears C[(t+1)%3].
+__global__ void k_sir_body(SirParams p, uint32_t t)
+{
+    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    zero_quads(grid_of(p, t + 1), p.quads, q, gridDim.x * blockDim.x);
+    if (q < p.groups) sir_body_group(p, q, t);
+}
+
+// tail: transition(t); clears C[(t+2)%3].
+__global__ void k_sir_tail(SirParams p, uint32_t t)
+{
+    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    zero_quads(grid_of(p, t + 2), p.quads, q, gridDim.x * blockDim.x);
+    if (q < p.groups) sir_tail_group(p, q, t);
+}
+
+// Persistent form: G groups of 4 agents per thread (group q = tid + g*threads).
+template <int G>
+__global__ __launch_bounds__(256) void k_sir_persistent(SirParams p, uint32_t t0, uint32_t n_steps)
+{
+    cg::grid_group grid = cg::this_grid();
+    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t nthr = gridDim.x * blockDim.x;
+    int4 X[G], Y[G];
+    uint32_t S[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const uint32_t q = tid + g * nthr;
+        if (q < p.groups) {
+            X[g] = ((const int4 *)p.x)[q];
+            Y[g] = ((const int4 *)p.y)[q];
+            S[g] = ((const uint32_t *)p.s)[q];
+        } else {
+            X[g] = Y[g] = make_int4(0, 0, 0, 0);
+            S[g] = 0x02020202u;
+        }
     }
-    __syncthreads();
-    const uint32_t pairs = div_up(n, 2);
     for (uint32_t i = 0; i < n_steps; ++i) {
         const uint32_t t = t0 + i;
-        for (uint32_t p = threadIdx.x; p < pairs; p += blockDim.x) {
-            const uint32_t a = 2 * p;
-            const int32_t v0 = sw[a];
-            const int32_t v1 = (a + 1 < n) ? sw[a + 1] : 0;
-            const bool d0 = v0 > 0, d1 = v1 > 0;
-            if (d0 | d1) {
-                const uint4 r = philox(p, t, P_RECIPIENT, k0, k1);
-                if (d0) {
-                    sw[a] = v0 - 1;
-                    atomicAdd(&sinc[recipient(r.x, r.y, n)], 1);
-                }
-                if (d1) {
-                    sw[a + 1] = v1 - 1;
-                    atomicAdd(&sinc[recipient(r.z, r.w, n)], 1);
-                }
+        uint32_t *cur = grid_of(p, t);
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const uint32_t q = tid + g * nthr;
+            if (q < p.groups) {
+                sir_move4(p, q, t, X[g], Y[g]);
+                sir_bin4(p, cur, q, S[g], X[g], Y[g]);
             }
         }
-        __syncthreads();
-        for (uint32_t a = threadIdx.x; a < n; a += blockDim.x) {
-            sw[a] += sinc[a];
-            sinc[a] = 0;
+        grid.sync();
+        zero_quads(grid_of(p, t + 2), p.quads, tid, nthr);
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const uint32_t q = tid + g * nthr;
+            if (q < p.groups) S[g] = sir_transition4(p, cur, q, t, S[g], X[g], Y[g]);
         }
-        __syncthreads();
     }
-    for (uint32_t a = threadIdx.x; a < n; a += blockDim.x) w[a] = sw[a];
-}
-
-// ------------------------------------------------------------------ SIR
-
-// Positions come from the caller's columns; a coordinate outside [0, L) (only
-// possible if the caller overwrote a column) is never used as an address.
-__device__ __forceinline__ bool on_grid(int32_t x, int32_t y, int32_t L)
-{
-    return (uint32_t)x < (uint32_t)L && (uint32_t)y < (uint32_t)L;
-}
-
-__device__ __forceinline__ void bin_infected(uint32_t *__restrict__ count, int32_t L, bool inf,
-                                             int32_t x, int32_t y)
-{
-    if (inf && on_grid(x, y, L)) atomicAdd(&count[(uint32_t)y * L + x], 1u);
-}
-
-// Phase 1: move every agent (same words and rule as the random walk) and
-// count the agents infected at the start of the step in their post-move cell.
-__global__ void k_sir_move_bin(int4 *__restrict__ x, int4 *__restrict__ y,
-                               const uint32_t *__restrict__ s4, uint32_t *__restrict__ count,
-                               uint32_t groups, uint32_t n, int32_t L, uint32_t k0, uint32_t k1,
-                               uint32_t t)
-{
-    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= groups) return;
-    int4 X = x[q];
-    int4 Y = y[q];
-    const uint32_t S = s4[q];
-    const uint4 r = philox(q, t, P_MOVE, k0, k1);
-    moore_move(r.x, L, X.x, Y.x);
-    moore_move(r.y, L, X.y, Y.y);
-    moore_move(r.z, L, X.z, Y.z);
-    moore_move(r.w, L, X.w, Y.w);
-    x[q] = X;
-    y[q] = Y;
-    const uint32_t a = 4 * q;
-    bin_infected(count, L, (S & 0xffu) == ST_I && a + 0 < n, X.x, Y.x);
-    bin_infected(count, L, ((S >> 8) & 0xffu) == ST_I && a + 1 < n, X.y, Y.y);
-    bin_infected(count, L, ((S >> 16) & 0xffu) == ST_I && a + 2 < n, X.z, Y.z);
-    bin_infected(count, L, (S >> 24) == ST_I && a + 3 < n, X.w, Y.w);
-}
-
-// Infected agents in the distinct cells of the 3x3 torus block around (cx, cy).
-__device__ __forceinline__ uint32_t block_count(const uint32_t *__restrict__ count, int32_t L,
-                                                int32_t cx, int32_t cy)
-{
-    if (!on_grid(cx, cy, L)) return 0;
-    if (L >= 3) {
-        const int32_t xm = cx == 0 ? L - 1 : cx - 1;
-        const int32_t xp = cx == L - 1 ? 0 : cx + 1;
-        const int32_t ym = cy == 0 ? L - 1 : cy - 1;
-        const int32_t yp = cy == L - 1 ? 0 : cy + 1;
-        const uint32_t *rm = count + (uint32_t)ym * L;
-        const uint32_t *r0 = count + (uint32_t)cy * L;
-        const uint32_t *rp = count + (uint32_t)yp * L;
-        return rm[xm] + rm[cx] + rm[xp] + r0[xm] + r0[cx] + r0[xp] + rp[xm] + rp[cx] + rp[xp];
-    }
-    // L = 1 or 2: the wrapped block covers each of the L*L cells exactly once.
-    uint32_t k = 0;
-    for (int32_t c = 0; c < L * L; ++c) k += count[c];
-    return k;
-}
-
-// Phase 2: state transitions from the snapshot state and the counts; clears
-// the other count buffer for the next step.
-__global__ void k_sir_transition(const int4 *__restrict__ x, const int4 *__restrict__ y,
-                                 uint32_t *__restrict__ s4, const uint32_t *__restrict__ count,
-                                 uint4 *__restrict__ count_next, uint32_t count_quads,
-                                 const uint32_t *__restrict__ t_inf, uint32_t k_last,
-                                 uint32_t t_rec, uint32_t groups, uint32_t n, int32_t L,
-                                 uint32_t k0, uint32_t k1, uint32_t t)
-{
-    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t i = q; i < count_quads; i += stride) count_next[i] = make_uint4(0, 0, 0, 0);
-    if (q >= groups) return;
-
-    const uint32_t S = s4[q];
-    const uint32_t a = 4 * q;
-    uint32_t st[4], k[4];
-    bool any_sus = false;
-    for (int j = 0; j < 4; ++j) {
-        st[j] = (a + j < n) ? (S >> (8 * j)) & 0xffu : (uint32_t)ST_R;   // padding never changes
-        any_sus |= st[j] == ST_S;
-        k[j] = 0;
-    }
-    if (any_sus) {
-        const int4 X = x[q];
-        const int4 Y = y[q];
-        if (st[0] == ST_S) k[0] = block_count(count, L, X.x, Y.x);
-        if (st[1] == ST_S) k[1] = block_count(count, L, X.y, Y.y);
-        if (st[2] == ST_S) k[2] = block_count(count, L, X.z, Y.z);
-        if (st[3] == ST_S) k[3] = block_count(count, L, X.w, Y.w);
-    }
-    bool need = false;
-    for (int j = 0; j < 4; ++j) need |= (st[j] == ST_S && k[j] > 0) || st[j] == ST_I;
-    if (!need) return;
-    const uint4 r = philox(q, t, P_EPI, k0, k1);
-    const uint32_t u[4] = {r.x, r.y, r.z, r.w};
-    uint32_t out = S;
-    for (int j = 0; j < 4; ++j) {
-        uint32_t ns = st[j];
-        if (st[j] == ST_S && k[j] > 0) {
-            const uint32_t thr = t_inf[k[j] < k_last ? k[j] : k_last];
-            if (u[j] < thr) ns = ST_I;
-        } else if (st[j] == ST_I) {
-            if (u[j] < t_rec) ns = ST_R;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const uint32_t q = tid + g * nthr;
+        if (q < p.groups) {
+            ((int4 *)p.x)[q] = X[g];
+            ((int4 *)p.y)[q] = Y[g];
+            ((uint32_t *)p.s)[q] = S[g];
         }
-        if (ns != st[j]) out = (out & ~(0xffu << (8 * j))) | (ns << (8 * j));
     }
-    if (out != S) s4[q] = out;
 }
-
 // ------------------------------------------------------------------ invariants
 
 __device__ __forceinline__ uint64_t fmix64(uint64_t z)
@@ -387,68 +202,112 @@ __device__ __forceinline__ int wave_min(int v)
     return v;
 }
 
-__global__ void k_inv_clear(DevInvariants *acc)
+struct InvAcc {
+    unsigned long long wsum, ns, ni, nr, oob, dig;
+    int wmin;
+};
+
+__device__ __forceinline__ void inv_wave_reduce(InvAcc &v)
 {
+    v.wsum = wave_sum(v.wsum);
+    v.ns = wave_sum(v.ns);
+    v.ni = wave_sum(v.ni);
+    v.nr = wave_sum(v.nr);
+    v.oob = wave_sum(v.oob);
+    v.dig = wave_sum(v.dig);
+    v.wmin = wave_min(v.wmin);
+}
+
+// Reduce the accumulators of a 256-thread workgroup; thread 0 returns the total.
+__device__ __forceinline__ void inv_block_reduce(InvAcc &v)
+{
+    __shared__ InvAcc part[4];
+    inv_wave_reduce(v);
+    const uint32_t wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) part[wave] = v;
+    __syncthreads();
     if (threadIdx.x == 0) {
-        acc->wealth_sum = 0;
-        acc->n_s = acc->n_i = acc->n_r = 0;
-        acc->out_of_bounds = 0;
-        acc->digest = 0;
-        acc->wealth_min = 0x7fffffff;
+        for (uint32_t w = 1; w < blockDim.x / 64; ++w) {
+            v.wsum += part[w].wsum;
+            v.ns += part[w].ns;
+            v.ni += part[w].ni;
+            v.nr += part[w].nr;
+            v.oob += part[w].oob;
+            v.dig += part[w].dig;
+            v.wmin = min(v.wmin, part[w].wmin);
+        }
     }
 }
 
-__global__ void k_invariants(uint32_t model, uint32_t n, int32_t L, const int32_t *__restrict__ w,
-                             const int32_t *__restrict__ x, const int32_t *__restrict__ y,
-                             const uint8_t *__restrict__ s, DevInvariants *acc)
+__device__ __forceinline__ void inv_store(DevInvariants *d, const InvAcc &v)
 {
-    unsigned long long wsum = 0, ns = 0, ni = 0, nr = 0, oob = 0, dig = 0;
-    int wmin = 0x7fffffff;
+    d->wealth_sum = v.wsum;
+    d->n_s = v.ns;
+    d->n_i = v.ni;
+    d->n_r = v.nr;
+    d->out_of_bounds = v.oob;
+    d->digest = v.dig;
+    d->wealth_min = v.wmin;
+}
+
+// Stage 1: workgroup b reduces a grid-stride share of the agents into partials[b].
+__global__ __launch_bounds__(256) void k_invariants(uint32_t model, uint32_t n, int32_t L,
+                                                    const int32_t *__restrict__ w,
+                                                    const int32_t *__restrict__ x,
+                                                    const int32_t *__restrict__ y,
+                                                    const uint8_t *__restrict__ s,
+                                                    DevInvariants *__restrict__ partials)
+{
+    InvAcc v{0, 0, 0, 0, 0, 0, 0x7fffffff};
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t a = blockIdx.x * blockDim.x + threadIdx.x; a < n; a += stride) {
         uint64_t h = fmix64((uint64_t)a);
         bool bad = false;
         if (model == 0) {
-            const int32_t v = w[a];
-            wsum += (unsigned long long)(long long)v;
-            wmin = min(wmin, v);
-            bad = v < 0;
-            h = mix_col(h, 0, (uint32_t)v);
+            const int32_t wv = w[a];
+            v.wsum += (unsigned long long)(long long)wv;
+            v.wmin = min(v.wmin, wv);
+            bad = wv < 0;
+            h = mix_col(h, 0, (uint32_t)wv);
         } else {
             const int32_t px = x[a], py = y[a];
-            bad = px < 0 || px >= L || py < 0 || py >= L;
+            bad = !on_grid(px, py, L);
             h = mix_col(h, 0, (uint32_t)px);
             h = mix_col(h, 1, (uint32_t)py);
             if (model == 2) {
                 const uint32_t sv = s[a];
-                ns += sv == ST_S;
-                ni += sv == ST_I;
-                nr += sv == ST_R;
+                v.ns += sv == ST_S;
+                v.ni += sv == ST_I;
+                v.nr += sv == ST_R;
                 bad |= sv > ST_R;
                 h = mix_col(h, 2, sv);
             }
         }
-        oob += bad;
-        dig += h;
+        v.oob += bad;
+        v.dig += h;
     }
-    wsum = wave_sum(wsum);
-    ns = wave_sum(ns);
-    ni = wave_sum(ni);
-    nr = wave_sum(nr);
-    oob = wave_sum(oob);
-    dig = wave_sum(dig);
-    wmin = wave_min(wmin);
-    if ((threadIdx.x & 63) == 0) {
-        if (wsum) atomicAdd(&acc->wealth_sum, wsum);
-        if (ns) atomicAdd(&acc->n_s, ns);
-        if (ni) atomicAdd(&acc->n_i, ni);
-        if (nr) atomicAdd(&acc->n_r, nr);
-        if (oob) atomicAdd(&acc->out_of_bounds, oob);
-        atomicAdd(&acc->digest, dig);
-        if (model == 0) atomicMin(&acc->wealth_min, wmin);
-    }
+    inv_block_reduce(v);
+    if (threadIdx.x == 0) inv_store(&partials[blockIdx.x], v);
 }
 
+// Stage 2: one workgroup folds the partials.
+__global__ __launch_bounds__(256) void k_invariants_final(const DevInvariants *__restrict__ partials,
+                                                          uint32_t count, DevInvariants *acc)
+{
+    InvAcc v{0, 0, 0, 0, 0, 0, 0x7fffffff};
+    for (uint32_t i = threadIdx.x; i < count; i += blockDim.x) {
+        const DevInvariants &d = partials[i];
+        v.wsum += d.wealth_sum;
+        v.ns += d.n_s;
+        v.ni += d.n_i;
+        v.nr += d.n_r;
+        v.oob += d.out_of_bounds;
+        v.dig += d.digest;
+        v.wmin = min(v.wmin, d.wealth_min);
+    }
+    inv_block_reduce(v);
+    if (threadIdx.x == 0) inv_store(acc, v);
+}
 // ------------------------------------------------------------------ launchers
 
 static inline dim3 grid_for(uint32_t items, uint32_t block) { return dim3(div_up(items, block)); }
@@ -525,34 +384,105 @@ hipError_t launch_wealth_small(int32_t *w, uint32_t n, uint32_t k0, uint32_t k1,
     return hipGetLastError();
 }
 
-hipError_t launch_sir_step(const SirParams &p, uint32_t t, const Tuning &tu, hipStream_t st)
+void sir_fill(SirParams &p)
 {
-    const uint32_t g = groups_of(p.n);
-    const uint32_t cells = (uint32_t)p.L * (uint32_t)p.L;
-    const uint32_t quads = div_up(cells, 4);
-    uint32_t *cur = p.count[t & 1];
-    uint32_t *nxt = p.count[(t + 1) & 1];
-    hipLaunchKernelGGL(k_sir_move_bin, grid_for(g, tu.block), dim3(tu.block), 0, st,
-                       (int4 *)p.x, (int4 *)p.y, (const uint32_t *)p.s, cur, g, p.n, p.L,
-                       p.k0, p.k1, t);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sir_transition, grid_for(g, tu.block), dim3(tu.block), 0, st,
-                       (const int4 *)p.x, (const int4 *)p.y, (uint32_t *)p.s, cur, (uint4 *)nxt,
-                       quads, p.t_inf, p.table_len - 1, p.t_rec, g, p.n, p.L, p.k0, p.k1, t);
+    p.groups = groups_of(p.n);
+    p.quads = div_up((uint32_t)p.L * (uint32_t)p.L, 4);
+}
+
+hipError_t launch_sir_head(SirParams p, uint32_t t, const Tuning &tu, hipStream_t st)
+{
+    sir_fill(p);
+    hipLaunchKernelGGL(k_sir_head, grid_for(p.groups, tu.block), dim3(tu.block), 0, st, p, t);
     return hipGetLastError();
+}
+
+hipError_t launch_sir_body(SirParams p, uint32_t t, const Tuning &tu, hipStream_t st)
+{
+    sir_fill(p);
+    hipLaunchKernelGGL(k_sir_body, grid_for(p.groups, tu.block), dim3(tu.block), 0, st, p, t);
+    return hipGetLastError();
+}
+
+hipError_t launch_sir_tail(SirParams p, uint32_t t, const Tuning &tu, hipStream_t st)
+{
+    sir_fill(p);
+    hipLaunchKernelGGL(k_sir_tail, grid_for(p.groups, tu.block), dim3(tu.block), 0, st, p, t);
+    return hipGetLastError();
+}
+
+// Co-resident workgroups of 256 threads for the persistent SIR kernel with G
+// groups per thread on the current device (0 if it cannot run).
+template <int G>
+static uint32_t persistent_capacity()
+{
+    int dev = 0, cus = 0, per_cu = 0, coop = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop)
+        return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sir_persistent<G>, 256, 0) !=
+        hipSuccess)
+        return 0;
+    return (uint32_t)(cus * per_cu);
+}
+
+template <int G>
+static hipError_t launch_persistent_g(SirParams p, uint32_t t0, uint32_t n_steps, uint32_t blocks,
+                                      hipStream_t st)
+{
+    void *args[] = {&p, &t0, &n_steps};
+    return hipLaunchCooperativeKernel((const void *)k_sir_persistent<G>, dim3(blocks), dim3(256),
+                                      args, 0, st);
+}
+
+uint32_t sir_persistent_groups_per_thread(uint32_t n, uint32_t max_g, uint32_t *blocks_out)
+{
+    const uint32_t groups = groups_of(n);
+    static const uint32_t gs[] = {1, 2, 4, 8};
+    for (uint32_t g : gs) {
+        if (g > max_g) break;
+        uint32_t cap = 0;
+        switch (g) {
+        case 1: cap = persistent_capacity<1>(); break;
+        case 2: cap = persistent_capacity<2>(); break;
+        case 4: cap = persistent_capacity<4>(); break;
+        case 8: cap = persistent_capacity<8>(); break;
+        }
+        const uint32_t need = div_up(groups, 256 * g);
+        if (cap && need <= cap) {
+            if (blocks_out) *blocks_out = need;
+            return g;
+        }
+    }
+    return 0;
+}
+
+hipError_t launch_sir_persistent(SirParams p, uint32_t t0, uint32_t n_steps, uint32_t g,
+                                 uint32_t blocks, hipStream_t st)
+{
+    sir_fill(p);
+    switch (g) {
+    case 1: return launch_persistent_g<1>(p, t0, n_steps, blocks, st);
+    case 2: return launch_persistent_g<2>(p, t0, n_steps, blocks, st);
+    case 4: return launch_persistent_g<4>(p, t0, n_steps, blocks, st);
+    case 8: return launch_persistent_g<8>(p, t0, n_steps, blocks, st);
+    }
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_invariants(uint32_t model, uint32_t n, int32_t L, const int32_t *w,
                              const int32_t *x, const int32_t *y, const uint8_t *s,
-                             DevInvariants *acc, hipStream_t st)
+                             DevInvariants *acc, DevInvariants *partials, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_inv_clear, dim3(1), dim3(64), 0, st, acc);
+    uint32_t blocks = div_up(n, 256 * 4);
+    if (blocks > INV_MAX_BLOCKS) blocks = INV_MAX_BLOCKS;
+    hipLaunchKernelGGL(k_invariants, dim3(blocks), dim3(256), 0, st, model, n, L, w, x, y, s,
+                       partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    uint32_t blocks = div_up(n, 256);
-    if (blocks > 2048) blocks = 2048;
-    hipLaunchKernelGGL(k_invariants, dim3(blocks), dim3(256), 0, st, model, n, L, w, x, y, s, acc);
+    hipLaunchKernelGGL(k_invariants_final, dim3(1), dim3(256), 0, st, partials, blocks, acc);
     return hipGetLastError();
 }
 

@@ -1,0 +1,353 @@
+// amber_device_common.h -- device helpers shared by the single-run kernels
+// (amber_device.hip) and the batched kernels (amber_batch.hip).
+#pragma once
+
+#include "amber_internal.h"
+
+namespace amber {
+
+// ------------------------------------------------------------------ Philox
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  Multipliers and Weyl
+// key increments as published.  The key lives in SGPRs (wavefront-uniform);
+// each 32x32->64 product is one v_mad_u64_u32.
+constexpr uint32_t PHILOX_M0 = 0xD2511F53u;
+constexpr uint32_t PHILOX_M1 = 0xCD9E8D57u;
+constexpr uint32_t PHILOX_W0 = 0x9E3779B9u;
+constexpr uint32_t PHILOX_W1 = 0xBB67AE85u;
+
+__device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2,
+                                        uint32_t k0, uint32_t k1)
+{
+    uint32_t c3 = 0;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)PHILOX_M0 * c0;
+        const uint64_t p1 = (uint64_t)PHILOX_M1 * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += PHILOX_W0;
+        k1 += PHILOX_W1;
+    }
+    return make_uint4(c0, c1, c2, c3);
+}
+
+// ------------------------------------------------------------------ mappings
+// Moore move from the top 3 bits of a word: index d selects (dx, dy) from the
+// 8 moves in lexicographic order without (0,0).  The tables hold dx+1 and
+// dy+1 as 2-bit fields at bit 2d.
+constexpr uint32_t MOVE_DX1 = (0u << 0) | (0u << 2) | (0u << 4) | (1u << 6) | (1u << 8) |
+                              (2u << 10) | (2u << 12) | (2u << 14);
+constexpr uint32_t MOVE_DY1 = (0u << 0) | (1u << 2) | (2u << 4) | (0u << 6) | (2u << 8) |
+                              (0u << 10) | (1u << 12) | (2u << 14);
+
+// Torus step of one coordinate in [0, L) by d in {-1, 0, 1}.
+__device__ __forceinline__ int32_t wrap_step(int32_t v, int32_t d, int32_t L)
+{
+    v += d;
+    v = (v < 0) ? v + L : v;
+    v = (v >= L) ? v - L : v;
+    return v;
+}
+
+__device__ __forceinline__ void moore_move(uint32_t u, int32_t L, int32_t &x, int32_t &y)
+{
+    const uint32_t sh = (u >> 28) & 14u;   // 2 * (u >> 29)
+    x = wrap_step(x, (int32_t)((MOVE_DX1 >> sh) & 3u) - 1, L);
+    y = wrap_step(y, (int32_t)((MOVE_DY1 >> sh) & 3u) - 1, L);
+}
+
+// floor(u * L / 2^32)
+__device__ __forceinline__ int32_t grid_coord(uint32_t u, int32_t L)
+{
+    return (int32_t)__umulhi(u, (uint32_t)L);
+}
+
+// floor((hi:lo) * n / 2^64) for n < 2^32.
+__device__ __forceinline__ uint32_t recipient(uint32_t hi, uint32_t lo, uint32_t n)
+{
+    const uint64_t lo_n = (uint64_t)lo * n;
+    const uint64_t mid = (uint64_t)hi * n + (lo_n >> 32);
+    return (uint32_t)(mid >> 32);
+}
+
+__host__ __device__ inline uint32_t div_up(uint32_t a, uint32_t b) { return (a + b - 1) / b; }
+__host__ __device__ inline uint32_t groups_of(uint32_t n) { return div_up(n, 4); }
+__host__ __device__ inline uint32_t padded_groups(uint32_t n) { return div_up(n, AGENT_PAD) * (AGENT_PAD / 4); }
+
+// ------------------------------------------------------------------ per-group bodies
+// Each body handles agent group q (agents 4q..4q+3) of one run.
+
+// Random walk: steps t0 .. t0+n_steps-1 with positions in registers.
+__device__ __forceinline__ void walk_group(int4 *__restrict__ x, int4 *__restrict__ y, uint32_t q,
+                                           int32_t L, uint32_t k0, uint32_t k1, uint32_t t0,
+                                           uint32_t n_steps)
+{
+    int4 X = x[q];
+    int4 Y = y[q];
+    for (uint32_t i = 0; i < n_steps; ++i) {
+        const uint4 r = philox(q, t0 + i, P_MOVE, k0, k1);
+        moore_move(r.x, L, X.x, Y.x);
+        moore_move(r.y, L, X.y, Y.y);
+        moore_move(r.z, L, X.z, Y.z);
+        moore_move(r.w, L, X.w, Y.w);
+    }
+    x[q] = X;
+    y[q] = Y;
+}
+
+// Wealth: one synchronous transfer step.  The state of agent a is base[a] +
+// inc_cur[a]; the snapshot decides the donors (wealth > 0).  A donor's unit
+// leaves base in place (plain store, the thread owns the row) and lands in
+// inc_nxt[recipient] through an integer atomic add, so duplicates accumulate
+// in any order with an identical result.  inc_cur is cleared for reuse two
+// steps later.
+__device__ __forceinline__ void wealth_step_group(int4 *__restrict__ base, int4 *__restrict__ inc_cur,
+                                                  int32_t *__restrict__ inc_nxt, uint32_t q,
+                                                  uint32_t n, uint32_t k0, uint32_t k1, uint32_t t)
+{
+    const int4 B = base[q];
+    const int4 I = inc_cur[q];
+    const int32_t v0 = B.x + I.x, v1 = B.y + I.y, v2 = B.z + I.z, v3 = B.w + I.w;
+    const uint32_t a = 4 * q;
+    const bool d0 = v0 > 0 && a + 0 < n;
+    const bool d1 = v1 > 0 && a + 1 < n;
+    const bool d2 = v2 > 0 && a + 2 < n;
+    const bool d3 = v3 > 0 && a + 3 < n;
+    base[q] = make_int4(v0 - d0, v1 - d1, v2 - d2, v3 - d3);
+    inc_cur[q] = make_int4(0, 0, 0, 0);
+    if (d0 | d1) {
+        const uint4 r = philox(2 * q, t, P_RECIPIENT, k0, k1);
+        if (d0) atomicAdd(&inc_nxt[recipient(r.x, r.y, n)], 1);
+        if (d1) atomicAdd(&inc_nxt[recipient(r.z, r.w, n)], 1);
+    }
+    if (d2 | d3) {
+        const uint4 r = philox(2 * q + 1, t, P_RECIPIENT, k0, k1);
+        if (d2) atomicAdd(&inc_nxt[recipient(r.x, r.y, n)], 1);
+        if (d3) atomicAdd(&inc_nxt[recipient(r.z, r.w, n)], 1);
+    }
+}
+
+__device__ __forceinline__ void wealth_fold_group(int4 *__restrict__ base, int4 *__restrict__ inc,
+                                                  uint32_t q)
+{
+    const int4 B = base[q];
+    const int4 I = inc[q];
+    base[q] = make_int4(B.x + I.x, B.y + I.y, B.z + I.z, B.w + I.w);
+    inc[q] = make_int4(0, 0, 0, 0);
+}
+
+// Small populations: one workgroup runs every step with the wealth column and
+// the increments in LDS; two barriers per step separate the donor/scatter
+// phase from the apply phase.  A thread owns agent pairs (one RECIPIENT
+// block per pair).
+constexpr uint32_t WEALTH_SMALL_THREADS = 1024;
+constexpr uint32_t WEALTH_SMALL_MAX = 8192;   // 2 x 32 KB of LDS
+
+__device__ __forceinline__ void wealth_small_run(int32_t *__restrict__ w, int32_t *sw, int32_t *sinc,
+                                                 uint32_t n, uint32_t k0, uint32_t k1, uint32_t t0,
+                                                 uint32_t n_steps)
+{
+    for (uint32_t a = threadIdx.x; a < n; a += blockDim.x) {
+        sw[a] = w[a];
+        sinc[a] = 0;
+    }
+    __syncthreads();
+    const uint32_t pairs = div_up(n, 2);
+    for (uint32_t i = 0; i < n_steps; ++i) {
+        const uint32_t t = t0 + i;
+        for (uint32_t p = threadIdx.x; p < pairs; p += blockDim.x) {
+            const uint32_t a = 2 * p;
+            const int32_t v0 = sw[a];
+            const int32_t v1 = (a + 1 < n) ? sw[a + 1] : 0;
+            const bool d0 = v0 > 0, d1 = v1 > 0;
+            if (d0 | d1) {
+                const uint4 r = philox(p, t, P_RECIPIENT, k0, k1);
+                if (d0) {
+                    sw[a] = v0 - 1;
+                    atomicAdd(&sinc[recipient(r.x, r.y, n)], 1);
+                }
+                if (d1) {
+                    sw[a + 1] = v1 - 1;
+                    atomicAdd(&sinc[recipient(r.z, r.w, n)], 1);
+                }
+            }
+        }
+        __syncthreads();
+        for (uint32_t a = threadIdx.x; a < n; a += blockDim.x) {
+            sw[a] += sinc[a];
+            sinc[a] = 0;
+        }
+        __syncthreads();
+    }
+    for (uint32_t a = threadIdx.x; a < n; a += blockDim.x) w[a] = sw[a];
+}
+
+// ------------------------------------------------------------------ SIR
+// Step t maps (positions, states) at the start of step t to the next state:
+//   move(t)       every agent moves by its MOVE word (the random-walk rule);
+//   bin(t)        C_t[c] = number of agents infected at the start of step t
+//                 whose post-move cell is c (integer atomic adds);
+//   transition(t) S -> I iff EPI word < T_inf[min(k, k_sat)] with k the infected
+//                 count of the distinct cells of the 3x3 torus block, I -> R iff
+//                 EPI word < T_rec, from C_t and the start-of-step state.
+// Three count grids rotate with t mod 3.  At every call boundary t (the
+// handle's step count) C[t%3] and C[(t+1)%3] are all zero; the third holds
+// garbage.  Every launch form below keeps that invariant, so forms may be
+// mixed between calls on one handle.
+//
+// Pipelined form (any N): "head" = move+bin(t0); "body"(t) = transition(t-1)
+// then move+bin(t), with the positions and states of its 4 agents held in
+// registers between the halves, so each column is read and written once per
+// step; "tail" = transition(t_last).  n steps cost n+1 launches.
+//
+// Persistent form (N up to what the chip holds in registers): one cooperative
+// launch; each thread keeps its agents' positions and states in registers for
+// every step, and one grid barrier per step separates bin(t) from
+// transition(t).  The columns are read once and written once per call.
+
+// Positions come from the caller's columns; a coordinate outside [0, L) (only
+// possible if the caller overwrote a column) is never used as an address.
+__device__ __forceinline__ bool on_grid(int32_t x, int32_t y, int32_t L)
+{
+    return (uint32_t)x < (uint32_t)L && (uint32_t)y < (uint32_t)L;
+}
+
+__device__ __forceinline__ void bin_infected(uint32_t *__restrict__ count, int32_t L, bool inf,
+                                             int32_t x, int32_t y)
+{
+    if (inf && on_grid(x, y, L)) atomicAdd(&count[(uint32_t)y * L + x], 1u);
+}
+
+__device__ __forceinline__ void sir_move4(const SirParams &p, uint32_t q, uint32_t t, int4 &X,
+                                          int4 &Y)
+{
+    const uint4 r = philox(q, t, P_MOVE, p.k0, p.k1);
+    moore_move(r.x, p.L, X.x, Y.x);
+    moore_move(r.y, p.L, X.y, Y.y);
+    moore_move(r.z, p.L, X.z, Y.z);
+    moore_move(r.w, p.L, X.w, Y.w);
+}
+
+// Bin the infected among agents 4q..4q+3 (state word S) at (X, Y).
+__device__ __forceinline__ void sir_bin4(const SirParams &p, uint32_t *__restrict__ count,
+                                         uint32_t q, uint32_t S, const int4 &X, const int4 &Y)
+{
+    const uint32_t a = 4 * q;
+    bin_infected(count, p.L, (S & 0xffu) == ST_I && a + 0 < p.n, X.x, Y.x);
+    bin_infected(count, p.L, ((S >> 8) & 0xffu) == ST_I && a + 1 < p.n, X.y, Y.y);
+    bin_infected(count, p.L, ((S >> 16) & 0xffu) == ST_I && a + 2 < p.n, X.z, Y.z);
+    bin_infected(count, p.L, (S >> 24) == ST_I && a + 3 < p.n, X.w, Y.w);
+}
+
+// Infected agents in the distinct cells of the 3x3 torus block around (cx, cy).
+__device__ __forceinline__ uint32_t block_count(const uint32_t *__restrict__ count, int32_t L,
+                                                int32_t cx, int32_t cy)
+{
+    if (!on_grid(cx, cy, L)) return 0;
+    if (L >= 3) {
+        const int32_t xm = cx == 0 ? L - 1 : cx - 1;
+        const int32_t xp = cx == L - 1 ? 0 : cx + 1;
+        const int32_t ym = cy == 0 ? L - 1 : cy - 1;
+        const int32_t yp = cy == L - 1 ? 0 : cy + 1;
+        const uint32_t *rm = count + (uint32_t)ym * L;
+        const uint32_t *r0 = count + (uint32_t)cy * L;
+        const uint32_t *rp = count + (uint32_t)yp * L;
+        return rm[xm] + rm[cx] + rm[xp] + r0[xm] + r0[cx] + r0[xp] + rp[xm] + rp[cx] + rp[xp];
+    }
+    // L = 1 or 2: the wrapped block covers each of the L*L cells exactly once.
+    uint32_t k = 0;
+    for (int32_t c = 0; c < L * L; ++c) k += count[c];
+    return k;
+}
+
+// transition(t) of agents 4q..4q+3: returns the new state word.
+__device__ __forceinline__ uint32_t sir_transition4(const SirParams &p,
+                                                    const uint32_t *__restrict__ count,
+                                                    uint32_t q, uint32_t t, uint32_t S,
+                                                    const int4 &X, const int4 &Y)
+{
+    const uint32_t a = 4 * q;
+    uint32_t st[4], k[4] = {0, 0, 0, 0};
+    bool any_sus = false, need = false;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        st[j] = (a + j < p.n) ? (S >> (8 * j)) & 0xffu : (uint32_t)ST_R;   // padding never changes
+        any_sus |= st[j] == ST_S;
+    }
+    if (any_sus) {
+        if (st[0] == ST_S) k[0] = block_count(count, p.L, X.x, Y.x);
+        if (st[1] == ST_S) k[1] = block_count(count, p.L, X.y, Y.y);
+        if (st[2] == ST_S) k[2] = block_count(count, p.L, X.z, Y.z);
+        if (st[3] == ST_S) k[3] = block_count(count, p.L, X.w, Y.w);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) need |= (st[j] == ST_S && k[j] > 0) || st[j] == ST_I;
+    if (!need) return S;
+    const uint4 r = philox(q, t, P_EPI, p.k0, p.k1);
+    const uint32_t u[4] = {r.x, r.y, r.z, r.w};
+    const uint32_t k_last = p.table_len - 1;
+    uint32_t out = S;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        uint32_t ns = st[j];
+        if (st[j] == ST_S && k[j] > 0) {
+            if (u[j] < p.t_inf[k[j] < k_last ? k[j] : k_last]) ns = ST_I;
+        } else if (st[j] == ST_I) {
+            if (u[j] < p.t_rec) ns = ST_R;
+        }
+        out = (out & ~(0xffu << (8 * j))) | (ns << (8 * j));
+    }
+    return out;
+}
+
+__device__ __forceinline__ void zero_quads(uint32_t *__restrict__ p, uint32_t quads, uint32_t i,
+                                           uint32_t stride)
+{
+    uint4 *p4 = (uint4 *)p;
+    for (; i < quads; i += stride) p4[i] = make_uint4(0, 0, 0, 0);
+}
+
+__device__ __forceinline__ uint32_t *grid_of(const SirParams &p, uint32_t t) { return p.count[t % 3]; }
+
+// head(t): move + bin(t) of group q.
+__device__ __forceinline__ void sir_head_group(const SirParams &p, uint32_t q, uint32_t t)
+{
+    int4 X = ((const int4 *)p.x)[q];
+    int4 Y = ((const int4 *)p.y)[q];
+    const uint32_t S = ((const uint32_t *)p.s)[q];
+    sir_move4(p, q, t, X, Y);
+    ((int4 *)p.x)[q] = X;
+    ((int4 *)p.y)[q] = Y;
+    sir_bin4(p, grid_of(p, t), q, S, X, Y);
+}
+
+// body(t): transition(t-1), then move + bin(t) of group q.  The caller clears
+// C[(t+1)%3].
+__device__ __forceinline__ void sir_body_group(const SirParams &p, uint32_t q, uint32_t t)
+{
+    int4 X = ((const int4 *)p.x)[q];
+    int4 Y = ((const int4 *)p.y)[q];
+    const uint32_t S = ((const uint32_t *)p.s)[q];
+    const uint32_t S2 = sir_transition4(p, grid_of(p, t - 1), q, t - 1, S, X, Y);
+    sir_move4(p, q, t, X, Y);
+    ((int4 *)p.x)[q] = X;
+    ((int4 *)p.y)[q] = Y;
+    if (S2 != S) ((uint32_t *)p.s)[q] = S2;
+    sir_bin4(p, grid_of(p, t), q, S2, X, Y);
+}
+
+// tail(t): transition(t) of group q.  The caller clears C[(t+2)%3].
+__device__ __forceinline__ void sir_tail_group(const SirParams &p, uint32_t q, uint32_t t)
+{
+    const int4 X = ((const int4 *)p.x)[q];
+    const int4 Y = ((const int4 *)p.y)[q];
+    const uint32_t S = ((const uint32_t *)p.s)[q];
+    const uint32_t S2 = sir_transition4(p, grid_of(p, t), q, t, S, X, Y);
+    if (S2 != S) ((uint32_t *)p.s)[q] = S2;
+}
+
+}  // namespace amber

@@ -194,6 +194,8 @@ uint32_t round_sqrt(uint32_t n)
 
 uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
 
+uint32_t groups_of_host(uint32_t n) { return (n + 3) / 4; }
+
 // Resolved, validated parameters of a run.
 struct Resolved {
     uint32_t model = 0, n = 0, L = 0, i0 = 0, seed = 0, stream = 0;
@@ -201,7 +203,7 @@ struct Resolved {
     uint32_t t_rec = 0;
     std::vector<uint32_t> t_inf;
     // workspace layout (byte offsets)
-    uint64_t off_inc0 = 0, off_inc1 = 0, off_table = 0, off_count0 = 0, off_count1 = 0;
+    uint64_t off_inc0 = 0, off_inc1 = 0, off_table = 0, off_count[3] = {0, 0, 0};
     uint64_t ws_bytes = 0;
 };
 
@@ -219,7 +221,7 @@ amber_status_t resolve(const amber_run_desc_t *d, Resolved &r, bool want_table)
     r.n = d->n_agents;
     r.seed = d->seed;
     r.stream = d->stream;
-    uint64_t ws = 256;   // invariants block
+    uint64_t ws = INV_REGION;   // invariants result + per-block partials
     if (d->model == AMBER_WEALTH) {
         if (d->wealth_init < 0) return fail(AMBER_E_INVALID, "wealth_init must be >= 0");
         if ((uint64_t)d->n_agents * (uint64_t)d->wealth_init > 0x7fffffffull)
@@ -252,10 +254,10 @@ amber_status_t resolve(const amber_run_desc_t *d, Resolved &r, bool want_table)
             const uint64_t cells = align_up((uint64_t)L * L, AGENT_PAD) * 4;
             r.off_table = ws;
             ws += align_up((uint64_t)AMBER_MAX_TABLE * 4, 256);
-            r.off_count0 = ws;
-            ws += align_up(cells, 256);
-            r.off_count1 = ws;
-            ws += align_up(cells, 256);
+            for (int b = 0; b < 3; ++b) {
+                r.off_count[b] = ws;
+                ws += align_up(cells, 256);
+            }
         }
     }
     r.ws_bytes = ws;
@@ -278,6 +280,48 @@ size_t column_bytes(const Resolved &r, amber_col_t c)
 
 // ------------------------------------------------------------------ handle
 
+// Optional per-kernel timing: HIP events recorded on the handle's stream
+// around every kernel the handle enqueues.
+struct KernelTimer {
+    bool on = false;
+    struct Pending {
+        uint32_t kernel;
+        hipEvent_t start, stop;
+    };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> pool;
+    std::vector<std::string> names;
+    std::vector<uint64_t> launches;
+    std::vector<double> total_ms;
+
+    uint32_t id(const char *name)
+    {
+        for (uint32_t i = 0; i < names.size(); ++i)
+            if (names[i] == name) return i;
+        names.emplace_back(name);
+        launches.push_back(0);
+        total_ms.push_back(0.0);
+        return (uint32_t)names.size() - 1;
+    }
+    hipError_t event(hipEvent_t *e)
+    {
+        if (!pool.empty()) {
+            *e = pool.back();
+            pool.pop_back();
+            return hipSuccess;
+        }
+        return hipEventCreate(e);
+    }
+    ~KernelTimer()
+    {
+        for (auto &p : pending) {
+            (void)hipEventDestroy(p.start);
+            (void)hipEventDestroy(p.stop);
+        }
+        for (auto e : pool) (void)hipEventDestroy(e);
+    }
+};
+
 struct amber_pop {
     Resolved r;
     amber_buffers_t b{};
@@ -286,6 +330,8 @@ struct amber_pop {
     uint64_t step = 0;
     amber::Tuning tuning;
     DevInvariants *acc = nullptr;      // inside the workspace
+    KernelTimer timer;
+    uint32_t persist_g = 0, persist_blocks = 0;   // SIR persistent form fit (0 = none)
 };
 
 namespace {
@@ -316,49 +362,220 @@ amber_status_t check_device_ptr(const void *p, int device, const char *what, siz
     return AMBER_OK;
 }
 
+// Launch one kernel through f(), bracketed by timing events when enabled.
+template <class F>
+hipError_t timed(amber_pop *p, const char *name, F &&f)
+{
+    KernelTimer &tm = p->timer;
+    if (!tm.on) return f();
+    hipEvent_t a, b;
+    hipError_t e = tm.event(&a);
+    if (e != hipSuccess) return e;
+    if ((e = tm.event(&b)) != hipSuccess) return e;
+    if ((e = hipEventRecord(a, p->stream)) != hipSuccess) return e;
+    if ((e = f()) != hipSuccess) return e;
+    if ((e = hipEventRecord(b, p->stream)) != hipSuccess) return e;
+    tm.pending.push_back({tm.id(name), a, b});
+    return hipSuccess;
+}
+
 int32_t *col_i32(amber_pop *p, amber_col_t c) { return (int32_t *)p->b.col[c]; }
 uint8_t *ws_ptr(amber_pop *p, uint64_t off) { return (uint8_t *)p->b.workspace + off; }
+
+SirParams sir_params(amber_pop *p)
+{
+    const Resolved &r = p->r;
+    SirParams sp{};
+    sp.x = col_i32(p, AMBER_COL_X);
+    sp.y = col_i32(p, AMBER_COL_Y);
+    sp.s = (uint8_t *)p->b.col[AMBER_COL_STATE];
+    for (int b = 0; b < 3; ++b) sp.count[b] = (uint32_t *)ws_ptr(p, r.off_count[b]);
+    sp.t_inf = (const uint32_t *)ws_ptr(p, r.off_table);
+    sp.table_len = (uint32_t)r.t_inf.size();
+    sp.t_rec = r.t_rec;
+    sp.n = r.n;
+    sp.L = (int32_t)r.L;
+    sp.k0 = r.seed;
+    sp.k1 = r.stream;
+    return sp;
+}
 
 amber_status_t enqueue_steps(amber_pop *p, uint32_t n_steps)
 {
     const Resolved &r = p->r;
     const uint32_t t0 = (uint32_t)p->step;
     hipStream_t st = p->stream;
+    const Tuning &tu = p->tuning;
     if (r.model == AMBER_RANDOM_WALK) {
-        HIP_TRY(launch_walk(col_i32(p, AMBER_COL_X), col_i32(p, AMBER_COL_Y), r.n, (int32_t)r.L,
-                            r.seed, r.stream, t0, n_steps, p->tuning, st),
+        int32_t *x = col_i32(p, AMBER_COL_X), *y = col_i32(p, AMBER_COL_Y);
+        HIP_TRY(timed(p, "walk", [&] {
+                    return launch_walk(x, y, r.n, (int32_t)r.L, r.seed, r.stream, t0, n_steps, tu,
+                                       st);
+                }),
                 "walk kernel");
     } else if (r.model == AMBER_WEALTH) {
         int32_t *w = col_i32(p, AMBER_COL_WEALTH);
         if (r.n <= wealth_small_max_agents()) {
-            HIP_TRY(launch_wealth_small(w, r.n, r.seed, r.stream, t0, n_steps, st),
+            HIP_TRY(timed(p, "wealth_small", [&] {
+                        return launch_wealth_small(w, r.n, r.seed, r.stream, t0, n_steps, st);
+                    }),
                     "wealth small kernel");
         } else {
             int32_t *inc[2] = {(int32_t *)ws_ptr(p, r.off_inc0), (int32_t *)ws_ptr(p, r.off_inc1)};
             for (uint32_t i = 0; i < n_steps; ++i)
-                HIP_TRY(launch_wealth_step(w, inc[i & 1], inc[(i + 1) & 1], r.n, r.seed, r.stream,
-                                           t0 + i, p->tuning, st),
+                HIP_TRY(timed(p, "wealth_step", [&] {
+                            return launch_wealth_step(w, inc[i & 1], inc[(i + 1) & 1], r.n, r.seed,
+                                                      r.stream, t0 + i, tu, st);
+                        }),
                         "wealth step kernel");
-            HIP_TRY(launch_wealth_fold(w, inc[n_steps & 1], r.n, st), "wealth fold kernel");
+            HIP_TRY(timed(p, "wealth_fold",
+                          [&] { return launch_wealth_fold(w, inc[n_steps & 1], r.n, st); }),
+                    "wealth fold kernel");
         }
     } else {
-        SirParams sp;
-        sp.x = col_i32(p, AMBER_COL_X);
-        sp.y = col_i32(p, AMBER_COL_Y);
-        sp.s = (uint8_t *)p->b.col[AMBER_COL_STATE];
-        sp.count[0] = (uint32_t *)ws_ptr(p, r.off_count0);
-        sp.count[1] = (uint32_t *)ws_ptr(p, r.off_count1);
-        sp.t_inf = (const uint32_t *)ws_ptr(p, r.off_table);
-        sp.table_len = (uint32_t)r.t_inf.size();
-        sp.t_rec = r.t_rec;
-        sp.n = r.n;
-        sp.L = (int32_t)r.L;
-        sp.k0 = r.seed;
-        sp.k1 = r.stream;
-        for (uint32_t i = 0; i < n_steps; ++i)
-            HIP_TRY(launch_sir_step(sp, t0 + i, p->tuning, st), "sir step kernels");
+        SirParams sp = sir_params(p);
+        // Automatic choice: the pipelined form.  The persistent form keeps the
+        // state in registers but pays a device-wide barrier per step, which on
+        // gfx950 costs more than the launch it saves; it runs only on request.
+        uint32_t g = 0, blocks = 0;
+        if (tu.sir_form == 2) {
+            if (tu.max_g >= 8) {
+                g = p->persist_g;
+                blocks = p->persist_blocks;
+            } else {
+                g = sir_persistent_groups_per_thread(r.n, tu.max_g, &blocks);
+            }
+            if (g == 0)
+                return fail(AMBER_E_UNSUPPORTED,
+                            "the persistent SIR form does not fit %u agents on this device", r.n);
+        }
+        if (g) {
+            HIP_TRY(timed(p, "sir_persistent",
+                          [&] { return launch_sir_persistent(sp, t0, n_steps, g, blocks, st); }),
+                    "sir persistent kernel");
+        } else {
+            HIP_TRY(timed(p, "sir_head", [&] { return launch_sir_head(sp, t0, tu, st); }),
+                    "sir head kernel");
+            for (uint32_t i = 1; i < n_steps; ++i)
+                HIP_TRY(timed(p, "sir_body", [&] { return launch_sir_body(sp, t0 + i, tu, st); }),
+                        "sir body kernel");
+            HIP_TRY(timed(p, "sir_tail",
+                          [&] { return launch_sir_tail(sp, t0 + n_steps - 1, tu, st); }),
+                    "sir tail kernel");
+        }
     }
     return AMBER_OK;
+}
+
+// Join the streams of the batch's handles onto the first handle's stream
+// (before) or the first stream onto the others (after).
+amber_status_t join_streams(amber_pop *const *pops, uint32_t n, bool before)
+{
+    hipStream_t main = pops[0]->stream;
+    std::vector<hipStream_t> others;
+    for (uint32_t i = 1; i < n; ++i)
+        if (pops[i]->stream != main &&
+            std::find(others.begin(), others.end(), pops[i]->stream) == others.end())
+            others.push_back(pops[i]->stream);
+    for (hipStream_t o : others) {
+        hipEvent_t ev;
+        HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "hipEventCreate");
+        hipError_t e = hipEventRecord(ev, before ? o : main);
+        if (e == hipSuccess) e = hipStreamWaitEvent(before ? main : o, ev, 0);
+        (void)hipEventDestroy(ev);
+        if (e != hipSuccess) return hip_fail(e, "stream join");
+    }
+    return AMBER_OK;
+}
+
+amber_status_t run_batch(amber_pop *const *pops, uint32_t n, uint32_t n_steps)
+{
+    amber_pop *lead = pops[0];
+    hipStream_t st = lead->stream;
+    const uint32_t block = lead->tuning.block;
+    amber_status_t rc = join_streams(pops, n, true);
+    if (rc != AMBER_OK) return rc;
+
+    std::vector<amber_pop *> walk, wealth_small, wealth_big, sir;
+    for (uint32_t i = 0; i < n; ++i) {
+        amber_pop *p = pops[i];
+        if (p->r.model == AMBER_RANDOM_WALK) walk.push_back(p);
+        else if (p->r.model == AMBER_SIR) sir.push_back(p);
+        else if (p->r.n <= wealth_small_max_agents()) wealth_small.push_back(p);
+        else wealth_big.push_back(p);
+    }
+    auto blocks_for = [&](uint32_t agents) { return (groups_of_host(agents) + block - 1) / block; };
+
+    for (size_t c = 0; c < walk.size(); c += BATCH_RUNS) {
+        WalkBatch b{};
+        uint32_t blocks = 0;
+        for (size_t k = c; k < walk.size() && k < c + BATCH_RUNS; ++k) {
+            amber_pop *p = walk[k];
+            const uint32_t j = b.nruns++;
+            b.x[j] = col_i32(p, AMBER_COL_X);
+            b.y[j] = col_i32(p, AMBER_COL_Y);
+            b.n[j] = p->r.n;
+            b.L[j] = (int32_t)p->r.L;
+            b.k0[j] = p->r.seed;
+            b.k1[j] = p->r.stream;
+            b.t0[j] = (uint32_t)p->step;
+            blocks += blocks_for(p->r.n);
+            b.block_end[j] = blocks;
+        }
+        HIP_TRY(timed(lead, "walk_batch", [&] { return launch_walk_batch(b, n_steps, block, st); }),
+                "walk batch kernel");
+    }
+    for (size_t c = 0; c < wealth_small.size(); c += BATCH_SMALL_RUNS) {
+        WealthSmallBatch b{};
+        for (size_t k = c; k < wealth_small.size() && k < c + BATCH_SMALL_RUNS; ++k) {
+            amber_pop *p = wealth_small[k];
+            const uint32_t j = b.nruns++;
+            b.w[j] = col_i32(p, AMBER_COL_WEALTH);
+            b.n[j] = p->r.n;
+            b.k0[j] = p->r.seed;
+            b.k1[j] = p->r.stream;
+            b.t0[j] = (uint32_t)p->step;
+        }
+        HIP_TRY(timed(lead, "wealth_small_batch",
+                      [&] { return launch_wealth_small_batch(b, n_steps, st); }),
+                "wealth small batch kernel");
+    }
+    for (size_t c = 0; c < wealth_big.size(); c += BATCH_RUNS) {
+        WealthBatch b{};
+        uint32_t blocks = 0;
+        for (size_t k = c; k < wealth_big.size() && k < c + BATCH_RUNS; ++k) {
+            amber_pop *p = wealth_big[k];
+            const uint32_t j = b.nruns++;
+            b.base[j] = col_i32(p, AMBER_COL_WEALTH);
+            b.inc[0][j] = (int32_t *)ws_ptr(p, p->r.off_inc0);
+            b.inc[1][j] = (int32_t *)ws_ptr(p, p->r.off_inc1);
+            b.n[j] = p->r.n;
+            b.k0[j] = p->r.seed;
+            b.k1[j] = p->r.stream;
+            b.t0[j] = (uint32_t)p->step;
+            blocks += blocks_for(p->r.n);
+            b.block_end[j] = blocks;
+        }
+        HIP_TRY(timed(lead, "wealth_batch",
+                      [&] { return launch_wealth_batch(b, n_steps, block, st); }),
+                "wealth batch kernels");
+    }
+    for (size_t c = 0; c < sir.size(); c += BATCH_RUNS) {
+        SirBatch b{};
+        uint32_t blocks = 0;
+        for (size_t k = c; k < sir.size() && k < c + BATCH_RUNS; ++k) {
+            amber_pop *p = sir[k];
+            const uint32_t j = b.nruns++;
+            b.run[j] = sir_params(p);
+            sir_fill(b.run[j]);
+            b.t0[j] = (uint32_t)p->step;
+            blocks += blocks_for(p->r.n);
+            b.block_end[j] = blocks;
+        }
+        HIP_TRY(timed(lead, "sir_batch", [&] { return launch_sir_batch(b, n_steps, block, st); }),
+                "sir batch kernels");
+    }
+    return join_streams(pops, n, false);
 }
 
 }  // namespace
@@ -448,10 +665,12 @@ amber_status_t amber_init_population(const amber_run_desc_t *desc, const amber_b
                                   (int32_t)rr.L, rr.seed, rr.stream, p->stream);
         if (e == hipSuccess && rr.model == AMBER_SIR) {
             e = launch_init_states((uint8_t *)p->b.col[AMBER_COL_STATE], rr.n, rr.i0, p->stream);
-            const uint64_t cell_words = (rr.off_count1 - rr.off_count0) / 4;
+            const uint64_t cell_words = (rr.off_count[1] - rr.off_count[0]) / 4;
             if (e == hipSuccess)
-                e = launch_zero_words((uint32_t *)ws_ptr(p, rr.off_count0), 2 * cell_words,
+                e = launch_zero_words((uint32_t *)ws_ptr(p, rr.off_count[0]), 3 * cell_words,
                                       p->stream);
+            if (e == hipSuccess)
+                p->persist_g = sir_persistent_groups_per_thread(rr.n, 8, &p->persist_blocks);
             if (e == hipSuccess)
                 e = hipMemcpyAsync(ws_ptr(p, rr.off_table), rr.t_inf.data(),
                                    rr.t_inf.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
@@ -493,10 +712,10 @@ amber_status_t amber_step_batch(amber_pop_t *const *pops, uint32_t n, uint32_t n
         if (pops[i]->step + n_steps > 0xffffffffull)
             return fail(AMBER_E_INVALID, "step index would exceed 2^32-1");
     }
-    for (uint32_t i = 0; i < n; ++i) {
-        amber_status_t st = amber_step(pops[i], n_steps);
-        if (st != AMBER_OK) return st;
-    }
+    if (n == 0 || n_steps == 0) return AMBER_OK;
+    amber_status_t st = run_batch(pops, n, n_steps);
+    if (st != AMBER_OK) return st;
+    for (uint32_t i = 0; i < n; ++i) pops[i]->step += n_steps;
     return AMBER_OK;
 }
 
@@ -529,7 +748,8 @@ amber_status_t amber_invariants(amber_pop_t *pop, amber_invariants_t *out)
     const Resolved &r = pop->r;
     HIP_TRY(launch_invariants(r.model, r.n, (int32_t)r.L, col_i32(pop, AMBER_COL_WEALTH),
                               col_i32(pop, AMBER_COL_X), col_i32(pop, AMBER_COL_Y),
-                              (const uint8_t *)pop->b.col[AMBER_COL_STATE], pop->acc, pop->stream),
+                              (const uint8_t *)pop->b.col[AMBER_COL_STATE], pop->acc,
+                              (DevInvariants *)ws_ptr(pop, INV_PARTIALS_OFFSET), pop->stream),
             "invariants kernel");
     DevInvariants h;
     HIP_TRY(hipMemcpyAsync(&h, pop->acc, sizeof h, hipMemcpyDeviceToHost, pop->stream),
@@ -565,6 +785,78 @@ amber_status_t amber_pop_info(const amber_pop_t *pop, amber_pop_info_t *out)
     out->table_len = (uint32_t)r.t_inf.size();
     out->t_rec = r.t_rec;
     out->step = pop->step;
+    return AMBER_OK;
+}
+
+amber_status_t amber_set_tuning(amber_pop_t *pop, const amber_tuning_t *t)
+{
+    if (!is_live(pop)) return fail(AMBER_E_STATE, "unknown or released handle");
+    if (!t) return fail(AMBER_E_INVALID, "tuning is NULL");
+    if (t->block < 64 || t->block > 1024 || t->block % 64)
+        return fail(AMBER_E_INVALID, "block must be a multiple of 64 in [64, 1024]");
+    if (t->sir_form > 2) return fail(AMBER_E_INVALID, "sir_form must be 0, 1 or 2");
+    if (t->max_groups_per_thread != 0 && t->max_groups_per_thread != 1 &&
+        t->max_groups_per_thread != 2 && t->max_groups_per_thread != 4 &&
+        t->max_groups_per_thread != 8)
+        return fail(AMBER_E_INVALID, "max_groups_per_thread must be 0, 1, 2, 4 or 8");
+    pop->tuning.block = t->block;
+    pop->tuning.sir_form = t->sir_form;
+    pop->tuning.max_g = t->max_groups_per_thread ? t->max_groups_per_thread : 8;
+    return AMBER_OK;
+}
+
+amber_status_t amber_get_tuning(const amber_pop_t *pop, amber_tuning_t *t)
+{
+    if (!is_live(pop)) return fail(AMBER_E_STATE, "unknown or released handle");
+    if (!t) return fail(AMBER_E_INVALID, "tuning is NULL");
+    std::memset(t, 0, sizeof *t);
+    t->block = pop->tuning.block;
+    t->sir_form = pop->tuning.sir_form;
+    t->max_groups_per_thread = pop->tuning.max_g;
+    return AMBER_OK;
+}
+
+amber_status_t amber_profile_enable(amber_pop_t *pop, int enable)
+{
+    if (!is_live(pop)) return fail(AMBER_E_STATE, "unknown or released handle");
+    KernelTimer &tm = pop->timer;
+    if (enable && !tm.on) {
+        HIP_TRY(hipStreamSynchronize(pop->stream), "stream synchronize");
+        for (auto &p : tm.pending) {
+            tm.pool.push_back(p.start);
+            tm.pool.push_back(p.stop);
+        }
+        tm.pending.clear();
+        std::fill(tm.launches.begin(), tm.launches.end(), 0);
+        std::fill(tm.total_ms.begin(), tm.total_ms.end(), 0.0);
+    }
+    tm.on = enable != 0;
+    return AMBER_OK;
+}
+
+amber_status_t amber_profile_read(amber_pop_t *pop, amber_kernel_time_t *out, uint32_t cap,
+                                  uint32_t *count)
+{
+    if (!is_live(pop)) return fail(AMBER_E_STATE, "unknown or released handle");
+    if (!count || (cap && !out)) return fail(AMBER_E_INVALID, "out/count is NULL");
+    KernelTimer &tm = pop->timer;
+    HIP_TRY(hipStreamSynchronize(pop->stream), "stream synchronize");
+    for (auto &p : tm.pending) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, p.start, p.stop), "hipEventElapsedTime");
+        tm.launches[p.kernel] += 1;
+        tm.total_ms[p.kernel] += ms;
+        tm.pool.push_back(p.start);
+        tm.pool.push_back(p.stop);
+    }
+    tm.pending.clear();
+    *count = (uint32_t)tm.names.size();
+    for (uint32_t i = 0; i < tm.names.size() && i < cap; ++i) {
+        std::memset(&out[i], 0, sizeof out[i]);
+        std::snprintf(out[i].name, sizeof out[i].name, "%s", tm.names[i].c_str());
+        out[i].launches = tm.launches[i];
+        out[i].total_ms = tm.total_ms[i];
+    }
     return AMBER_OK;
 }
 

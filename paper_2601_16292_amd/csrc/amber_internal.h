@@ -25,25 +25,35 @@ struct DevInvariants {
     int wealth_min;
     int pad[3];
 };
-static_assert(sizeof(DevInvariants) <= 256, "invariants block must fit 256 B");
+static_assert(sizeof(DevInvariants) <= 64, "invariants block must fit 64 B");
 
-// Per-run parameters of a SIR step, passed by value.
+// Workspace head: the reduced invariants at offset 0, then up to
+// INV_MAX_BLOCKS per-workgroup partials.
+constexpr uint32_t INV_MAX_BLOCKS = 1024;
+constexpr uint64_t INV_PARTIALS_OFFSET = 256;
+constexpr uint64_t INV_REGION = INV_PARTIALS_OFFSET + 64ull * INV_MAX_BLOCKS;
+
+// Per-run parameters of a SIR step, passed by value as a kernel argument.
 struct SirParams {
     int32_t *x;
     int32_t *y;
     uint8_t *s;
-    uint32_t *count[2];        // per-cell infected counts, double buffered by step parity
+    uint32_t *count[3];        // per-cell infected counts, rotating with step mod 3
     const uint32_t *t_inf;     // infection thresholds, table_len entries
     uint32_t table_len;        // k_sat + 1
     uint32_t t_rec;
     uint32_t n;
     int32_t L;
     uint32_t k0, k1;           // Philox key (seed, stream)
+    uint32_t groups;           // ceil(n / 4), filled by the launcher
+    uint32_t quads;            // ceil(L*L / 4), filled by the launcher
 };
 
 // Launch configuration knobs (results never depend on them).
 struct Tuning {
     uint32_t block = 256;      // threads per workgroup (multiple of 64, <= 1024)
+    uint32_t sir_form = 0;     // 0 = automatic, 1 = pipelined, 2 = persistent
+    uint32_t max_g = 8;        // persistent form: largest groups-per-thread to try
 };
 
 hipError_t launch_init_wealth(int32_t *w, int32_t *inc0, int32_t *inc1, uint32_t n,
@@ -71,12 +81,69 @@ hipError_t launch_wealth_small(int32_t *w, uint32_t n, uint32_t k0, uint32_t k1,
                                uint32_t t0, uint32_t n_steps, hipStream_t st);
 uint32_t wealth_small_max_agents();
 
-// SIR: one step t (move + bin into count[t&1]; then transition, which also
-// clears count[(t+1)&1] for the next step).
-hipError_t launch_sir_step(const SirParams &p, uint32_t t, const Tuning &tu, hipStream_t st);
+// SIR, pipelined form: head = move+bin(t); body = transition(t-1) + move+bin(t);
+// tail = transition(t).  n steps from t0: head(t0), body(t0+1..t0+n-1), tail(t0+n-1).
+hipError_t launch_sir_head(SirParams p, uint32_t t, const Tuning &tu, hipStream_t st);
+hipError_t launch_sir_body(SirParams p, uint32_t t, const Tuning &tu, hipStream_t st);
+hipError_t launch_sir_tail(SirParams p, uint32_t t, const Tuning &tu, hipStream_t st);
+// SIR, persistent form: all n steps in one cooperative launch.  Returns the
+// groups-per-thread G (1, 2, 4 or 8, at most max_g) and the workgroup count
+// for n agents, or 0 when the population does not fit co-resident.
+uint32_t sir_persistent_groups_per_thread(uint32_t n, uint32_t max_g, uint32_t *blocks);
+hipError_t launch_sir_persistent(SirParams p, uint32_t t0, uint32_t n_steps, uint32_t g,
+                                 uint32_t blocks, hipStream_t st);
 
+// ------------------------------------------------------------------ batches
+// Run tables of the batched launches, passed by value as kernel arguments.
+// run r owns workgroups [block_end[r-1], block_end[r]).
+constexpr uint32_t BATCH_RUNS = 16;          // runs per launch (per-step kernels)
+constexpr uint32_t BATCH_SMALL_RUNS = 48;    // runs per launch (one workgroup per run)
+
+struct WalkBatch {
+    int32_t *x[BATCH_RUNS];
+    int32_t *y[BATCH_RUNS];
+    uint32_t n[BATCH_RUNS], k0[BATCH_RUNS], k1[BATCH_RUNS], t0[BATCH_RUNS];
+    int32_t L[BATCH_RUNS];
+    uint32_t block_end[BATCH_RUNS];
+    uint32_t nruns;
+};
+
+struct WealthSmallBatch {
+    int32_t *w[BATCH_SMALL_RUNS];
+    uint32_t n[BATCH_SMALL_RUNS], k0[BATCH_SMALL_RUNS], k1[BATCH_SMALL_RUNS], t0[BATCH_SMALL_RUNS];
+    uint32_t nruns;
+};
+
+struct WealthBatch {
+    int32_t *base[BATCH_RUNS];
+    int32_t *inc[2][BATCH_RUNS];
+    uint32_t n[BATCH_RUNS], k0[BATCH_RUNS], k1[BATCH_RUNS], t0[BATCH_RUNS];
+    uint32_t block_end[BATCH_RUNS];
+    uint32_t nruns;
+};
+
+struct SirBatch {
+    SirParams run[BATCH_RUNS];   // groups and quads filled in
+    uint32_t t0[BATCH_RUNS];
+    uint32_t block_end[BATCH_RUNS];
+    uint32_t nruns;
+};
+
+// Random walk: every step of the call, one launch for the chunk.
+hipError_t launch_walk_batch(const WalkBatch &b, uint32_t n_steps, uint32_t block, hipStream_t st);
+// Wealth, runs of at most wealth_small_max_agents(): one launch for the chunk.
+hipError_t launch_wealth_small_batch(const WealthSmallBatch &b, uint32_t n_steps, hipStream_t st);
+// Wealth, larger runs: one launch per step for the chunk, then one fold.
+hipError_t launch_wealth_batch(const WealthBatch &b, uint32_t n_steps, uint32_t block,
+                               hipStream_t st);
+// SIR, pipelined: head, n_steps-1 bodies and a tail, each one launch for the chunk.
+hipError_t launch_sir_batch(const SirBatch &b, uint32_t n_steps, uint32_t block, hipStream_t st);
+void sir_fill(SirParams &p);
+
+// Two-stage reduction: per-workgroup partials, then one workgroup folds them
+// into *acc.  No atomics, so the result does not depend on timing.
 hipError_t launch_invariants(uint32_t model, uint32_t n, int32_t L, const int32_t *w,
                              const int32_t *x, const int32_t *y, const uint8_t *s,
-                             DevInvariants *acc, hipStream_t st);
+                             DevInvariants *acc, DevInvariants *partials, hipStream_t st);
 
 }  // namespace amber

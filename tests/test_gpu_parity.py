@@ -183,12 +183,14 @@ def test_full_walk_1m(A, O, golden):
     assert np.array_equal(x[more], ox) and np.array_equal(y[more], oy)
 
 
-def test_full_sir_1m(A, golden):
+@pytest.mark.parametrize("form", [1, 2])
+def test_full_sir_1m(A, golden, form):
     g = golden["sir_1m"]
     c = g["config"]
-    say("case full SIR N=1e6 L=1000 x 500")
+    say(f"case full SIR N=1e6 L=1000 x 500 form={form}")
     pop = A.Population(A.SIR, c["n"], L=c["L"], seed=c["seed"], stream_id=c["stream"],
                        beta=tuple(c["beta"]), gamma=tuple(c["gamma"]))
+    pop.tune(sir_form=form)
     done = 0
     for t in sorted(int(k) for k in g["checkpoints"]):
         pop.step(t - done)
@@ -227,3 +229,66 @@ def test_device_validation(A):
     assert A.amber_release(h) == A.OK
     assert A.amber_release(h) == A.E_STATE
     assert A.amber_step(h, 1) == A.E_STATE
+
+
+# ------------------------------------------------------------------ launch shapes
+
+def _sir_tuned(A, n, L, steps, chunks, tunings, seed=2, stream=6, beta=(1, 10), gamma=(1, 30)):
+    pop = A.Population(A.SIR, n, L=L, seed=seed, stream_id=stream, beta=beta, gamma=gamma)
+    for c, tu in zip(chunks, tunings):
+        pop.tune(**tu)
+        pop.step(c)
+    got = pop.read()
+    inv = pop.invariants()
+    pop.release()
+    return got, inv
+
+
+SIR_FORMS = [dict(sir_form=1), dict(sir_form=1, block=64), dict(sir_form=1, block=1024),
+             dict(sir_form=2, max_groups_per_thread=1), dict(sir_form=2, max_groups_per_thread=2),
+             dict(sir_form=2, max_groups_per_thread=8), dict(sir_form=0)]
+
+
+@pytest.mark.parametrize("n,L", [(1, 1), (7, 2), (4097, 64), (70001, 265)])
+@pytest.mark.parametrize("tu", SIR_FORMS)
+def test_sir_launch_forms_match_oracle(A, O, n, L, tu):
+    say(f"case sir form {tu} n={n} L={L}")
+    got, inv = _sir_tuned(A, n, L, 23, [23], [tu])
+    ref = O.OracleRun(O.SIR, n, L, seed=2, stream=6, beta=(1, 10), gamma=(1, 30)).step(23)
+    assert_same(got, inv, ref, 23)
+
+
+def test_sir_forms_mixed_across_calls(A, O):
+    n, L = 50000, 223
+    chunks = [1, 5, 1, 7, 2, 1, 9]
+    tunings = [dict(sir_form=2), dict(sir_form=1), dict(sir_form=1), dict(sir_form=2),
+               dict(sir_form=1, block=128), dict(sir_form=2, max_groups_per_thread=4),
+               dict(sir_form=0)]
+    say("case sir mixed forms")
+    got, inv = _sir_tuned(A, n, L, sum(chunks), chunks, tunings)
+    ref = O.OracleRun(O.SIR, n, L, seed=2, stream=6, beta=(1, 10), gamma=(1, 30)).step(sum(chunks))
+    assert_same(got, inv, ref, sum(chunks))
+
+
+@pytest.mark.parametrize("model,n", [(0, 30001), (1, 30001)])
+@pytest.mark.parametrize("block", [64, 192, 1024])
+def test_block_size_invariance(A, O, model, n, block):
+    say(f"case block={block} model={model}")
+    pop = A.Population(model, n, L=97, seed=1, stream_id=3)
+    pop.tune(block=block)
+    pop.step(13)
+    got, inv = pop.read(), pop.invariants()
+    pop.release()
+    ref = O.OracleRun(model, n, 97, seed=1, stream=3).step(13)
+    assert_same(got, inv, ref, 13)
+
+
+def test_tuning_validation(A):
+    pop = A.Population(A.RANDOM_WALK, 100, L=10)
+    for bad in [dict(block=32), dict(block=1088), dict(block=100), dict(sir_form=3),
+                dict(max_groups_per_thread=3)]:
+        with pytest.raises(A.AmberError):
+            pop.tune(**bad)
+    st, t = A.amber_get_tuning(pop.handle)
+    assert st == A.OK and t.block == 256
+    pop.release()
