@@ -76,14 +76,14 @@ def timed_steps(torch, pop, steps, chunk):
     return max(wall, ev0.elapsed_time(ev1) / 1e3)
 
 
-def sir_bench(torch, A, W, K, chunk, form):
+def sir_bench(torch, A, W, K, chunk, form, count=0):
     from paper_2601_16292_amd import workloads as WL
     c = WL.SIR_1M
 
     def mk():
         p = A.Population(A.SIR, c["n"], L=c["L"], seed=c["seed"], stream_id=c["stream"],
                          beta=c["beta"], gamma=c["gamma"])
-        p.tune(sir_form=form)
+        p.tune(sir_form=form, sir_count=count)
         return p
 
     pop = mk()
@@ -192,6 +192,87 @@ def cpu_baseline(budget_s):
             "host_cpus": os.cpu_count()}
 
 
+def roofline_big(torch, A, log2n):
+    """Per-step kernels at an out-of-cache size (columns far above the 256 MB
+    last-level cache): average launch time from HIP events on the library's
+    stream, algorithmic bytes per launch, achieved GB/s against HBM peak."""
+    n = 1 << log2n
+    res = {"n_agents": n}
+
+    def priced(name, times, bytes_per_launch):
+        launches, total_ms = times[name]
+        avg = total_ms / launches / 1e3
+        gbs = bytes_per_launch / avg / 1e9
+        return {"kernel": name, "launches": launches, "avg_launch_us": round(avg * 1e6, 2),
+                "algorithmic_bytes_per_launch": int(bytes_per_launch),
+                "achieved_GBs": round(gbs, 1), "frac_of_hbm_peak": round(gbs / PEAK_HBM_GBS, 4)}
+
+    # random walk, one step per launch (16 B per agent-step)
+    pop = A.Population(A.RANDOM_WALK, n, L=1000)
+    pop.step(1)
+    pop.profile(True)
+    for _ in range(8):
+        pop.step(1)
+    res["walk_step"] = priced("walk", pop.kernel_times(), 16 * n)
+    pop.release()
+    torch.cuda.empty_cache()
+
+    # wealth: 8 B per agent + 8 B per donor
+    pop = A.Population(A.WEALTH, n, wealth_init=1)
+    pop.step(2)
+    (w,) = pop.read()
+    donors = int((w > 0).sum())
+    del w
+    pop.profile(True)
+    pop.step(1)
+    res["wealth_step"] = priced("wealth_step", pop.kernel_times(), 8 * n + 8 * donors)
+    res["wealth_step"]["donors"] = donors
+    pop.release()
+    torch.cuda.empty_cache()
+
+    # SIR pipelined body: 18 B per agent + 8 B per cell + 8 B per infected,
+    # in both count modes (gather: the body reads the 3x3 block of the count
+    # grid; box: a stencil kernel box-sums the grid, the body reads one cell)
+    for mode, label in ((1, "gather"), (2, "box")):
+        pop = A.Population(A.SIR, n, L=0, beta=(1, 20), gamma=(1, 100))
+        L = pop.info().grid_side
+        pop.tune(sir_form=1, sir_count=mode)
+        pop.step(30)
+        i_t = pop.invariants()["n_i"]
+        pop.profile(True)
+        pop.step(2)        # the body is step 31
+        times = pop.kernel_times()
+        step_bytes = 18 * n + 8 * L * L + 8 * i_t
+        if mode == 1:
+            entry = priced("sir_body", times, step_bytes)
+        else:
+            entry = priced("sir_body_box", times, step_bytes - 8 * L * L)
+            entry["box_kernel"] = priced("sir_box", {"sir_box": (times["sir_box"][0],
+                                                                 times["sir_box"][1])},
+                                         8 * L * L)
+            both = (times["sir_body_box"][1] / times["sir_body_box"][0] +
+                    times["sir_box"][1] / times["sir_box"][0]) / 1e3
+            entry["step_GBs"] = round(step_bytes / both / 1e9, 1)
+            entry["step_frac_of_hbm_peak"] = round(step_bytes / both / 1e9 / PEAK_HBM_GBS, 4)
+        entry.update({"grid_side": L, "infected": i_t})
+        res[f"sir_body_{label}"] = entry
+        pop.release()
+        torch.cuda.empty_cache()
+    return res
+
+
+def copy_probe():
+    """A plain device copy of exactly 1 GiB, 5 times: the reference for scaling
+    rocprofv3 FETCH_SIZE / WRITE_SIZE readings to bytes."""
+    import torch
+    a = torch.ones(1 << 28, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": a.numel() * 4, "copies": 5}), flush=True)
+
+
 # ------------------------------------------------------------------ main
 
 def main():
@@ -204,7 +285,13 @@ def main():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--sir-form", choices=["auto", "pipelined", "persistent"], default="auto")
+    ap.add_argument("--sir-count", choices=["auto", "gather", "box"], default="auto")
     ap.add_argument("--no-sweep", action="store_true", help="skip the 256-replicate sweep")
+    ap.add_argument("--roofline-big", action="store_true",
+                    help="also time the per-step kernels at an out-of-cache size")
+    ap.add_argument("--big-log2", type=int, default=27)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a 1 GiB device copy (counter calibration)")
     ap.add_argument("--serve", type=int, default=0,
                     help="serve the first N requests of the 10,000-request stream (0 = skip)")
     ap.add_argument("--serve-scale", type=float, default=1.0,
@@ -214,6 +301,10 @@ def main():
     ap.add_argument("--serve-plain", action="store_true",
                     help="also serve the stream FIFO one request at a time")
     args = ap.parse_args()
+
+    if args.copy_probe:
+        copy_probe()
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -233,8 +324,11 @@ def main():
 
     n, L = 1_000_000, 1000
     form = {"auto": 0, "pipelined": 1, "persistent": 2}[args.sir_form]
-    log(f"bench: SIR N={n} L={L} warmup={args.warmup} steps={args.steps} form={args.sir_form}")
-    secs, inv, times, infected = sir_bench(torch, A, args.warmup, args.steps, args.chunk, form)
+    count = {"auto": 0, "gather": 1, "box": 2}[args.sir_count]
+    log(f"bench: SIR N={n} L={L} warmup={args.warmup} steps={args.steps} form={args.sir_form} "
+        f"count={args.sir_count}")
+    secs, inv, times, infected = sir_bench(torch, A, args.warmup, args.steps, args.chunk, form,
+                                           count)
     value = n * args.steps / secs
     log(f"bench: {value:.4g} agent-steps/s, {secs * 1e3 / args.steps:.4f} ms/step, kernels {times}")
 
@@ -245,6 +339,9 @@ def main():
         priced["sir_persistent"] = sum(step_bytes)          # every step in each launch
     if "sir_body" in times:
         priced["sir_body"] = sum(step_bytes[1:])            # one step per body launch
+    if "sir_body_box" in times:                             # box mode: grid bytes go to sir_box
+        priced["sir_body_box"] = sum(b - 8 * L * L for b in step_bytes[1:])
+        priced["sir_box"] = 8 * L * L * len(step_bytes)
     roof = roofline_for(times, priced, load_traffic())
     if roof is not None:
         roof["timed_region_GBs"] = round(sum(step_bytes) / secs / 1e9, 1)
@@ -267,7 +364,8 @@ def main():
         "config": {"workload": "grid SIR, N=1e6 on a 1000x1000 torus, beta=1/20, gamma=1/100, "
                                "0.1% initially infected, key (0,0), 500 steps",
                    "n_agents": n, "grid_side": L, "timed_steps": f"{args.warmup}..{args.warmup + args.steps - 1}",
-                   "chunk": args.chunk or args.steps, "sir_form": args.sir_form},
+                   "chunk": args.chunk or args.steps, "sir_form": args.sir_form,
+                   "sir_count": args.sir_count},
         "final_invariants": {k: inv[k] for k in ("step", "n_s", "n_i", "n_r", "digest")},
         "kernels": kernels,
         "roofline": roof,
@@ -297,6 +395,10 @@ def main():
                             "out_of_bounds": rinv["out_of_bounds"]}
         out["extra"] = extra
         log(f"bench: extra {extra}")
+
+    if args.roofline_big:
+        out["roofline_big"] = roofline_big(torch, A, args.big_log2)
+        log(f"bench: roofline_big {out['roofline_big']}")
 
     if not args.no_sweep:
         from paper_2601_16292_amd import sweep as SW, workloads as WL

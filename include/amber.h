@@ -209,7 +209,11 @@ typedef struct {
                                   AMBER_E_UNSUPPORTED when N does not fit)        */
     uint32_t max_groups_per_thread; /* persistent form: largest number of 4-agent
                                   groups a thread may hold (1, 2, 4, 8; 0 = 8)    */
-    uint32_t reserved;
+    uint32_t sir_count;        /* SIR neighbour counts in the pipelined form:
+                                  0 = automatic, 1 = sum the 3x3 block of the
+                                  count grid per agent, 2 = box-sum the grid once
+                                  per step (one stencil kernel) and read one
+                                  cell per agent                                  */
 } amber_tuning_t;
 
 /* Set / get a handle's launch-shape knobs (host only). */

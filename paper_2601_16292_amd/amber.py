@@ -72,10 +72,11 @@ class PopInfo(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("block", ctypes.c_uint32), ("sir_form", ctypes.c_uint32),
-                ("max_groups_per_thread", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("max_groups_per_thread", ctypes.c_uint32), ("sir_count", ctypes.c_uint32)]
 
 
 SIR_AUTO, SIR_PIPELINED, SIR_PERSISTENT = 0, 1, 2
+COUNT_AUTO, COUNT_GATHER, COUNT_BOX = 0, 1, 2
 
 
 class KernelTime(ctypes.Structure):
@@ -216,8 +217,9 @@ def amber_pop_info(handle):
     return st, out
 
 
-def amber_set_tuning(handle, block=256, sir_form=SIR_AUTO, max_groups_per_thread=0):
-    t = Tuning(block, sir_form, max_groups_per_thread, 0)
+def amber_set_tuning(handle, block=256, sir_form=SIR_AUTO, max_groups_per_thread=0,
+                     sir_count=COUNT_AUTO):
+    t = Tuning(block, sir_form, max_groups_per_thread, sir_count)
     return lib().amber_set_tuning(handle, ctypes.byref(t))
 
 
@@ -326,8 +328,8 @@ class Population:
         check(amber_read_columns(self.handle, mask, ptrs))
         return [outs[c] for c in MODEL_COLUMNS[self.model]]
 
-    def tune(self, block=256, sir_form=SIR_AUTO, max_groups_per_thread=0):
-        check(amber_set_tuning(self.handle, block, sir_form, max_groups_per_thread))
+    def tune(self, block=256, sir_form=SIR_AUTO, max_groups_per_thread=0, sir_count=COUNT_AUTO):
+        check(amber_set_tuning(self.handle, block, sir_form, max_groups_per_thread, sir_count))
         return self
 
     def profile(self, enable=True):

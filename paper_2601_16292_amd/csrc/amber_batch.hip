@@ -68,15 +68,17 @@ __global__ void k_wealth_fold_batch(WealthBatch b, uint32_t parity)
 
 // ------------------------------------------------------------------ SIR (pipelined)
 
+template <bool BOX>
 __global__ void k_sir_head_batch(SirBatch b)
 {
     uint32_t lb, nb;
     const uint32_t r = batch_run(b.block_end, b.nruns, lb, nb);
     const SirParams &p = b.run[r];
     const uint32_t q = lb * blockDim.x + threadIdx.x;
-    if (q < p.groups) sir_head_group(p, q, b.t0[r]);
+    if (q < p.groups) sir_head_group<BOX>(p, q, b.t0[r]);
 }
 
+template <bool BOX>
 __global__ void k_sir_body_batch(SirBatch b, uint32_t i)
 {
     uint32_t lb, nb;
@@ -84,10 +86,11 @@ __global__ void k_sir_body_batch(SirBatch b, uint32_t i)
     const SirParams &p = b.run[r];
     const uint32_t t = b.t0[r] + i;
     const uint32_t q = lb * blockDim.x + threadIdx.x;
-    zero_quads(grid_of(p, t + 1), p.quads, q, nb * blockDim.x);
-    if (q < p.groups) sir_body_group(p, q, t);
+    if (!BOX) zero_quads(grid_of(p, t + 1), p.quads, q, nb * blockDim.x);
+    if (q < p.groups) sir_body_group<BOX>(p, q, t);
 }
 
+template <bool BOX>
 __global__ void k_sir_tail_batch(SirBatch b, uint32_t i)
 {
     uint32_t lb, nb;
@@ -95,8 +98,30 @@ __global__ void k_sir_tail_batch(SirBatch b, uint32_t i)
     const SirParams &p = b.run[r];
     const uint32_t t = b.t0[r] + i;
     const uint32_t q = lb * blockDim.x + threadIdx.x;
-    zero_quads(grid_of(p, t + 2), p.quads, q, nb * blockDim.x);
-    if (q < p.groups) sir_tail_group(p, q, t);
+    if (!BOX) zero_quads(grid_of(p, t + 2), p.quads, q, nb * blockDim.x);
+    if (q < p.groups) sir_tail_group<BOX>(p, q, t);
+}
+
+// Box and clear kernels map workgroups to each run's grid cells.
+__global__ void k_sir_box_batch(SirBatch b, uint32_t i)
+{
+    uint32_t lb, nb;
+    const uint32_t r = batch_run(b.cell_block_end, b.nruns, lb, nb);
+    const SirParams &p = b.run[r];
+    const uint32_t t = b.t0[r] + i;
+    const uint32_t c = lb * blockDim.x + threadIdx.x;
+    zero_quads(cgrid_box(p, t + 1), p.quads, c, nb * blockDim.x);
+    if (c < p.quads) sir_box_quad(p, cgrid_box(p, t), kgrid_box(p), c);
+}
+
+__global__ void k_sir_clear_batch(SirBatch b, uint32_t mask)
+{
+    uint32_t lb, nb;
+    const uint32_t r = batch_run(b.cell_block_end, b.nruns, lb, nb);
+    const SirParams &p = b.run[r];
+    const uint32_t c = lb * blockDim.x + threadIdx.x;
+    for (int g = 0; g < 3; ++g)
+        if (mask & (1u << g)) zero_quads(p.count[g], p.quads, c, nb * blockDim.x);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -128,18 +153,37 @@ hipError_t launch_wealth_batch(const WealthBatch &b, uint32_t n_steps, uint32_t 
     return hipGetLastError();
 }
 
-hipError_t launch_sir_batch(const SirBatch &b, uint32_t n_steps, uint32_t block, hipStream_t st)
+hipError_t launch_sir_batch(const SirBatch &b, uint32_t n_steps, bool box, uint32_t block,
+                            hipStream_t st)
 {
     const uint32_t blocks = b.block_end[b.nruns - 1];
-    hipLaunchKernelGGL(k_sir_head_batch, dim3(blocks), dim3(block), 0, st, b);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    for (uint32_t i = 1; i < n_steps; ++i) {
-        hipLaunchKernelGGL(k_sir_body_batch, dim3(blocks), dim3(block), 0, st, b, i);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+    const uint32_t cblocks = b.cell_block_end[b.nruns - 1];
+    hipError_t e;
+#define AMBER_LAUNCH(...)                                              \
+    do {                                                               \
+        hipLaunchKernelGGL(__VA_ARGS__);                               \
+        if ((e = hipGetLastError()) != hipSuccess) return e;           \
+    } while (0)
+    if (box) {
+        AMBER_LAUNCH(k_sir_head_batch<true>, dim3(blocks), dim3(block), 0, st, b);
+        AMBER_LAUNCH(k_sir_box_batch, dim3(cblocks), dim3(256), 0, st, b, 0u);
+        for (uint32_t i = 1; i < n_steps; ++i) {
+            AMBER_LAUNCH(k_sir_body_batch<true>, dim3(blocks), dim3(block), 0, st, b, i);
+            AMBER_LAUNCH(k_sir_box_batch, dim3(cblocks), dim3(256), 0, st, b, i);
+        }
+        AMBER_LAUNCH(k_sir_tail_batch<true>, dim3(blocks), dim3(block), 0, st, b, n_steps - 1);
+        AMBER_LAUNCH(k_sir_clear_batch, dim3(cblocks), dim3(256), 0, st, b,
+                     (1u << ((n_steps - 1) & 1)) | 4u);
+    } else {
+        AMBER_LAUNCH(k_sir_head_batch<false>, dim3(blocks), dim3(block), 0, st, b);
+        for (uint32_t i = 1; i < n_steps; ++i)
+            AMBER_LAUNCH(k_sir_body_batch<false>, dim3(blocks), dim3(block), 0, st, b, i);
+        AMBER_LAUNCH(k_sir_tail_batch<false>, dim3(blocks), dim3(block), 0, st, b, n_steps - 1);
+        AMBER_LAUNCH(k_sir_clear_batch, dim3(cblocks), dim3(256), 0, st, b,
+                     1u << ((n_steps - 1) % 3));
     }
-    hipLaunchKernelGGL(k_sir_tail_batch, dim3(blocks), dim3(block), 0, st, b, n_steps - 1);
-    return hipGetLastError();
+#undef AMBER_LAUNCH
+    return hipSuccess;
 }
 
 }  // namespace amber

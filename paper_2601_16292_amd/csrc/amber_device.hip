@@ -14,10 +14,6 @@
 // VALU throughput for Philox, and by atomic throughput for the scatter-adds.
 #include "amber_device_common.h"
 
-#include <hip/hip_cooperative_groups.h>
-
-namespace cg = cooperative_groups;
-
 namespace amber {
 
 // ------------------------------------------------------------------ init
@@ -104,33 +100,179 @@ __global__ __launch_bounds__(WEALTH_SMALL_THREADS) void k_wealth_small(
 }
 
 // head: move + bin(t)
+template <bool BOX>
 __global__ void k_sir_head(SirParams p, uint32_t t)
 {
     const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q < p.groups) sir_head_group(p, q, t);
+    if (q < p.groups) sir_head_group<BOX>(p, q, t);
 }
 
-// body: transition(t-1), then move + bin(t); clears C[(t+1)%3].
+// body (gather mode): transition(t-1), then move + bin(t); clears the grid of t+1.
 __global__ void k_sir_body(SirParams p, uint32_t t)
 {
     const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
     zero_quads(grid_of(p, t + 1), p.quads, q, gridDim.x * blockDim.x);
-    if (q < p.groups) sir_body_group(p, q, t);
+    if (q < p.groups) sir_body_group<false>(p, q, t);
 }
 
-// tail: transition(t); clears C[(t+2)%3].
+// body (box mode): transition(t-1) from K, then move + bin(t).
+__global__ void k_sir_body_box(SirParams p, uint32_t t)
+{
+    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < p.groups) sir_body_group<true>(p, q, t);
+}
+
+// tail (gather mode): transition(t); clears the grid of t+2.
 __global__ void k_sir_tail(SirParams p, uint32_t t)
 {
     const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
     zero_quads(grid_of(p, t + 2), p.quads, q, gridDim.x * blockDim.x);
-    if (q < p.groups) sir_tail_group(p, q, t);
+    if (q < p.groups) sir_tail_group<false>(p, q, t);
 }
 
-// Persistent form: G groups of 4 agents per thread (group q = tid + g*threads).
-template <int G>
-__global__ __launch_bounds__(256) void k_sir_persistent(SirParams p, uint32_t t0, uint32_t n_steps)
+// tail (box mode): transition(t) from K.
+__global__ void k_sir_tail_box(SirParams p, uint32_t t)
 {
-    cg::grid_group grid = cg::this_grid();
+    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < p.groups) sir_tail_group<true>(p, q, t);
+}
+
+// box (box mode): K = box sum of C_t; clears C_{t+1}.  One thread per 4 cells.
+__global__ void k_sir_box(SirParams p, uint32_t t)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    zero_quads(cgrid_box(p, t + 1), p.quads, i, gridDim.x * blockDim.x);
+    if (i < p.quads) sir_box_quad(p, cgrid_box(p, t), kgrid_box(p), i);
+}
+
+// Clear the count grids in mask (bit b = count[b]) at the end of a call.
+__global__ void k_sir_clear(SirParams p, uint32_t mask)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (int b = 0; b < 3; ++b)
+        if (mask & (1u << b)) zero_quads(p.count[b], p.quads, i, stride);
+}
+
+// ------------------------------------------------------------------ SIR, persistent form
+// One cooperative launch runs every step of the call.  Each thread keeps G
+// groups of 4 agents (positions and states) in registers; the only data
+// shared between workgroups are the count grids, and every access to them
+// uses agent-scope atomics (adds, stores, loads), which are coherent across
+// the XCDs' separate L2 caches without whole-cache write-backs.  One
+// device-wide barrier per step separates bin(t) from transition(t).
+//
+// The barrier is two-level: workgroups arrive on one of several group
+// counters (each on its own 128-byte line), the last arrival of a group bumps
+// the top counter, and every workgroup waits for the top counter.  Waits are
+// bounded: a wait that exceeds SYNC_SPIN_LIMIT sets a sticky error flag
+// (reported by the host at the next synchronising call) and every later wait
+// returns at once, so the kernel always runs to completion.
+
+constexpr uint32_t SYNC_STRIDE = 32;          // words between counters (128 B)
+constexpr uint32_t SYNC_SPIN_LIMIT = 1u << 22;
+
+__device__ __forceinline__ uint32_t ld_agent(const uint32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void st_agent(uint32_t *p, uint32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void grid_sync(const SyncParams &s, uint32_t epoch)
+{
+    __builtin_amdgcn_s_waitcnt(0);   // this wave's adds and stores have been performed
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t g = blockIdx.x / s.group_size;
+        const uint32_t first = g * s.group_size;
+        const uint32_t members = min(s.group_size, gridDim.x - first);
+        const uint32_t old = __hip_atomic_fetch_add(&s.words[g * SYNC_STRIDE], 1u, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t *top = &s.words[s.ngroups * SYNC_STRIDE];
+        if (old + 1 == epoch * members)
+            __hip_atomic_fetch_add(top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t spins = 0;
+        while (ld_agent(top) < epoch * s.ngroups) {
+            if ((++spins & 255u) == 0 && (spins > SYNC_SPIN_LIMIT || ld_agent(s.err))) {
+                __hip_atomic_fetch_or(s.err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    __syncthreads();
+}
+
+// Infected agents in the distinct cells of the 3x3 block, read coherently.
+__device__ __forceinline__ uint32_t block_count_agent(const uint32_t *__restrict__ count, int32_t L,
+                                                      int32_t cx, int32_t cy)
+{
+    if (!on_grid(cx, cy, L)) return 0;
+    if (L >= 3) {
+        const int32_t xm = cx == 0 ? L - 1 : cx - 1;
+        const int32_t xp = cx == L - 1 ? 0 : cx + 1;
+        const int32_t ym = cy == 0 ? L - 1 : cy - 1;
+        const int32_t yp = cy == L - 1 ? 0 : cy + 1;
+        const uint32_t *rm = count + (uint32_t)ym * L;
+        const uint32_t *r0 = count + (uint32_t)cy * L;
+        const uint32_t *rp = count + (uint32_t)yp * L;
+        return ld_agent(rm + xm) + ld_agent(rm + cx) + ld_agent(rm + xp) + ld_agent(r0 + xm) +
+               ld_agent(r0 + cx) + ld_agent(r0 + xp) + ld_agent(rp + xm) + ld_agent(rp + cx) +
+               ld_agent(rp + xp);
+    }
+    uint32_t k = 0;
+    for (int32_t c = 0; c < L * L; ++c) k += ld_agent(count + c);
+    return k;
+}
+
+// transition(t) with coherent count reads (same rule as sir_transition4).
+__device__ __forceinline__ uint32_t sir_transition4_agent(const SirParams &p,
+                                                          const uint32_t *__restrict__ count,
+                                                          uint32_t q, uint32_t t, uint32_t S,
+                                                          const int4 &X, const int4 &Y)
+{
+    const uint32_t a = 4 * q;
+    uint32_t st[4], k[4] = {0, 0, 0, 0};
+    bool any_sus = false, need = false;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        st[j] = (a + j < p.n) ? (S >> (8 * j)) & 0xffu : (uint32_t)ST_R;
+        any_sus |= st[j] == ST_S;
+    }
+    if (any_sus) {
+        if (st[0] == ST_S) k[0] = block_count_agent(count, p.L, X.x, Y.x);
+        if (st[1] == ST_S) k[1] = block_count_agent(count, p.L, X.y, Y.y);
+        if (st[2] == ST_S) k[2] = block_count_agent(count, p.L, X.z, Y.z);
+        if (st[3] == ST_S) k[3] = block_count_agent(count, p.L, X.w, Y.w);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) need |= (st[j] == ST_S && k[j] > 0) || st[j] == ST_I;
+    if (!need) return S;
+    const uint4 r = philox(q, t, P_EPI, p.k0, p.k1);
+    const uint32_t u[4] = {r.x, r.y, r.z, r.w};
+    const uint32_t k_last = p.table_len - 1;
+    uint32_t out = S;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        uint32_t ns = st[j];
+        if (st[j] == ST_S && k[j] > 0) {
+            if (u[j] < p.t_inf[k[j] < k_last ? k[j] : k_last]) ns = ST_I;
+        } else if (st[j] == ST_I) {
+            if (u[j] < p.t_rec) ns = ST_R;
+        }
+        out = (out & ~(0xffu << (8 * j))) | (ns << (8 * j));
+    }
+    return out;
+}
+
+template <int G>
+__global__ __launch_bounds__(256) void k_sir_persistent(SirParams p, SyncParams sync, uint32_t t0,
+                                                        uint32_t n_steps)
+{
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t nthr = gridDim.x * blockDim.x;
     int4 X[G], Y[G];
@@ -147,6 +289,7 @@ __global__ __launch_bounds__(256) void k_sir_persistent(SirParams p, uint32_t t0
             S[g] = 0x02020202u;
         }
     }
+    const uint32_t words = p.quads * 4;
     for (uint32_t i = 0; i < n_steps; ++i) {
         const uint32_t t = t0 + i;
         uint32_t *cur = grid_of(p, t);
@@ -155,15 +298,16 @@ __global__ __launch_bounds__(256) void k_sir_persistent(SirParams p, uint32_t t0
             const uint32_t q = tid + g * nthr;
             if (q < p.groups) {
                 sir_move4(p, q, t, X[g], Y[g]);
-                sir_bin4(p, cur, q, S[g], X[g], Y[g]);
+                sir_bin4(p, cur, q, S[g], X[g], Y[g]);   // agent-scope atomic adds
             }
         }
-        grid.sync();
-        zero_quads(grid_of(p, t + 2), p.quads, tid, nthr);
+        grid_sync(sync, i + 1);
+        uint32_t *clr = grid_of(p, t + 2);
+        for (uint32_t w = tid; w < words; w += nthr) st_agent(clr + w, 0u);
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             const uint32_t q = tid + g * nthr;
-            if (q < p.groups) S[g] = sir_transition4(p, cur, q, t, S[g], X[g], Y[g]);
+            if (q < p.groups) S[g] = sir_transition4_agent(p, cur, q, t, S[g], X[g], Y[g]);
         }
     }
 #pragma unroll
@@ -176,6 +320,12 @@ __global__ __launch_bounds__(256) void k_sir_persistent(SirParams p, uint32_t t0
         }
     }
 }
+
+__global__ void k_sync_reset(uint32_t *words, uint32_t n)
+{
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) words[i] = 0;
+}
+
 // ------------------------------------------------------------------ invariants
 
 __device__ __forceinline__ uint64_t fmix64(uint64_t z)
@@ -390,24 +540,49 @@ void sir_fill(SirParams &p)
     p.quads = div_up((uint32_t)p.L * (uint32_t)p.L, 4);
 }
 
-hipError_t launch_sir_head(SirParams p, uint32_t t, const Tuning &tu, hipStream_t st)
+hipError_t launch_sir_head(SirParams p, uint32_t t, bool box, const Tuning &tu, hipStream_t st)
 {
     sir_fill(p);
-    hipLaunchKernelGGL(k_sir_head, grid_for(p.groups, tu.block), dim3(tu.block), 0, st, p, t);
+    if (box)
+        hipLaunchKernelGGL(k_sir_head<true>, grid_for(p.groups, tu.block), dim3(tu.block), 0, st, p, t);
+    else
+        hipLaunchKernelGGL(k_sir_head<false>, grid_for(p.groups, tu.block), dim3(tu.block), 0, st, p, t);
     return hipGetLastError();
 }
 
-hipError_t launch_sir_body(SirParams p, uint32_t t, const Tuning &tu, hipStream_t st)
+hipError_t launch_sir_body(SirParams p, uint32_t t, bool box, const Tuning &tu, hipStream_t st)
 {
     sir_fill(p);
-    hipLaunchKernelGGL(k_sir_body, grid_for(p.groups, tu.block), dim3(tu.block), 0, st, p, t);
+    if (box)
+        hipLaunchKernelGGL(k_sir_body_box, grid_for(p.groups, tu.block), dim3(tu.block), 0, st, p, t);
+    else
+        hipLaunchKernelGGL(k_sir_body, grid_for(p.groups, tu.block), dim3(tu.block), 0, st, p, t);
     return hipGetLastError();
 }
 
-hipError_t launch_sir_tail(SirParams p, uint32_t t, const Tuning &tu, hipStream_t st)
+hipError_t launch_sir_tail(SirParams p, uint32_t t, bool box, const Tuning &tu, hipStream_t st)
 {
     sir_fill(p);
-    hipLaunchKernelGGL(k_sir_tail, grid_for(p.groups, tu.block), dim3(tu.block), 0, st, p, t);
+    if (box)
+        hipLaunchKernelGGL(k_sir_tail_box, grid_for(p.groups, tu.block), dim3(tu.block), 0, st, p, t);
+    else
+        hipLaunchKernelGGL(k_sir_tail, grid_for(p.groups, tu.block), dim3(tu.block), 0, st, p, t);
+    return hipGetLastError();
+}
+
+hipError_t launch_sir_box(SirParams p, uint32_t t, hipStream_t st)
+{
+    sir_fill(p);
+    hipLaunchKernelGGL(k_sir_box, grid_for(p.quads, 256), dim3(256), 0, st, p, t);
+    return hipGetLastError();
+}
+
+hipError_t launch_sir_clear(SirParams p, uint32_t mask, hipStream_t st)
+{
+    sir_fill(p);
+    uint32_t blocks = div_up(p.quads, 256);
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL(k_sir_clear, dim3(blocks), dim3(256), 0, st, p, mask);
     return hipGetLastError();
 }
 
@@ -429,10 +604,10 @@ static uint32_t persistent_capacity()
 }
 
 template <int G>
-static hipError_t launch_persistent_g(SirParams p, uint32_t t0, uint32_t n_steps, uint32_t blocks,
-                                      hipStream_t st)
+static hipError_t launch_persistent_g(SirParams p, SyncParams sync, uint32_t t0, uint32_t n_steps,
+                                      uint32_t blocks, hipStream_t st)
 {
-    void *args[] = {&p, &t0, &n_steps};
+    void *args[] = {&p, &sync, &t0, &n_steps};
     return hipLaunchCooperativeKernel((const void *)k_sir_persistent<G>, dim3(blocks), dim3(256),
                                       args, 0, st);
 }
@@ -440,6 +615,14 @@ static hipError_t launch_persistent_g(SirParams p, uint32_t t0, uint32_t n_steps
 uint32_t sir_persistent_groups_per_thread(uint32_t n, uint32_t max_g, uint32_t *blocks_out)
 {
     const uint32_t groups = groups_of(n);
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    // Fewer workgroups make the barrier cheaper (arrivals serialise on the
+    // counters); more workgroups hide more latency.  Take the smallest G that
+    // fits in at most two workgroups per CU, else the smallest that fits.
+    uint32_t best_g = 0, best_blocks = 0;
     static const uint32_t gs[] = {1, 2, 4, 8};
     for (uint32_t g : gs) {
         if (g > max_g) break;
@@ -451,23 +634,41 @@ uint32_t sir_persistent_groups_per_thread(uint32_t n, uint32_t max_g, uint32_t *
         case 8: cap = persistent_capacity<8>(); break;
         }
         const uint32_t need = div_up(groups, 256 * g);
-        if (cap && need <= cap) {
-            if (blocks_out) *blocks_out = need;
-            return g;
+        const uint32_t max_blocks = (SYNC_WORDS / SYNC_STRIDE - 1) * 16;
+        if (!cap || need > cap || need > max_blocks) continue;
+        if (!best_g) {
+            best_g = g;
+            best_blocks = need;
+        }
+        if (need <= 2u * (uint32_t)cus) {
+            best_g = g;
+            best_blocks = need;
+            break;
         }
     }
-    return 0;
+    if (blocks_out) *blocks_out = best_blocks;
+    return best_g;
 }
 
-hipError_t launch_sir_persistent(SirParams p, uint32_t t0, uint32_t n_steps, uint32_t g,
-                                 uint32_t blocks, hipStream_t st)
+hipError_t launch_sir_persistent(SirParams p, uint32_t *sync_words, uint32_t *err, uint32_t t0,
+                                 uint32_t n_steps, uint32_t g, uint32_t blocks, hipStream_t st)
 {
     sir_fill(p);
+    SyncParams sync;
+    sync.words = sync_words;
+    sync.err = err;
+    sync.group_size = 16;
+    sync.ngroups = div_up(blocks, sync.group_size);
+    if ((sync.ngroups + 1) * SYNC_STRIDE > SYNC_WORDS) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_sync_reset, dim3(1), dim3(256), 0, st, sync_words,
+                       (sync.ngroups + 1) * SYNC_STRIDE);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     switch (g) {
-    case 1: return launch_persistent_g<1>(p, t0, n_steps, blocks, st);
-    case 2: return launch_persistent_g<2>(p, t0, n_steps, blocks, st);
-    case 4: return launch_persistent_g<4>(p, t0, n_steps, blocks, st);
-    case 8: return launch_persistent_g<8>(p, t0, n_steps, blocks, st);
+    case 1: return launch_persistent_g<1>(p, sync, t0, n_steps, blocks, st);
+    case 2: return launch_persistent_g<2>(p, sync, t0, n_steps, blocks, st);
+    case 4: return launch_persistent_g<4>(p, sync, t0, n_steps, blocks, st);
+    case 8: return launch_persistent_g<8>(p, sync, t0, n_steps, blocks, st);
     }
     return hipErrorInvalidValue;
 }

@@ -194,20 +194,28 @@ __device__ __forceinline__ void wealth_small_run(int32_t *__restrict__ w, int32_
 //   transition(t) S -> I iff EPI word < T_inf[min(k, k_sat)] with k the infected
 //                 count of the distinct cells of the 3x3 torus block, I -> R iff
 //                 EPI word < T_rec, from C_t and the start-of-step state.
-// Three count grids rotate with t mod 3.  At every call boundary t (the
-// handle's step count) C[t%3] and C[(t+1)%3] are all zero; the third holds
-// garbage.  Every launch form below keeps that invariant, so forms may be
-// mixed between calls on one handle.
+//
+// Workspace grids: count[0..2], each L*L uint32, all zero at every call
+// boundary.  Inside a call (first step t_base) the grids are used by the
+// step's offset i = t - t_base, so every launch form starts from the same
+// state and forms can be mixed between calls on one handle:
+//   gather mode  C_t = count[i % 3]; transition(t) sums the 3x3 block of C_t
+//                (9 cells, read as three 3-cell rows);
+//   box mode     C_t = count[i % 2]; a stencil kernel writes the box-summed
+//                K = count[2] (K[c] = k of any agent in cell c), so
+//                transition(t) reads one cell of K.
+// The last kernels of a call leave the used grids zero again.
 //
 // Pipelined form (any N): "head" = move+bin(t0); "body"(t) = transition(t-1)
 // then move+bin(t), with the positions and states of its 4 agents held in
 // registers between the halves, so each column is read and written once per
-// step; "tail" = transition(t_last).  n steps cost n+1 launches.
+// step; "tail" = transition(t_last).  n steps cost n+1 launches (box mode adds
+// one stencil launch per step).
 //
 // Persistent form (N up to what the chip holds in registers): one cooperative
 // launch; each thread keeps its agents' positions and states in registers for
 // every step, and one grid barrier per step separates bin(t) from
-// transition(t).  The columns are read once and written once per call.
+// transition(t).
 
 // Positions come from the caller's columns; a coordinate outside [0, L) (only
 // possible if the caller overwrote a column) is never used as an address.
@@ -243,20 +251,33 @@ __device__ __forceinline__ void sir_bin4(const SirParams &p, uint32_t *__restric
     bin_infected(count, p.L, (S >> 24) == ST_I && a + 3 < p.n, X.w, Y.w);
 }
 
+// Three consecutive cells x-1, x, x+1 of one row, 1 <= x <= L-2: one
+// dword-aligned 12-byte load.
+struct __attribute__((packed, aligned(4))) Cells3 {
+    uint32_t a, b, c;
+};
+
+__device__ __forceinline__ uint32_t row3(const uint32_t *__restrict__ row, int32_t x, int32_t L)
+{
+    if (x >= 1 && x <= L - 2) {
+        const Cells3 v = *(const Cells3 *)(row + x - 1);
+        return v.a + v.b + v.c;
+    }
+    const int32_t xm = x == 0 ? L - 1 : x - 1;
+    const int32_t xp = x == L - 1 ? 0 : x + 1;
+    return row[xm] + row[x] + row[xp];
+}
+
 // Infected agents in the distinct cells of the 3x3 torus block around (cx, cy).
 __device__ __forceinline__ uint32_t block_count(const uint32_t *__restrict__ count, int32_t L,
                                                 int32_t cx, int32_t cy)
 {
     if (!on_grid(cx, cy, L)) return 0;
     if (L >= 3) {
-        const int32_t xm = cx == 0 ? L - 1 : cx - 1;
-        const int32_t xp = cx == L - 1 ? 0 : cx + 1;
         const int32_t ym = cy == 0 ? L - 1 : cy - 1;
         const int32_t yp = cy == L - 1 ? 0 : cy + 1;
-        const uint32_t *rm = count + (uint32_t)ym * L;
-        const uint32_t *r0 = count + (uint32_t)cy * L;
-        const uint32_t *rp = count + (uint32_t)yp * L;
-        return rm[xm] + rm[cx] + rm[xp] + r0[xm] + r0[cx] + r0[xp] + rp[xm] + rp[cx] + rp[xp];
+        return row3(count + (uint32_t)ym * L, cx, L) + row3(count + (uint32_t)cy * L, cx, L) +
+               row3(count + (uint32_t)yp * L, cx, L);
     }
     // L = 1 or 2: the wrapped block covers each of the L*L cells exactly once.
     uint32_t k = 0;
@@ -264,7 +285,18 @@ __device__ __forceinline__ uint32_t block_count(const uint32_t *__restrict__ cou
     return k;
 }
 
+// k of an agent at (cx, cy): from the count grid (gather mode) or from the
+// box-summed grid (box mode).
+template <bool BOX>
+__device__ __forceinline__ uint32_t neighbour_k(const uint32_t *__restrict__ g, int32_t L,
+                                                int32_t cx, int32_t cy)
+{
+    if (BOX) return on_grid(cx, cy, L) ? g[(uint32_t)cy * L + cx] : 0u;
+    return block_count(g, L, cx, cy);
+}
+
 // transition(t) of agents 4q..4q+3: returns the new state word.
+template <bool BOX>
 __device__ __forceinline__ uint32_t sir_transition4(const SirParams &p,
                                                     const uint32_t *__restrict__ count,
                                                     uint32_t q, uint32_t t, uint32_t S,
@@ -279,10 +311,10 @@ __device__ __forceinline__ uint32_t sir_transition4(const SirParams &p,
         any_sus |= st[j] == ST_S;
     }
     if (any_sus) {
-        if (st[0] == ST_S) k[0] = block_count(count, p.L, X.x, Y.x);
-        if (st[1] == ST_S) k[1] = block_count(count, p.L, X.y, Y.y);
-        if (st[2] == ST_S) k[2] = block_count(count, p.L, X.z, Y.z);
-        if (st[3] == ST_S) k[3] = block_count(count, p.L, X.w, Y.w);
+        if (st[0] == ST_S) k[0] = neighbour_k<BOX>(count, p.L, X.x, Y.x);
+        if (st[1] == ST_S) k[1] = neighbour_k<BOX>(count, p.L, X.y, Y.y);
+        if (st[2] == ST_S) k[2] = neighbour_k<BOX>(count, p.L, X.z, Y.z);
+        if (st[3] == ST_S) k[3] = neighbour_k<BOX>(count, p.L, X.w, Y.w);
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) need |= (st[j] == ST_S && k[j] > 0) || st[j] == ST_I;
@@ -311,9 +343,32 @@ __device__ __forceinline__ void zero_quads(uint32_t *__restrict__ p, uint32_t qu
     for (; i < quads; i += stride) p4[i] = make_uint4(0, 0, 0, 0);
 }
 
-__device__ __forceinline__ uint32_t *grid_of(const SirParams &p, uint32_t t) { return p.count[t % 3]; }
+// Count grid of step t: gather mode rotates three grids, box mode two.
+__device__ __forceinline__ uint32_t *grid_of(const SirParams &p, uint32_t t)
+{
+    return p.count[(t - p.t_base) % 3];
+}
+__device__ __forceinline__ uint32_t *cgrid_box(const SirParams &p, uint32_t t)
+{
+    return p.count[(t - p.t_base) & 1];
+}
+__device__ __forceinline__ uint32_t *kgrid_box(const SirParams &p) { return p.count[2]; }
+
+// Grid a transition(t) reads in each mode.
+template <bool BOX>
+__device__ __forceinline__ const uint32_t *kin(const SirParams &p, uint32_t t)
+{
+    return BOX ? kgrid_box(p) : grid_of(p, t);
+}
+// Grid bin(t) adds into in each mode.
+template <bool BOX>
+__device__ __forceinline__ uint32_t *bin_target(const SirParams &p, uint32_t t)
+{
+    return BOX ? cgrid_box(p, t) : grid_of(p, t);
+}
 
 // head(t): move + bin(t) of group q.
+template <bool BOX>
 __device__ __forceinline__ void sir_head_group(const SirParams &p, uint32_t q, uint32_t t)
 {
     int4 X = ((const int4 *)p.x)[q];
@@ -322,32 +377,51 @@ __device__ __forceinline__ void sir_head_group(const SirParams &p, uint32_t q, u
     sir_move4(p, q, t, X, Y);
     ((int4 *)p.x)[q] = X;
     ((int4 *)p.y)[q] = Y;
-    sir_bin4(p, grid_of(p, t), q, S, X, Y);
+    sir_bin4(p, bin_target<BOX>(p, t), q, S, X, Y);
 }
 
-// body(t): transition(t-1), then move + bin(t) of group q.  The caller clears
-// C[(t+1)%3].
+// body(t): transition(t-1), then move + bin(t) of group q.
+template <bool BOX>
 __device__ __forceinline__ void sir_body_group(const SirParams &p, uint32_t q, uint32_t t)
 {
     int4 X = ((const int4 *)p.x)[q];
     int4 Y = ((const int4 *)p.y)[q];
     const uint32_t S = ((const uint32_t *)p.s)[q];
-    const uint32_t S2 = sir_transition4(p, grid_of(p, t - 1), q, t - 1, S, X, Y);
+    const uint32_t S2 = sir_transition4<BOX>(p, kin<BOX>(p, t - 1), q, t - 1, S, X, Y);
     sir_move4(p, q, t, X, Y);
     ((int4 *)p.x)[q] = X;
     ((int4 *)p.y)[q] = Y;
     if (S2 != S) ((uint32_t *)p.s)[q] = S2;
-    sir_bin4(p, grid_of(p, t), q, S2, X, Y);
+    sir_bin4(p, bin_target<BOX>(p, t), q, S2, X, Y);
 }
 
-// tail(t): transition(t) of group q.  The caller clears C[(t+2)%3].
+// tail(t): transition(t) of group q.
+template <bool BOX>
 __device__ __forceinline__ void sir_tail_group(const SirParams &p, uint32_t q, uint32_t t)
 {
     const int4 X = ((const int4 *)p.x)[q];
     const int4 Y = ((const int4 *)p.y)[q];
     const uint32_t S = ((const uint32_t *)p.s)[q];
-    const uint32_t S2 = sir_transition4(p, grid_of(p, t), q, t, S, X, Y);
+    const uint32_t S2 = sir_transition4<BOX>(p, kin<BOX>(p, t), q, t, S, X, Y);
     if (S2 != S) ((uint32_t *)p.s)[q] = S2;
+}
+
+// box(t) for cells 4i..4i+3: K = 3x3 torus box sum of C_t (each distinct
+// cell once), written as one 16-byte store; cells past L*L (grid padding)
+// get 0.
+__device__ __forceinline__ void sir_box_quad(const SirParams &p, const uint32_t *__restrict__ C,
+                                             uint32_t *__restrict__ K, uint32_t i)
+{
+    const uint32_t cells = (uint32_t)p.L * (uint32_t)p.L;
+    uint32_t v[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t c = 4 * i + j;
+        v[j] = c < cells ? block_count(C, p.L, (int32_t)(c % (uint32_t)p.L),
+                                       (int32_t)(c / (uint32_t)p.L))
+                         : 0u;
+    }
+    ((uint4 *)K)[i] = make_uint4(v[0], v[1], v[2], v[3]);
 }
 
 }  // namespace amber

@@ -203,7 +203,7 @@ struct Resolved {
     uint32_t t_rec = 0;
     std::vector<uint32_t> t_inf;
     // workspace layout (byte offsets)
-    uint64_t off_inc0 = 0, off_inc1 = 0, off_table = 0, off_count[3] = {0, 0, 0};
+    uint64_t off_inc0 = 0, off_inc1 = 0, off_table = 0, off_count[3] = {0, 0, 0}, off_sync = 0;
     uint64_t ws_bytes = 0;
 };
 
@@ -258,6 +258,8 @@ amber_status_t resolve(const amber_run_desc_t *d, Resolved &r, bool want_table)
                 r.off_count[b] = ws;
                 ws += align_up(cells, 256);
             }
+            r.off_sync = ws;
+            ws += align_up((uint64_t)SYNC_WORDS * 4, 256);
         }
     }
     r.ws_bytes = ws;
@@ -362,6 +364,18 @@ amber_status_t check_device_ptr(const void *p, int device, const char *what, siz
     return AMBER_OK;
 }
 
+// After a synchronisation: report (and clear) the sticky device error word
+// that a persistent launch sets when one of its barrier waits gave up.
+amber_status_t check_device_flag(amber_pop *p, uint32_t flag)
+{
+    if (!flag) return AMBER_OK;
+    const uint32_t zero = 0;
+    HIP_TRY(hipMemcpy((uint8_t *)p->b.workspace + ERR_FLAG_OFFSET, &zero, 4, hipMemcpyHostToDevice),
+            "error flag clear");
+    return fail(AMBER_E_DEVICE, "a device-wide barrier of the persistent SIR form timed out; "
+                                "the run's state is invalid");
+}
+
 // Launch one kernel through f(), bracketed by timing events when enabled.
 template <class F>
 hipError_t timed(amber_pop *p, const char *name, F &&f)
@@ -397,7 +411,18 @@ SirParams sir_params(amber_pop *p)
     sp.L = (int32_t)r.L;
     sp.k0 = r.seed;
     sp.k1 = r.stream;
+    sp.t_base = (uint32_t)p->step;
     return sp;
+}
+
+// Box-summed count grid or 3x3 gathers: the automatic choice takes the box
+// mode once the grid no longer fits the last-level cache, where each of the
+// nine gathered cells would cost its own memory line.
+bool sir_box_mode(const amber_pop *p)
+{
+    if (p->tuning.sir_count == 1) return false;
+    if (p->tuning.sir_count == 2) return true;
+    return (uint64_t)p->r.L * p->r.L > (16ull << 20);
 }
 
 amber_status_t enqueue_steps(amber_pop *p, uint32_t n_steps)
@@ -450,18 +475,42 @@ amber_status_t enqueue_steps(amber_pop *p, uint32_t n_steps)
                             "the persistent SIR form does not fit %u agents on this device", r.n);
         }
         if (g) {
+            uint32_t *sync_words = (uint32_t *)ws_ptr(p, r.off_sync);
+            uint32_t *err = (uint32_t *)ws_ptr(p, ERR_FLAG_OFFSET);
             HIP_TRY(timed(p, "sir_persistent",
-                          [&] { return launch_sir_persistent(sp, t0, n_steps, g, blocks, st); }),
+                          [&] {
+                              return launch_sir_persistent(sp, sync_words, err, t0, n_steps, g,
+                                                           blocks, st);
+                          }),
                     "sir persistent kernel");
+            HIP_TRY(launch_sir_clear(sp, 1u << ((n_steps - 1) % 3), st), "sir clear kernel");
+        } else if (sir_box_mode(p)) {
+            HIP_TRY(timed(p, "sir_head", [&] { return launch_sir_head(sp, t0, true, tu, st); }),
+                    "sir head kernel");
+            HIP_TRY(timed(p, "sir_box", [&] { return launch_sir_box(sp, t0, st); }),
+                    "sir box kernel");
+            for (uint32_t i = 1; i < n_steps; ++i) {
+                HIP_TRY(timed(p, "sir_body_box",
+                              [&] { return launch_sir_body(sp, t0 + i, true, tu, st); }),
+                        "sir body kernel");
+                HIP_TRY(timed(p, "sir_box", [&] { return launch_sir_box(sp, t0 + i, st); }),
+                        "sir box kernel");
+            }
+            HIP_TRY(timed(p, "sir_tail_box",
+                          [&] { return launch_sir_tail(sp, t0 + n_steps - 1, true, tu, st); }),
+                    "sir tail kernel");
+            HIP_TRY(launch_sir_clear(sp, (1u << ((n_steps - 1) & 1)) | 4u, st), "sir clear kernel");
         } else {
-            HIP_TRY(timed(p, "sir_head", [&] { return launch_sir_head(sp, t0, tu, st); }),
+            HIP_TRY(timed(p, "sir_head", [&] { return launch_sir_head(sp, t0, false, tu, st); }),
                     "sir head kernel");
             for (uint32_t i = 1; i < n_steps; ++i)
-                HIP_TRY(timed(p, "sir_body", [&] { return launch_sir_body(sp, t0 + i, tu, st); }),
+                HIP_TRY(timed(p, "sir_body",
+                              [&] { return launch_sir_body(sp, t0 + i, false, tu, st); }),
                         "sir body kernel");
             HIP_TRY(timed(p, "sir_tail",
-                          [&] { return launch_sir_tail(sp, t0 + n_steps - 1, tu, st); }),
+                          [&] { return launch_sir_tail(sp, t0 + n_steps - 1, false, tu, st); }),
                     "sir tail kernel");
+            HIP_TRY(launch_sir_clear(sp, 1u << ((n_steps - 1) % 3), st), "sir clear kernel");
         }
     }
     return AMBER_OK;
@@ -560,20 +609,29 @@ amber_status_t run_batch(amber_pop *const *pops, uint32_t n, uint32_t n_steps)
                       [&] { return launch_wealth_batch(b, n_steps, block, st); }),
                 "wealth batch kernels");
     }
-    for (size_t c = 0; c < sir.size(); c += BATCH_RUNS) {
-        SirBatch b{};
-        uint32_t blocks = 0;
-        for (size_t k = c; k < sir.size() && k < c + BATCH_RUNS; ++k) {
-            amber_pop *p = sir[k];
-            const uint32_t j = b.nruns++;
-            b.run[j] = sir_params(p);
-            sir_fill(b.run[j]);
-            b.t0[j] = (uint32_t)p->step;
-            blocks += blocks_for(p->r.n);
-            b.block_end[j] = blocks;
+    // SIR runs go in chunks of one count mode each
+    for (int box = 0; box < 2; ++box) {
+        std::vector<amber_pop *> runs;
+        for (amber_pop *p : sir)
+            if (sir_box_mode(p) == (box != 0)) runs.push_back(p);
+        for (size_t c = 0; c < runs.size(); c += BATCH_RUNS) {
+            SirBatch b{};
+            uint32_t blocks = 0, cblocks = 0;
+            for (size_t k = c; k < runs.size() && k < c + BATCH_RUNS; ++k) {
+                amber_pop *p = runs[k];
+                const uint32_t j = b.nruns++;
+                b.run[j] = sir_params(p);
+                sir_fill(b.run[j]);
+                b.t0[j] = (uint32_t)p->step;
+                blocks += blocks_for(p->r.n);
+                b.block_end[j] = blocks;
+                cblocks += (b.run[j].quads + 255) / 256;
+                b.cell_block_end[j] = cblocks;
+            }
+            HIP_TRY(timed(lead, "sir_batch",
+                          [&] { return launch_sir_batch(b, n_steps, box != 0, block, st); }),
+                    "sir batch kernels");
         }
-        HIP_TRY(timed(lead, "sir_batch", [&] { return launch_sir_batch(b, n_steps, block, st); }),
-                "sir batch kernels");
     }
     return join_streams(pops, n, false);
 }
@@ -656,7 +714,9 @@ amber_status_t amber_init_population(const amber_run_desc_t *desc, const amber_b
         delete p;
         return s;
     };
-    hipError_t e = hipSuccess;
+    // header: invariants result and the sticky device error word
+    hipError_t e = launch_zero_words((uint32_t *)p->b.workspace, 64, p->stream);
+    if (e != hipSuccess) return bail(hip_fail(e, "workspace clear"));
     if (rr.model == AMBER_WEALTH) {
         e = launch_init_wealth(col_i32(p, AMBER_COL_WEALTH), (int32_t *)ws_ptr(p, rr.off_inc0),
                                (int32_t *)ws_ptr(p, rr.off_inc1), rr.n, rr.w_init, p->stream);
@@ -737,7 +797,13 @@ amber_status_t amber_read_columns(amber_pop_t *pop, uint32_t col_mask, void *con
                                pop->stream),
                 "column copy");
     }
+    uint32_t flag = 0;
+    HIP_TRY(hipMemcpyAsync(&flag, (uint8_t *)pop->b.workspace + ERR_FLAG_OFFSET, 4,
+                           hipMemcpyDeviceToHost, pop->stream),
+            "error flag copy");
     HIP_TRY(hipStreamSynchronize(pop->stream), "stream synchronize");
+    amber_status_t fst = check_device_flag(pop, flag);
+    if (fst != AMBER_OK) return fst;
     return AMBER_OK;
 }
 
@@ -751,10 +817,16 @@ amber_status_t amber_invariants(amber_pop_t *pop, amber_invariants_t *out)
                               (const uint8_t *)pop->b.col[AMBER_COL_STATE], pop->acc,
                               (DevInvariants *)ws_ptr(pop, INV_PARTIALS_OFFSET), pop->stream),
             "invariants kernel");
-    DevInvariants h;
-    HIP_TRY(hipMemcpyAsync(&h, pop->acc, sizeof h, hipMemcpyDeviceToHost, pop->stream),
+    uint8_t head[256];
+    HIP_TRY(hipMemcpyAsync(head, pop->acc, sizeof head, hipMemcpyDeviceToHost, pop->stream),
             "invariants copy");
     HIP_TRY(hipStreamSynchronize(pop->stream), "stream synchronize");
+    DevInvariants h;
+    std::memcpy(&h, head, sizeof h);
+    uint32_t flag;
+    std::memcpy(&flag, head + ERR_FLAG_OFFSET, 4);
+    amber_status_t fst = check_device_flag(pop, flag);
+    if (fst != AMBER_OK) return fst;
     std::memset(out, 0, sizeof *out);
     out->step = pop->step;
     out->digest = h.digest;
@@ -799,8 +871,10 @@ amber_status_t amber_set_tuning(amber_pop_t *pop, const amber_tuning_t *t)
         t->max_groups_per_thread != 2 && t->max_groups_per_thread != 4 &&
         t->max_groups_per_thread != 8)
         return fail(AMBER_E_INVALID, "max_groups_per_thread must be 0, 1, 2, 4 or 8");
+    if (t->sir_count > 2) return fail(AMBER_E_INVALID, "sir_count must be 0, 1 or 2");
     pop->tuning.block = t->block;
     pop->tuning.sir_form = t->sir_form;
+    pop->tuning.sir_count = t->sir_count;
     pop->tuning.max_g = t->max_groups_per_thread ? t->max_groups_per_thread : 8;
     return AMBER_OK;
 }
@@ -813,6 +887,7 @@ amber_status_t amber_get_tuning(const amber_pop_t *pop, amber_tuning_t *t)
     t->block = pop->tuning.block;
     t->sir_form = pop->tuning.sir_form;
     t->max_groups_per_thread = pop->tuning.max_g;
+    t->sir_count = pop->tuning.sir_count;
     return AMBER_OK;
 }
 

@@ -30,6 +30,7 @@ static_assert(sizeof(DevInvariants) <= 64, "invariants block must fit 64 B");
 // Workspace head: the reduced invariants at offset 0, then up to
 // INV_MAX_BLOCKS per-workgroup partials.
 constexpr uint32_t INV_MAX_BLOCKS = 1024;
+constexpr uint64_t ERR_FLAG_OFFSET = 128;      // sticky device error word (uint32)
 constexpr uint64_t INV_PARTIALS_OFFSET = 256;
 constexpr uint64_t INV_REGION = INV_PARTIALS_OFFSET + 64ull * INV_MAX_BLOCKS;
 
@@ -47,6 +48,16 @@ struct SirParams {
     uint32_t k0, k1;           // Philox key (seed, stream)
     uint32_t groups;           // ceil(n / 4), filled by the launcher
     uint32_t quads;            // ceil(L*L / 4), filled by the launcher
+    uint32_t t_base;           // first step of the current call (grid rotation origin)
+};
+
+// Device-wide barrier state of the persistent SIR form (inside the workspace).
+constexpr uint32_t SYNC_WORDS = 64 * 32;      // up to 63 counter groups + the top counter
+struct SyncParams {
+    uint32_t *words;           // group counters every 32 words, then the top counter
+    uint32_t *err;             // sticky: set when a barrier wait gave up
+    uint32_t group_size;       // workgroups per group counter
+    uint32_t ngroups;
 };
 
 // Launch configuration knobs (results never depend on them).
@@ -54,6 +65,7 @@ struct Tuning {
     uint32_t block = 256;      // threads per workgroup (multiple of 64, <= 1024)
     uint32_t sir_form = 0;     // 0 = automatic, 1 = pipelined, 2 = persistent
     uint32_t max_g = 8;        // persistent form: largest groups-per-thread to try
+    uint32_t sir_count = 0;    // 0 = automatic, 1 = gather 3x3 cells, 2 = box-summed grid
 };
 
 hipError_t launch_init_wealth(int32_t *w, int32_t *inc0, int32_t *inc1, uint32_t n,
@@ -81,17 +93,21 @@ hipError_t launch_wealth_small(int32_t *w, uint32_t n, uint32_t k0, uint32_t k1,
                                uint32_t t0, uint32_t n_steps, hipStream_t st);
 uint32_t wealth_small_max_agents();
 
-// SIR, pipelined form: head = move+bin(t); body = transition(t-1) + move+bin(t);
-// tail = transition(t).  n steps from t0: head(t0), body(t0+1..t0+n-1), tail(t0+n-1).
-hipError_t launch_sir_head(SirParams p, uint32_t t, const Tuning &tu, hipStream_t st);
-hipError_t launch_sir_body(SirParams p, uint32_t t, const Tuning &tu, hipStream_t st);
-hipError_t launch_sir_tail(SirParams p, uint32_t t, const Tuning &tu, hipStream_t st);
+// SIR, pipelined form.  Gather mode: head(t0), body(t0+1 .. t_last),
+// tail(t_last), clear(1 << ((n-1) % 3)).  Box mode: head(t0), box(t0),
+// then body(t), box(t) for t0 < t <= t_last, tail(t_last),
+// clear(1 << ((n-1) & 1) | 4).  sir_fill() runs inside every launcher.
+hipError_t launch_sir_head(SirParams p, uint32_t t, bool box, const Tuning &tu, hipStream_t st);
+hipError_t launch_sir_body(SirParams p, uint32_t t, bool box, const Tuning &tu, hipStream_t st);
+hipError_t launch_sir_tail(SirParams p, uint32_t t, bool box, const Tuning &tu, hipStream_t st);
+hipError_t launch_sir_box(SirParams p, uint32_t t, hipStream_t st);
+hipError_t launch_sir_clear(SirParams p, uint32_t mask, hipStream_t st);
 // SIR, persistent form: all n steps in one cooperative launch.  Returns the
 // groups-per-thread G (1, 2, 4 or 8, at most max_g) and the workgroup count
 // for n agents, or 0 when the population does not fit co-resident.
 uint32_t sir_persistent_groups_per_thread(uint32_t n, uint32_t max_g, uint32_t *blocks);
-hipError_t launch_sir_persistent(SirParams p, uint32_t t0, uint32_t n_steps, uint32_t g,
-                                 uint32_t blocks, hipStream_t st);
+hipError_t launch_sir_persistent(SirParams p, uint32_t *sync_words, uint32_t *err, uint32_t t0,
+                                 uint32_t n_steps, uint32_t g, uint32_t blocks, hipStream_t st);
 
 // ------------------------------------------------------------------ batches
 // Run tables of the batched launches, passed by value as kernel arguments.
@@ -123,9 +139,10 @@ struct WealthBatch {
 };
 
 struct SirBatch {
-    SirParams run[BATCH_RUNS];   // groups and quads filled in
+    SirParams run[BATCH_RUNS];   // groups, quads and t_base filled in
     uint32_t t0[BATCH_RUNS];
-    uint32_t block_end[BATCH_RUNS];
+    uint32_t block_end[BATCH_RUNS];       // over agent groups (block threads each)
+    uint32_t cell_block_end[BATCH_RUNS];  // over grid quads (256 threads each)
     uint32_t nruns;
 };
 
@@ -137,7 +154,8 @@ hipError_t launch_wealth_small_batch(const WealthSmallBatch &b, uint32_t n_steps
 hipError_t launch_wealth_batch(const WealthBatch &b, uint32_t n_steps, uint32_t block,
                                hipStream_t st);
 // SIR, pipelined: head, n_steps-1 bodies and a tail, each one launch for the chunk.
-hipError_t launch_sir_batch(const SirBatch &b, uint32_t n_steps, uint32_t block, hipStream_t st);
+hipError_t launch_sir_batch(const SirBatch &b, uint32_t n_steps, bool box, uint32_t block,
+                            hipStream_t st);
 void sir_fill(SirParams &p);
 
 // Two-stage reduction: per-workgroup partials, then one workgroup folds them

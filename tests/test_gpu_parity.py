@@ -183,14 +183,14 @@ def test_full_walk_1m(A, O, golden):
     assert np.array_equal(x[more], ox) and np.array_equal(y[more], oy)
 
 
-@pytest.mark.parametrize("form", [1, 2])
-def test_full_sir_1m(A, golden, form):
+@pytest.mark.parametrize("form,count", [(1, 1), (1, 2), (2, 0)])
+def test_full_sir_1m(A, golden, form, count):
     g = golden["sir_1m"]
     c = g["config"]
-    say(f"case full SIR N=1e6 L=1000 x 500 form={form}")
+    say(f"case full SIR N=1e6 L=1000 x 500 form={form} count={count}")
     pop = A.Population(A.SIR, c["n"], L=c["L"], seed=c["seed"], stream_id=c["stream"],
                        beta=tuple(c["beta"]), gamma=tuple(c["gamma"]))
-    pop.tune(sir_form=form)
+    pop.tune(sir_form=form, sir_count=count)
     done = 0
     for t in sorted(int(k) for k in g["checkpoints"]):
         pop.step(t - done)
@@ -245,6 +245,8 @@ def _sir_tuned(A, n, L, steps, chunks, tunings, seed=2, stream=6, beta=(1, 10), 
 
 
 SIR_FORMS = [dict(sir_form=1), dict(sir_form=1, block=64), dict(sir_form=1, block=1024),
+             dict(sir_form=1, sir_count=1), dict(sir_form=1, sir_count=2),
+             dict(sir_form=1, sir_count=2, block=128),
              dict(sir_form=2, max_groups_per_thread=1), dict(sir_form=2, max_groups_per_thread=2),
              dict(sir_form=2, max_groups_per_thread=8), dict(sir_form=0)]
 
@@ -260,10 +262,10 @@ def test_sir_launch_forms_match_oracle(A, O, n, L, tu):
 
 def test_sir_forms_mixed_across_calls(A, O):
     n, L = 50000, 223
-    chunks = [1, 5, 1, 7, 2, 1, 9]
-    tunings = [dict(sir_form=2), dict(sir_form=1), dict(sir_form=1), dict(sir_form=2),
+    chunks = [1, 5, 1, 7, 2, 1, 9, 1, 4, 3]
+    tunings = [dict(sir_form=2), dict(sir_form=1), dict(sir_form=1, sir_count=2), dict(sir_form=2),
                dict(sir_form=1, block=128), dict(sir_form=2, max_groups_per_thread=4),
-               dict(sir_form=0)]
+               dict(sir_form=0), dict(sir_count=2), dict(sir_count=1), dict(sir_count=2)]
     say("case sir mixed forms")
     got, inv = _sir_tuned(A, n, L, sum(chunks), chunks, tunings)
     ref = O.OracleRun(O.SIR, n, L, seed=2, stream=6, beta=(1, 10), gamma=(1, 30)).step(sum(chunks))
@@ -286,7 +288,7 @@ def test_block_size_invariance(A, O, model, n, block):
 def test_tuning_validation(A):
     pop = A.Population(A.RANDOM_WALK, 100, L=10)
     for bad in [dict(block=32), dict(block=1088), dict(block=100), dict(sir_form=3),
-                dict(max_groups_per_thread=3)]:
+                dict(max_groups_per_thread=3), dict(sir_count=3)]:
         with pytest.raises(A.AmberError):
             pop.tune(**bad)
     st, t = A.amber_get_tuning(pop.handle)
