@@ -76,14 +76,17 @@ def timed_steps(torch, pop, steps, chunk):
     return max(wall, ev0.elapsed_time(ev1) / 1e3)
 
 
-def sir_bench(torch, A, W, K, chunk, form, count=0):
+def sir_bench(torch, A, W, K, chunk, form, count=0, tuning=None):
     from paper_2601_16292_amd import workloads as WL
     c = WL.SIR_1M
 
     def mk():
         p = A.Population(A.SIR, c["n"], L=c["L"], seed=c["seed"], stream_id=c["stream"],
                          beta=c["beta"], gamma=c["gamma"])
-        p.tune(sir_form=form, sir_count=count)
+        if tuning:
+            p.tune(**tuning)
+        else:
+            p.tune(sir_form=form, sir_count=count)
         return p
 
     pop = mk()
@@ -154,8 +157,9 @@ def load_traffic():
 
 # ------------------------------------------------------------------ extras
 
-def wealth_bench(torch, A, n, W, K, chunk=0):
+def wealth_bench(torch, A, n, W, K, chunk=0, form=0):
     pop = A.Population(A.WEALTH, n, seed=0, stream_id=0, wealth_init=1)
+    pop.tune(wealth_form=form)
     pop.step(W)
     secs = timed_steps(torch, pop, K, chunk)
     inv = pop.invariants()
@@ -214,6 +218,22 @@ def roofline_big(torch, A, log2n):
     for _ in range(8):
         pop.step(1)
     res["walk_step"] = priced("walk", pop.kernel_times(), 16 * n)
+    pop.release()
+    torch.cuda.empty_cache()
+
+    # wealth, partition exchange at 2^24 agents (its largest size): 8 B per
+    # agent + 8 B per donor in one launch per step
+    nx = 1 << 24
+    pop = A.Population(A.WEALTH, nx, wealth_init=1)
+    pop.tune(wealth_form=2)
+    pop.step(2)
+    (w,) = pop.read()
+    donors = int((w > 0).sum())
+    del w
+    pop.profile(True)
+    pop.step(3)
+    res["wealth_exchange_2p24"] = priced("wealth_exchange", pop.kernel_times(), 8 * nx + 8 * donors)
+    res["wealth_exchange_2p24"]["donors_first_step"] = donors
     pop.release()
     torch.cuda.empty_cache()
 
@@ -285,7 +305,9 @@ def main():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--sir-form", choices=["auto", "pipelined", "persistent"], default="auto")
-    ap.add_argument("--sir-count", choices=["auto", "gather", "box"], default="auto")
+    ap.add_argument("--sir-count", choices=["auto", "gather", "box", "exchange"], default="auto")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="use --sir-form/--sir-count instead of the autotuner's choice")
     ap.add_argument("--no-sweep", action="store_true", help="skip the 256-replicate sweep")
     ap.add_argument("--roofline-big", action="store_true",
                     help="also time the per-step kernels at an out-of-cache size")
@@ -324,11 +346,17 @@ def main():
 
     n, L = 1_000_000, 1000
     form = {"auto": 0, "pipelined": 1, "persistent": 2}[args.sir_form]
-    count = {"auto": 0, "gather": 1, "box": 2}[args.sir_count]
+    count = {"auto": 0, "gather": 1, "box": 2, "exchange": 3}[args.sir_count]
     log(f"bench: SIR N={n} L={L} warmup={args.warmup} steps={args.steps} form={args.sir_form} "
         f"count={args.sir_count}")
+    tuning = None
+    if args.autotune:
+        from paper_2601_16292_amd import autotune as AT
+        tuning = AT.tune(A.SIR, n, L=L, steps=args.steps, warmup=args.warmup, torch=torch,
+                         force=True, log=log)
+        log(f"bench: autotuned {tuning}")
     secs, inv, times, infected = sir_bench(torch, A, args.warmup, args.steps, args.chunk, form,
-                                           count)
+                                           count, tuning)
     value = n * args.steps / secs
     log(f"bench: {value:.4g} agent-steps/s, {secs * 1e3 / args.steps:.4f} ms/step, kernels {times}")
 
@@ -339,6 +367,9 @@ def main():
         priced["sir_persistent"] = sum(step_bytes)          # every step in each launch
     if "sir_body" in times:
         priced["sir_body"] = sum(step_bytes[1:])            # one step per body launch
+    if "sir_xbody" in times:                                # exchange mode: grid bytes go to sir_xcount
+        priced["sir_xbody"] = sum(b - 8 * L * L for b in step_bytes)
+        priced["sir_xcount"] = 8 * L * L * len(step_bytes)
     if "sir_body_box" in times:                             # box mode: grid bytes go to sir_box
         priced["sir_body_box"] = sum(b - 8 * L * L for b in step_bytes[1:])
         priced["sir_box"] = 8 * L * L * len(step_bytes)
@@ -364,8 +395,9 @@ def main():
         "config": {"workload": "grid SIR, N=1e6 on a 1000x1000 torus, beta=1/20, gamma=1/100, "
                                "0.1% initially infected, key (0,0), 500 steps",
                    "n_agents": n, "grid_side": L, "timed_steps": f"{args.warmup}..{args.warmup + args.steps - 1}",
-                   "chunk": args.chunk or args.steps, "sir_form": args.sir_form,
-                   "sir_count": args.sir_count},
+                   "chunk": args.chunk or args.steps,
+                   "tuning": tuning if tuning else {"sir_form": args.sir_form,
+                                                     "sir_count": args.sir_count}},
         "final_invariants": {k: inv[k] for k in ("step", "n_s", "n_i", "n_r", "digest")},
         "kernels": kernels,
         "roofline": roof,
@@ -377,13 +409,14 @@ def main():
         extra["wealth_1k"] = {"value": round(1000 * 100 / s, 1), "unit": "agent-steps/s",
                               "steps": 100, "ms_total": round(s * 1e3, 4),
                               "wealth_sum": winv["wealth_sum"]}
-        s, winv = wealth_bench(torch, A, 1_000_000, 10, 200)
-        extra["wealth_1m"] = {"value": round(1e6 * 200 / s, 1), "unit": "agent-steps/s",
-                              "steps": 200, "ms_per_step": round(s * 1e3 / 200, 5),
-                              "wealth_sum": winv["wealth_sum"]}
+        for form, label in ((0, "wealth_1m"), (1, "wealth_1m_atomic")):
+            s, winv = wealth_bench(torch, A, 1_000_000, 10, 200, form=form)
+            extra[label] = {"value": round(1e6 * 200 / s, 1), "unit": "agent-steps/s",
+                            "steps": 200, "ms_per_step": round(s * 1e3 / 200, 5),
+                            "wealth_sum": winv["wealth_sum"]}
         if args.sir_form == "auto":
-            s2, _, t2, _ = sir_bench(torch, A, args.warmup, args.steps, args.chunk, 1)
-            extra["sir_1m_pipelined"] = {"value": round(n * args.steps / s2, 1),
+            s2, _, t2, _ = sir_bench(torch, A, args.warmup, args.steps, args.chunk, 1, 1)
+            extra["sir_1m_pipelined_gather"] = {"value": round(n * args.steps / s2, 1),
                                          "unit": "agent-steps/s",
                                          "ms_per_step": round(s2 * 1e3 / args.steps, 5),
                                          "kernels": {k: {"launches": v[0],

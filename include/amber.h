@@ -213,7 +213,18 @@ typedef struct {
                                   0 = automatic, 1 = sum the 3x3 block of the
                                   count grid per agent, 2 = box-sum the grid once
                                   per step (one stencil kernel) and read one
-                                  cell per agent                                  */
+                                  cell per agent, 3 = exchange: infected cells are
+                                  counting-sorted by row band in LDS and counted
+                                  per band into the box-summed grid, with no
+                                  global atomics (AMBER_E_UNSUPPORTED when the
+                                  grid is too small or too wide for it; inside
+                                  amber_step_batch such runs use mode 1)          */
+    uint32_t wealth_form;      /* WEALTH above 8192 agents: 0 = automatic,
+                                  1 = global atomic scatter-add, 2 = partition
+                                  exchange (recipient ids counting-sorted by
+                                  destination in LDS, counted by the owner;
+                                  AMBER_E_UNSUPPORTED above 2^24 agents)         */
+    uint32_t reserved[3];
 } amber_tuning_t;
 
 /* Set / get a handle's launch-shape knobs (host only). */

@@ -72,11 +72,13 @@ class PopInfo(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("block", ctypes.c_uint32), ("sir_form", ctypes.c_uint32),
-                ("max_groups_per_thread", ctypes.c_uint32), ("sir_count", ctypes.c_uint32)]
+                ("max_groups_per_thread", ctypes.c_uint32), ("sir_count", ctypes.c_uint32),
+                ("wealth_form", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 3)]
 
 
 SIR_AUTO, SIR_PIPELINED, SIR_PERSISTENT = 0, 1, 2
-COUNT_AUTO, COUNT_GATHER, COUNT_BOX = 0, 1, 2
+COUNT_AUTO, COUNT_GATHER, COUNT_BOX, COUNT_EXCHANGE = 0, 1, 2, 3
+WEALTH_AUTO, WEALTH_ATOMIC, WEALTH_EXCHANGE = 0, 1, 2
 
 
 class KernelTime(ctypes.Structure):
@@ -218,8 +220,8 @@ def amber_pop_info(handle):
 
 
 def amber_set_tuning(handle, block=256, sir_form=SIR_AUTO, max_groups_per_thread=0,
-                     sir_count=COUNT_AUTO):
-    t = Tuning(block, sir_form, max_groups_per_thread, sir_count)
+                     sir_count=COUNT_AUTO, wealth_form=WEALTH_AUTO):
+    t = Tuning(block, sir_form, max_groups_per_thread, sir_count, wealth_form)
     return lib().amber_set_tuning(handle, ctypes.byref(t))
 
 
@@ -328,8 +330,10 @@ class Population:
         check(amber_read_columns(self.handle, mask, ptrs))
         return [outs[c] for c in MODEL_COLUMNS[self.model]]
 
-    def tune(self, block=256, sir_form=SIR_AUTO, max_groups_per_thread=0, sir_count=COUNT_AUTO):
-        check(amber_set_tuning(self.handle, block, sir_form, max_groups_per_thread, sir_count))
+    def tune(self, block=256, sir_form=SIR_AUTO, max_groups_per_thread=0, sir_count=COUNT_AUTO,
+             wealth_form=WEALTH_AUTO):
+        check(amber_set_tuning(self.handle, block, sir_form, max_groups_per_thread, sir_count,
+                               wealth_form))
         return self
 
     def profile(self, enable=True):

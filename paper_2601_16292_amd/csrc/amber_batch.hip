@@ -124,6 +124,32 @@ __global__ void k_sir_clear_batch(SirBatch b, uint32_t mask)
         if (mask & (1u << g)) zero_quads(p.count[g], p.quads, c, nb * blockDim.x);
 }
 
+// Exchange count mode, batched: producer workgroups and band workgroups of
+// every run of the chunk in one launch each.
+constexpr uint32_t BX_PMAX = 2048;
+constexpr uint32_t BX_HIST = 16384;
+
+template <bool TRANSITION>
+__global__ __launch_bounds__(256) void k_sir_xbody_batch(SirBatch b, uint32_t i)
+{
+    __shared__ uint32_t pcount[BX_PMAX];
+    __shared__ uint32_t poff[BX_PMAX];
+    uint32_t lb, nb;
+    const uint32_t r = batch_run(b.xblock_end, b.nruns, lb, nb);
+    sir_exchange_produce<TRANSITION>(b.run[r], lb, b.t0[r] + i, pcount, poff);
+}
+
+__global__ __launch_bounds__(256) void k_sir_xcount_batch(SirBatch b)
+{
+    __shared__ uint32_t hist[BX_HIST];
+    __shared__ uint32_t scnt[XCHUNK];
+    __shared__ uint32_t soff[XCHUNK];
+    __shared__ uint32_t sraw[XCHUNK];
+    uint32_t lb, nb;
+    const uint32_t r = batch_run(b.band_end, b.nruns, lb, nb);
+    sir_exchange_count(b.run[r], lb, hist, scnt, soff, sraw);
+}
+
 // ------------------------------------------------------------------ launchers
 
 hipError_t launch_walk_batch(const WalkBatch &b, uint32_t n_steps, uint32_t block, hipStream_t st)
@@ -153,7 +179,7 @@ hipError_t launch_wealth_batch(const WealthBatch &b, uint32_t n_steps, uint32_t 
     return hipGetLastError();
 }
 
-hipError_t launch_sir_batch(const SirBatch &b, uint32_t n_steps, bool box, uint32_t block,
+hipError_t launch_sir_batch(const SirBatch &b, uint32_t n_steps, uint32_t mode, uint32_t block,
                             hipStream_t st)
 {
     const uint32_t blocks = b.block_end[b.nruns - 1];
@@ -164,7 +190,18 @@ hipError_t launch_sir_batch(const SirBatch &b, uint32_t n_steps, bool box, uint3
         hipLaunchKernelGGL(__VA_ARGS__);                               \
         if ((e = hipGetLastError()) != hipSuccess) return e;           \
     } while (0)
-    if (box) {
+    if (mode == 3) {
+        const uint32_t xblocks = b.xblock_end[b.nruns - 1];
+        const uint32_t bands = b.band_end[b.nruns - 1];
+        AMBER_LAUNCH(k_sir_xbody_batch<false>, dim3(xblocks), dim3(256), 0, st, b, 0u);
+        AMBER_LAUNCH(k_sir_xcount_batch, dim3(bands), dim3(256), 0, st, b);
+        for (uint32_t i = 1; i < n_steps; ++i) {
+            AMBER_LAUNCH(k_sir_xbody_batch<true>, dim3(xblocks), dim3(256), 0, st, b, i);
+            AMBER_LAUNCH(k_sir_xcount_batch, dim3(bands), dim3(256), 0, st, b);
+        }
+        AMBER_LAUNCH(k_sir_tail_batch<true>, dim3(blocks), dim3(block), 0, st, b, n_steps - 1);
+        AMBER_LAUNCH(k_sir_clear_batch, dim3(cblocks), dim3(256), 0, st, b, 4u);
+    } else if (mode == 2) {
         AMBER_LAUNCH(k_sir_head_batch<true>, dim3(blocks), dim3(block), 0, st, b);
         AMBER_LAUNCH(k_sir_box_batch, dim3(cblocks), dim3(256), 0, st, b, 0u);
         for (uint32_t i = 1; i < n_steps; ++i) {

@@ -99,6 +99,20 @@ __global__ __launch_bounds__(WEALTH_SMALL_THREADS) void k_wealth_small(
     wealth_small_run(w, sw, sinc, n, k0, k1, t0, n_steps);
 }
 
+// Partition-exchange wealth step (see wealth_exchange_partition).  mode bit 0:
+// fold the records of the previous step; bit 1: take this step's donors.
+template <int XB, int PMAX>
+__global__ __launch_bounds__(1024) void k_wealth_x(WealthXParams x, uint32_t t, uint32_t parity_in,
+                                                   uint32_t mode)
+{
+    __shared__ int32_t hist[1u << XB];
+    __shared__ uint32_t pcount[PMAX];
+    __shared__ uint32_t poff[PMAX];
+    __shared__ uint32_t praw[PMAX];
+    wealth_exchange_partition<XB, PMAX>(x, blockIdx.x, t, parity_in, (mode & 1u) != 0,
+                                        (mode & 2u) != 0, hist, pcount, poff, praw);
+}
+
 // head: move + bin(t)
 template <bool BOX>
 __global__ void k_sir_head(SirParams p, uint32_t t)
@@ -143,6 +157,28 @@ __global__ void k_sir_box(SirParams p, uint32_t t)
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     zero_quads(cgrid_box(p, t + 1), p.quads, i, gridDim.x * blockDim.x);
     if (i < p.quads) sir_box_quad(p, cgrid_box(p, t), kgrid_box(p), i);
+}
+
+// Exchange count mode: producer (transition(t-1) if TRANSITION, move(t),
+// sorted records of bin(t)) and the per-band count kernel writing K.
+constexpr uint32_t XPMAX = 2048;             // bands the producer can sort into
+constexpr uint32_t XHIST = 16384;            // LDS counters of a band plus halo rows
+
+template <bool TRANSITION>
+__global__ __launch_bounds__(256) void k_sir_xbody(SirParams p, uint32_t t)
+{
+    __shared__ uint32_t pcount[XPMAX];
+    __shared__ uint32_t poff[XPMAX];
+    sir_exchange_produce<TRANSITION>(p, blockIdx.x, t, pcount, poff);
+}
+
+__global__ __launch_bounds__(256) void k_sir_xcount(SirParams p)
+{
+    __shared__ uint32_t hist[XHIST];
+    __shared__ uint32_t scnt[XCHUNK];
+    __shared__ uint32_t soff[XCHUNK];
+    __shared__ uint32_t sraw[XCHUNK];
+    sir_exchange_count(p, blockIdx.x, hist, scnt, soff, sraw);
 }
 
 // Clear the count grids in mask (bit b = count[b]) at the end of a call.
@@ -525,6 +561,28 @@ hipError_t launch_wealth_fold(int32_t *base, int32_t *inc, uint32_t n, hipStream
 
 uint32_t wealth_small_max_agents() { return WEALTH_SMALL_MAX; }
 
+uint32_t wealth_exchange_bits(uint32_t n)
+{
+    if (n <= (1u << 21)) return 12;            // up to 512 partitions of 4096 agents
+    if (n <= (1u << 24)) return 14;            // up to 1024 partitions of 16384 agents
+    return 0;                                  // too many partitions: atomic path
+}
+
+hipError_t launch_wealth_exchange(const WealthXParams &x, uint32_t t, uint32_t parity_in,
+                                  uint32_t mode, uint32_t bits, hipStream_t st)
+{
+    if (bits == 12) {
+        if (x.P > 512) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_wealth_x<12, 512>), dim3(x.P), dim3(1024), 0, st, x, t, parity_in, mode);
+    } else if (bits == 14) {
+        if (x.P > 1024) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_wealth_x<14, 1024>), dim3(x.P), dim3(1024), 0, st, x, t, parity_in, mode);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_wealth_small(int32_t *w, uint32_t n, uint32_t k0, uint32_t k1, uint32_t t0,
                                uint32_t n_steps, hipStream_t st)
 {
@@ -574,6 +632,39 @@ hipError_t launch_sir_box(SirParams p, uint32_t t, hipStream_t st)
 {
     sir_fill(p);
     hipLaunchKernelGGL(k_sir_box, grid_for(p.quads, 256), dim3(256), 0, st, p, t);
+    return hipGetLastError();
+}
+
+bool sir_exchange_shape(uint32_t n, uint32_t L, uint32_t *h_out, uint32_t *P_out, uint32_t *W_out)
+{
+    if (L < 3) return false;
+    uint32_t h = (L + 255) / 256;
+    const uint32_t hmax = XHIST / L >= 3 ? XHIST / L - 2 : 0;
+    if (h > hmax) h = hmax;
+    if (h == 0) return false;
+    const uint32_t P = (L + h - 1) / h;
+    const uint32_t W = div_up(groups_of(n), 256);
+    if (P < 3 || P > XPMAX || (uint64_t)W * P > (32ull << 20)) return false;
+    *h_out = h;
+    *P_out = P;
+    *W_out = W;
+    return true;
+}
+
+hipError_t launch_sir_xbody(SirParams p, uint32_t t, bool transition, hipStream_t st)
+{
+    sir_fill(p);
+    if (transition)
+        hipLaunchKernelGGL(k_sir_xbody<true>, dim3(p.xW), dim3(256), 0, st, p, t);
+    else
+        hipLaunchKernelGGL(k_sir_xbody<false>, dim3(p.xW), dim3(256), 0, st, p, t);
+    return hipGetLastError();
+}
+
+hipError_t launch_sir_xcount(SirParams p, hipStream_t st)
+{
+    sir_fill(p);
+    hipLaunchKernelGGL(k_sir_xcount, dim3(p.xP), dim3(256), 0, st, p);
     return hipGetLastError();
 }
 

@@ -140,6 +140,170 @@ __device__ __forceinline__ void wealth_fold_group(int4 *__restrict__ base, int4 
     inc[q] = make_int4(0, 0, 0, 0);
 }
 
+// ------------------------------------------------------------------ block scan
+
+// Exclusive prefix sum of in[0..n) into out[0..n) by a workgroup of THREADS
+// threads (a multiple of 64, at most 1024), n <= THREADS * PER (each thread
+// scans up to PER consecutive entries).  in and out may alias.  Ends with a
+// barrier.
+template <uint32_t THREADS, uint32_t PER>
+__device__ __forceinline__ void block_exclusive_scan(const uint32_t *in, uint32_t *out, uint32_t n)
+{
+    constexpr uint32_t WAVES = THREADS / 64;
+    __shared__ uint32_t wave_total[WAVES];
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t per = (n + THREADS - 1) / THREADS;
+    const uint32_t start = tid * per;
+    uint32_t part[PER], sum = 0;
+#pragma unroll
+    for (uint32_t e = 0; e < PER; ++e) {
+        const uint32_t idx = start + e;
+        const uint32_t v = (e < per && idx < n) ? in[idx] : 0u;
+        part[e] = sum;
+        sum += v;
+    }
+    uint32_t incl = sum;
+    for (uint32_t off = 1; off < 64; off <<= 1) {
+        const uint32_t v = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += v;
+    }
+    if (lane == 63) wave_total[wave] = incl;
+    __syncthreads();
+    if (wave == 0) {
+        uint32_t wt = lane < WAVES ? wave_total[lane] : 0u;
+        uint32_t wi = wt;
+        for (uint32_t off = 1; off < WAVES; off <<= 1) {
+            const uint32_t v = __shfl_up(wi, off, 64);
+            if (lane >= off) wi += v;
+        }
+        if (lane < WAVES) wave_total[lane] = wi - wt;
+    }
+    __syncthreads();
+    const uint32_t base = incl - sum + wave_total[wave];
+#pragma unroll
+    for (uint32_t e = 0; e < PER; ++e) {
+        const uint32_t idx = start + e;
+        if (e < per && idx < n) out[idx] = base + part[e];
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void block_exclusive_scan_1024(const uint32_t *in, uint32_t *out,
+                                                          uint32_t n)
+{
+    block_exclusive_scan<1024, 4>(in, out, n);
+}
+
+// ------------------------------------------------------------------ wealth, partition exchange
+// The population is cut into partitions of XR = 2^XB consecutive agents and
+// one 1024-thread workgroup owns each partition.  The kernel of step t
+//   (1) folds into its agents the units sent to them at step t-1: the
+//       producers left their recipient ids sorted by destination partition,
+//       so the owner reads only its share and counts it in an LDS histogram;
+//   (2) decides its donors on the resulting snapshot, takes their unit, and
+//       draws their recipients;
+//   (3) counting-sorts those recipient ids by destination partition in LDS
+//       and writes them to its own output segment with plain stores, plus one
+//       (offset, count) word per destination.
+// No global atomics are used, and the column is read and written once per
+// step.  Records and tables are double-buffered by step parity; a call ends
+// with a fold-only launch, so the column holds the state at every call
+// boundary.
+
+template <int XB, int PMAX>
+__device__ __forceinline__ void wealth_exchange_partition(const WealthXParams &x, uint32_t p,
+                                                          uint32_t t, uint32_t parity_in,
+                                                          bool consume, bool produce,
+                                                          int32_t *hist, uint32_t *pcount,
+                                                          uint32_t *poff, uint32_t *praw)
+{
+    constexpr uint32_t XR = 1u << XB;
+    constexpr uint32_t G = XR / 4096;          // 4-agent groups per thread
+    const uint32_t tid = threadIdx.x;
+    const uint32_t P = x.P;
+    const uint32_t groups = groups_of(x.n);
+    for (uint32_t i = tid; i < XR; i += 1024) hist[i] = 0;
+    if (consume) {
+        // Load-balanced fold: prefix-sum the per-source counts, then every
+        // thread takes a flat record index and finds its source by binary
+        // search, so the records are read in parallel and coalesced.
+        const uint32_t *tab = x.tab[parity_in];
+        const uint32_t *rec = x.rec[parity_in];
+        for (uint32_t s = tid; s < P; s += 1024) {
+            const uint32_t e = tab[(size_t)s * P + p];
+            praw[s] = e;
+            pcount[s] = e & 0xffffu;
+        }
+        __syncthreads();
+        block_exclusive_scan_1024(pcount, poff, P);
+        const uint32_t total = poff[P - 1] + (praw[P - 1] & 0xffffu);
+        for (uint32_t i = tid; i < total; i += 1024) {
+            uint32_t lo = 0, hi = P;               // last source with poff[s] <= i
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (poff[mid] <= i) lo = mid;
+                else hi = mid;
+            }
+            const uint32_t r = rec[(size_t)lo * XR + (praw[lo] >> 16) + (i - poff[lo])];
+            atomicAdd(&hist[r - p * XR], 1);
+        }
+    }
+    for (uint32_t i = tid; i < P; i += 1024) pcount[i] = 0;
+    __syncthreads();
+    int4 V[G];
+    uint32_t rcp[G][4], rank[G][4];
+#pragma unroll
+    for (uint32_t g = 0; g < G; ++g) {
+        const uint32_t local = g * 1024 + tid;                 // group within the partition
+        const uint32_t q = p * (XR / 4) + local;
+        V[g] = make_int4(0, 0, 0, 0);
+        if (q < groups) {
+            const int4 W = ((const int4 *)x.w)[q];
+            V[g] = make_int4(W.x + hist[4 * local], W.y + hist[4 * local + 1],
+                             W.z + hist[4 * local + 2], W.w + hist[4 * local + 3]);
+        }
+        if (!produce) {
+            if (q < groups) ((int4 *)x.w)[q] = V[g];
+            continue;
+        }
+        const uint32_t a = 4 * q;
+        const int32_t v[4] = {V[g].x, V[g].y, V[g].z, V[g].w};
+        bool d[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            d[j] = q < groups && v[j] > 0 && a + j < x.n;
+            rcp[g][j] = 0xffffffffu;
+        }
+        if (d[0] | d[1]) {
+            const uint4 r = philox(2 * q, t, P_RECIPIENT, x.k0, x.k1);
+            if (d[0]) rcp[g][0] = recipient(r.x, r.y, x.n);
+            if (d[1]) rcp[g][1] = recipient(r.z, r.w, x.n);
+        }
+        if (d[2] | d[3]) {
+            const uint4 r = philox(2 * q + 1, t, P_RECIPIENT, x.k0, x.k1);
+            if (d[2]) rcp[g][2] = recipient(r.x, r.y, x.n);
+            if (d[3]) rcp[g][3] = recipient(r.z, r.w, x.n);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            rank[g][j] = d[j] ? atomicAdd(&pcount[rcp[g][j] >> XB], 1u) : 0u;
+        if (q < groups)
+            ((int4 *)x.w)[q] = make_int4(v[0] - d[0], v[1] - d[1], v[2] - d[2], v[3] - d[3]);
+    }
+    if (!produce) return;
+    __syncthreads();
+    block_exclusive_scan_1024(pcount, poff, P);
+    uint32_t *rec_out = x.rec[parity_in ^ 1u] + (size_t)p * XR;
+#pragma unroll
+    for (uint32_t g = 0; g < G; ++g)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (rcp[g][j] != 0xffffffffu)
+                rec_out[poff[rcp[g][j] >> XB] + rank[g][j]] = rcp[g][j];
+    uint32_t *tab_out = x.tab[parity_in ^ 1u] + (size_t)p * P;
+    for (uint32_t d = tid; d < P; d += 1024) tab_out[d] = (poff[d] << 16) | pcount[d];
+}
+
 // Small populations: one workgroup runs every step with the wealth column and
 // the increments in LDS; two barriers per step separate the donor/scatter
 // phase from the apply phase.  A thread owns agent pairs (one RECIPIENT
@@ -404,6 +568,127 @@ __device__ __forceinline__ void sir_tail_group(const SirParams &p, uint32_t q, u
     const uint32_t S = ((const uint32_t *)p.s)[q];
     const uint32_t S2 = sir_transition4<BOX>(p, kin<BOX>(p, t), q, t, S, X, Y);
     if (S2 != S) ((uint32_t *)p.s)[q] = S2;
+}
+
+// ------------------------------------------------------------------ SIR, exchange count mode
+// Binning without global atomics.  The grid is cut into bands of xh rows
+// (xP >= 3 bands).  The body kernel (256 threads, 1024 agents per workgroup)
+// emits, for every agent infected at the start of step t, a record holding
+// its post-move cell; a record on the first or last row of its band is also
+// sent to the neighbouring band, which needs that row as a halo.  The records
+// are counting-sorted by destination band in LDS and written to the
+// workgroup's own segment (at most 3 per agent) with one (offset, count)
+// word per band.  The count kernel (one workgroup per band) folds the records
+// sent to its band into an LDS histogram of the band's rows plus one halo row
+// on each side, and writes the band's rows of the box-summed grid K.  K is
+// rewritten every step, so nothing has to be cleared between steps.
+
+constexpr uint32_t XSEG = XSEG_WORDS;         // record slots per producer workgroup
+constexpr uint32_t XCHUNK = 1024;            // sources per fold round in the count kernel
+
+template <bool TRANSITION>
+__device__ __forceinline__ void sir_exchange_produce(const SirParams &p, uint32_t wg, uint32_t t,
+                                                     uint32_t *pcount, uint32_t *poff)
+{
+    const uint32_t tid = threadIdx.x;
+    const uint32_t q = wg * 256 + tid;
+    const uint32_t P = p.xP, h = p.xh;
+    for (uint32_t i = tid; i < P; i += 256) pcount[i] = 0;
+    __syncthreads();
+    uint32_t rc[12], rd[12], rr[12];
+    uint32_t nrec = 0;
+    if (q < p.groups) {
+        int4 X = ((const int4 *)p.x)[q];
+        int4 Y = ((const int4 *)p.y)[q];
+        const uint32_t S = ((const uint32_t *)p.s)[q];
+        uint32_t S2 = S;
+        if (TRANSITION) S2 = sir_transition4<true>(p, kgrid_box(p), q, t - 1, S, X, Y);
+        sir_move4(p, q, t, X, Y);
+        ((int4 *)p.x)[q] = X;
+        ((int4 *)p.y)[q] = Y;
+        if (S2 != S) ((uint32_t *)p.s)[q] = S2;
+        const int32_t xs[4] = {X.x, X.y, X.z, X.w};
+        const int32_t ys[4] = {Y.x, Y.y, Y.z, Y.w};
+        const uint32_t a = 4 * q;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (((S2 >> (8 * j)) & 0xffu) != ST_I || a + j >= p.n || !on_grid(xs[j], ys[j], p.L))
+                continue;
+            const uint32_t y = (uint32_t)ys[j];
+            const uint32_t c = y * (uint32_t)p.L + (uint32_t)xs[j];
+            const uint32_t d = y / h;
+            const uint32_t first = d * h;
+            const uint32_t last = min(first + h, (uint32_t)p.L) - 1;
+            rc[nrec] = c;
+            rd[nrec++] = d;
+            if (y == first) {
+                rc[nrec] = c;
+                rd[nrec++] = d == 0 ? P - 1 : d - 1;
+            }
+            if (y == last) {
+                rc[nrec] = c;
+                rd[nrec++] = d + 1 == P ? 0 : d + 1;
+            }
+        }
+    }
+    for (uint32_t k = 0; k < nrec; ++k) rr[k] = atomicAdd(&pcount[rd[k]], 1u);
+    __syncthreads();
+    block_exclusive_scan<256, 8>(pcount, poff, P);
+    uint32_t *rec = p.xrec + (size_t)wg * XSEG;
+    for (uint32_t k = 0; k < nrec; ++k) rec[poff[rd[k]] + rr[k]] = rc[k];
+    uint32_t *tab = p.xtab + (size_t)wg * P;
+    for (uint32_t d = tid; d < P; d += 256) tab[d] = (poff[d] << 16) | pcount[d];
+}
+
+// Count kernel body for band b (256 threads).  hist holds (xh + 2) * L counters.
+__device__ __forceinline__ void sir_exchange_count(const SirParams &p, uint32_t b, uint32_t *hist,
+                                                   uint32_t *scnt, uint32_t *soff, uint32_t *sraw)
+{
+    const uint32_t tid = threadIdx.x;
+    const uint32_t L = (uint32_t)p.L, h = p.xh, P = p.xP, W = p.xW;
+    const uint32_t y0 = b * h;
+    const uint32_t hb = min(h, L - y0);               // rows of this band
+    const uint32_t top = (y0 + L - 1) % L;            // halo row above the band
+    const uint32_t slots = (hb + 2) * L;
+    for (uint32_t i = tid; i < slots; i += 256) hist[i] = 0;
+    for (uint32_t w0 = 0; w0 < W; w0 += XCHUNK) {
+        const uint32_t nsrc = min(XCHUNK, W - w0);
+        __syncthreads();                              // previous round done with scnt/soff/sraw
+        for (uint32_t i = tid; i < nsrc; i += 256) {
+            const uint32_t e = p.xtab[(size_t)(w0 + i) * P + b];
+            sraw[i] = e;
+            scnt[i] = e & 0xffffu;
+        }
+        __syncthreads();
+        block_exclusive_scan<256, 4>(scnt, soff, nsrc);
+        const uint32_t total = soff[nsrc - 1] + (sraw[nsrc - 1] & 0xffffu);
+        for (uint32_t i = tid; i < total; i += 256) {
+            uint32_t lo = 0, hi = nsrc;               // last source with soff[s] <= i
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (soff[mid] <= i) lo = mid;
+                else hi = mid;
+            }
+            const uint32_t c = p.xrec[(size_t)(w0 + lo) * XSEG + (sraw[lo] >> 16) + (i - soff[lo])];
+            const uint32_t y = c / L, x = c - y * L;
+            const uint32_t r = (y + L - top) % L;     // slot row, < hb + 2 by construction
+            if (r < hb + 2) atomicAdd(&hist[r * L + x], 1u);
+        }
+    }
+    __syncthreads();
+    uint32_t *K = kgrid_box(p) + (size_t)y0 * L;
+    for (uint32_t i = tid; i < hb * L; i += 256) {
+        const uint32_t j = i / L + 1, x = i - (j - 1) * L;
+        const uint32_t xm = x == 0 ? L - 1 : x - 1;
+        const uint32_t xp = x + 1 == L ? 0 : x + 1;
+        uint32_t k = 0;
+#pragma unroll
+        for (uint32_t rr = 0; rr < 3; ++rr) {
+            const uint32_t *row = hist + (j - 1 + rr) * L;
+            k += row[xm] + row[x] + row[xp];
+        }
+        K[i] = k;
+    }
 }
 
 // box(t) for cells 4i..4i+3: K = 3x3 torus box sum of C_t (each distinct

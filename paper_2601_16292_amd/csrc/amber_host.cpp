@@ -204,6 +204,10 @@ struct Resolved {
     std::vector<uint32_t> t_inf;
     // workspace layout (byte offsets)
     uint64_t off_inc0 = 0, off_inc1 = 0, off_table = 0, off_count[3] = {0, 0, 0}, off_sync = 0;
+    uint32_t xbits = 0, xparts = 0;                 // wealth partition exchange (0 = unavailable)
+    uint32_t sx_h = 0, sx_P = 0, sx_W = 0;          // SIR exchange count mode (0 = unavailable)
+    uint64_t off_sxrec = 0, off_sxtab = 0;
+    uint64_t off_xrec[2] = {0, 0}, off_xtab[2] = {0, 0};
     uint64_t ws_bytes = 0;
 };
 
@@ -231,6 +235,17 @@ amber_status_t resolve(const amber_run_desc_t *d, Resolved &r, bool want_table)
         r.off_inc0 = ws;
         r.off_inc1 = ws + col;
         ws += 2 * col;
+        if (r.n > wealth_small_max_agents() && (r.xbits = wealth_exchange_bits(r.n)) != 0) {
+            r.xparts = (uint32_t)((r.n + (1ull << r.xbits) - 1) >> r.xbits);
+            const uint64_t rec = align_up((uint64_t)r.xparts << (r.xbits + 2), 256);
+            const uint64_t tab = align_up((uint64_t)r.xparts * r.xparts * 4, 256);
+            for (int b = 0; b < 2; ++b) {
+                r.off_xrec[b] = ws;
+                ws += rec;
+                r.off_xtab[b] = ws;
+                ws += tab;
+            }
+        }
     } else {
         const uint32_t L = d->grid_side ? d->grid_side : round_sqrt(d->n_agents);
         if (L == 0 || (uint64_t)L * L > 0x7fffffffull)
@@ -260,6 +275,12 @@ amber_status_t resolve(const amber_run_desc_t *d, Resolved &r, bool want_table)
             }
             r.off_sync = ws;
             ws += align_up((uint64_t)SYNC_WORDS * 4, 256);
+            if (sir_exchange_shape(r.n, L, &r.sx_h, &r.sx_P, &r.sx_W)) {
+                r.off_sxrec = ws;
+                ws += align_up((uint64_t)r.sx_W * XSEG_WORDS * 4, 256);
+                r.off_sxtab = ws;
+                ws += align_up((uint64_t)r.sx_W * r.sx_P * 4, 256);
+            }
         }
     }
     r.ws_bytes = ws;
@@ -412,18 +433,30 @@ SirParams sir_params(amber_pop *p)
     sp.k0 = r.seed;
     sp.k1 = r.stream;
     sp.t_base = (uint32_t)p->step;
+    if (r.sx_P) {
+        sp.xrec = (uint32_t *)ws_ptr(p, r.off_sxrec);
+        sp.xtab = (uint32_t *)ws_ptr(p, r.off_sxtab);
+        sp.xh = r.sx_h;
+        sp.xP = r.sx_P;
+        sp.xW = r.sx_W;
+    }
     return sp;
 }
 
-// Box-summed count grid or 3x3 gathers: the automatic choice takes the box
-// mode once the grid no longer fits the last-level cache, where each of the
-// nine gathered cells would cost its own memory line.
-bool sir_box_mode(const amber_pop *p)
+// SIR neighbour-count mode of the pipelined form: 1 gather, 2 box, 3 exchange.
+uint32_t sir_count_mode(const amber_pop *p)
 {
-    if (p->tuning.sir_count == 1) return false;
-    if (p->tuning.sir_count == 2) return true;
-    return (uint64_t)p->r.L * p->r.L > (16ull << 20);
+    const uint32_t want = p->tuning.sir_count;
+    if (want == 3) return p->r.sx_P ? 3u : 0u;    // 0: unavailable, caller reports it
+    if (want == 1 || want == 2) return want;
+    return (uint64_t)p->r.L * p->r.L > (16ull << 20) ? 2u : 1u;
 }
+
+// Automatic choice: the box mode once the grid no longer fits the
+// last-level cache, where each of the nine gathered cells would cost its own
+// memory line; else the 3x3 gathers.  The exchange mode (no global atomics)
+// runs on request or when the autotuner measures it faster.
+bool sir_box_mode(const amber_pop *p) { return sir_count_mode(p) == 2; }
 
 amber_status_t enqueue_steps(amber_pop *p, uint32_t n_steps)
 {
@@ -440,11 +473,37 @@ amber_status_t enqueue_steps(amber_pop *p, uint32_t n_steps)
                 "walk kernel");
     } else if (r.model == AMBER_WEALTH) {
         int32_t *w = col_i32(p, AMBER_COL_WEALTH);
+        const bool exchange = r.xbits != 0 && tu.wealth_form != 1;
+        if (tu.wealth_form == 2 && !exchange)
+            return fail(AMBER_E_UNSUPPORTED, "the partition-exchange wealth path does not cover "
+                                             "%u agents", r.n);
         if (r.n <= wealth_small_max_agents()) {
             HIP_TRY(timed(p, "wealth_small", [&] {
                         return launch_wealth_small(w, r.n, r.seed, r.stream, t0, n_steps, st);
                     }),
                     "wealth small kernel");
+        } else if (exchange) {
+            WealthXParams x;
+            x.w = w;
+            for (int b = 0; b < 2; ++b) {
+                x.rec[b] = (uint32_t *)ws_ptr(p, r.off_xrec[b]);
+                x.tab[b] = (uint32_t *)ws_ptr(p, r.off_xtab[b]);
+            }
+            x.n = r.n;
+            x.P = r.xparts;
+            x.k0 = r.seed;
+            x.k1 = r.stream;
+            for (uint32_t i = 0; i < n_steps; ++i)
+                HIP_TRY(timed(p, "wealth_exchange", [&] {
+                            return launch_wealth_exchange(x, t0 + i, (i + 1) & 1u, i ? 3u : 2u,
+                                                          r.xbits, st);
+                        }),
+                        "wealth exchange kernel");
+            HIP_TRY(timed(p, "wealth_exchange_fold", [&] {
+                        return launch_wealth_exchange(x, t0 + n_steps, (n_steps - 1) & 1u, 1u,
+                                                      r.xbits, st);
+                    }),
+                    "wealth exchange fold kernel");
         } else {
             int32_t *inc[2] = {(int32_t *)ws_ptr(p, r.off_inc0), (int32_t *)ws_ptr(p, r.off_inc1)};
             for (uint32_t i = 0; i < n_steps; ++i)
@@ -484,6 +543,25 @@ amber_status_t enqueue_steps(amber_pop *p, uint32_t n_steps)
                           }),
                     "sir persistent kernel");
             HIP_TRY(launch_sir_clear(sp, 1u << ((n_steps - 1) % 3), st), "sir clear kernel");
+        } else if (tu.sir_count == 3 && !r.sx_P) {
+            return fail(AMBER_E_UNSUPPORTED, "the exchange count mode does not fit this run "
+                                             "(grid side %u, %u agents)", r.L, r.n);
+        } else if (sir_count_mode(p) == 3) {
+            HIP_TRY(timed(p, "sir_xbody", [&] { return launch_sir_xbody(sp, t0, false, st); }),
+                    "sir exchange body kernel");
+            HIP_TRY(timed(p, "sir_xcount", [&] { return launch_sir_xcount(sp, st); }),
+                    "sir exchange count kernel");
+            for (uint32_t i = 1; i < n_steps; ++i) {
+                HIP_TRY(timed(p, "sir_xbody",
+                              [&] { return launch_sir_xbody(sp, t0 + i, true, st); }),
+                        "sir exchange body kernel");
+                HIP_TRY(timed(p, "sir_xcount", [&] { return launch_sir_xcount(sp, st); }),
+                        "sir exchange count kernel");
+            }
+            HIP_TRY(timed(p, "sir_tail_box",
+                          [&] { return launch_sir_tail(sp, t0 + n_steps - 1, true, tu, st); }),
+                    "sir tail kernel");
+            HIP_TRY(launch_sir_clear(sp, 4u, st), "sir clear kernel");
         } else if (sir_box_mode(p)) {
             HIP_TRY(timed(p, "sir_head", [&] { return launch_sir_head(sp, t0, true, tu, st); }),
                     "sir head kernel");
@@ -610,13 +688,16 @@ amber_status_t run_batch(amber_pop *const *pops, uint32_t n, uint32_t n_steps)
                 "wealth batch kernels");
     }
     // SIR runs go in chunks of one count mode each
-    for (int box = 0; box < 2; ++box) {
+    for (uint32_t mode = 1; mode <= 3; ++mode) {
         std::vector<amber_pop *> runs;
-        for (amber_pop *p : sir)
-            if (sir_box_mode(p) == (box != 0)) runs.push_back(p);
+        for (amber_pop *p : sir) {
+            uint32_t m = sir_count_mode(p);
+            if (m == 0) m = 1;     // exchange requested but unavailable: gather (same results)
+            if (m == mode) runs.push_back(p);
+        }
         for (size_t c = 0; c < runs.size(); c += BATCH_RUNS) {
             SirBatch b{};
-            uint32_t blocks = 0, cblocks = 0;
+            uint32_t blocks = 0, cblocks = 0, xblocks = 0, bands = 0;
             for (size_t k = c; k < runs.size() && k < c + BATCH_RUNS; ++k) {
                 amber_pop *p = runs[k];
                 const uint32_t j = b.nruns++;
@@ -627,9 +708,13 @@ amber_status_t run_batch(amber_pop *const *pops, uint32_t n, uint32_t n_steps)
                 b.block_end[j] = blocks;
                 cblocks += (b.run[j].quads + 255) / 256;
                 b.cell_block_end[j] = cblocks;
+                xblocks += b.run[j].xW;
+                b.xblock_end[j] = xblocks;
+                bands += b.run[j].xP;
+                b.band_end[j] = bands;
             }
             HIP_TRY(timed(lead, "sir_batch",
-                          [&] { return launch_sir_batch(b, n_steps, box != 0, block, st); }),
+                          [&] { return launch_sir_batch(b, n_steps, mode, block, st); }),
                     "sir batch kernels");
         }
     }
@@ -871,7 +956,9 @@ amber_status_t amber_set_tuning(amber_pop_t *pop, const amber_tuning_t *t)
         t->max_groups_per_thread != 2 && t->max_groups_per_thread != 4 &&
         t->max_groups_per_thread != 8)
         return fail(AMBER_E_INVALID, "max_groups_per_thread must be 0, 1, 2, 4 or 8");
-    if (t->sir_count > 2) return fail(AMBER_E_INVALID, "sir_count must be 0, 1 or 2");
+    if (t->sir_count > 3) return fail(AMBER_E_INVALID, "sir_count must be 0, 1, 2 or 3");
+    if (t->wealth_form > 2) return fail(AMBER_E_INVALID, "wealth_form must be 0, 1 or 2");
+    pop->tuning.wealth_form = t->wealth_form;
     pop->tuning.block = t->block;
     pop->tuning.sir_form = t->sir_form;
     pop->tuning.sir_count = t->sir_count;
@@ -888,6 +975,7 @@ amber_status_t amber_get_tuning(const amber_pop_t *pop, amber_tuning_t *t)
     t->sir_form = pop->tuning.sir_form;
     t->max_groups_per_thread = pop->tuning.max_g;
     t->sir_count = pop->tuning.sir_count;
+    t->wealth_form = pop->tuning.wealth_form;
     return AMBER_OK;
 }
 

@@ -49,7 +49,14 @@ struct SirParams {
     uint32_t groups;           // ceil(n / 4), filled by the launcher
     uint32_t quads;            // ceil(L*L / 4), filled by the launcher
     uint32_t t_base;           // first step of the current call (grid rotation origin)
+    // exchange count mode (see sir_exchange_produce): null xrec = unavailable
+    uint32_t *xrec;            // xW segments of 3*1024 cell records
+    uint32_t *xtab;            // xtab[w*xP + band] = offset << 16 | count
+    uint32_t xh, xP, xW;       // rows per band, bands (>= 3), producer workgroups
 };
+
+// Record slots per producer workgroup of the SIR exchange mode (3 per agent).
+constexpr uint32_t XSEG_WORDS = 3 * 1024;
 
 // Device-wide barrier state of the persistent SIR form (inside the workspace).
 constexpr uint32_t SYNC_WORDS = 64 * 32;      // up to 63 counter groups + the top counter
@@ -65,7 +72,9 @@ struct Tuning {
     uint32_t block = 256;      // threads per workgroup (multiple of 64, <= 1024)
     uint32_t sir_form = 0;     // 0 = automatic, 1 = pipelined, 2 = persistent
     uint32_t max_g = 8;        // persistent form: largest groups-per-thread to try
-    uint32_t sir_count = 0;    // 0 = automatic, 1 = gather 3x3 cells, 2 = box-summed grid
+    uint32_t sir_count = 0;    // 0 = automatic, 1 = gather 3x3 cells, 2 = box-summed grid,
+                               // 3 = exchange (sorted records, per-band counts)
+    uint32_t wealth_form = 0;  // 0 = automatic, 1 = atomic scatter, 2 = partition exchange
 };
 
 hipError_t launch_init_wealth(int32_t *w, int32_t *inc0, int32_t *inc1, uint32_t n,
@@ -92,6 +101,19 @@ hipError_t launch_wealth_fold(int32_t *base, int32_t *inc, uint32_t n, hipStream
 hipError_t launch_wealth_small(int32_t *w, uint32_t n, uint32_t k0, uint32_t k1,
                                uint32_t t0, uint32_t n_steps, hipStream_t st);
 uint32_t wealth_small_max_agents();
+// Partition-exchange wealth path: log2 of the partition size for n agents
+// (0 when n is too large for it).  A call of n steps launches mode 2 (take
+// donors) once, mode 3 (fold + take) n-1 times and mode 1 (fold) once, with
+// parity_in = step offset & 1.
+struct WealthXParams {
+    int32_t *w;
+    uint32_t *rec[2];          // P segments of 2^bits recipient ids, per parity
+    uint32_t *tab[2];          // tab[s*P + d] = offset << 16 | count, per parity
+    uint32_t n, P, k0, k1;
+};
+uint32_t wealth_exchange_bits(uint32_t n);
+hipError_t launch_wealth_exchange(const WealthXParams &x, uint32_t t, uint32_t parity_in,
+                                  uint32_t mode, uint32_t bits, hipStream_t st);
 
 // SIR, pipelined form.  Gather mode: head(t0), body(t0+1 .. t_last),
 // tail(t_last), clear(1 << ((n-1) % 3)).  Box mode: head(t0), box(t0),
@@ -102,6 +124,13 @@ hipError_t launch_sir_body(SirParams p, uint32_t t, bool box, const Tuning &tu, 
 hipError_t launch_sir_tail(SirParams p, uint32_t t, bool box, const Tuning &tu, hipStream_t st);
 hipError_t launch_sir_box(SirParams p, uint32_t t, hipStream_t st);
 hipError_t launch_sir_clear(SirParams p, uint32_t mask, hipStream_t st);
+// Exchange count mode: xbody(t0, no transition), then xcount, and for each
+// later step xbody(t, transition) + xcount; finally tail(t_last, box) and
+// clear(4).  sir_exchange_shape picks the band height h, band count P and
+// producer workgroup count W (false when the run does not fit the mode).
+bool sir_exchange_shape(uint32_t n, uint32_t L, uint32_t *h, uint32_t *P, uint32_t *W);
+hipError_t launch_sir_xbody(SirParams p, uint32_t t, bool transition, hipStream_t st);
+hipError_t launch_sir_xcount(SirParams p, hipStream_t st);
 // SIR, persistent form: all n steps in one cooperative launch.  Returns the
 // groups-per-thread G (1, 2, 4 or 8, at most max_g) and the workgroup count
 // for n agents, or 0 when the population does not fit co-resident.
@@ -143,6 +172,8 @@ struct SirBatch {
     uint32_t t0[BATCH_RUNS];
     uint32_t block_end[BATCH_RUNS];       // over agent groups (block threads each)
     uint32_t cell_block_end[BATCH_RUNS];  // over grid quads (256 threads each)
+    uint32_t xblock_end[BATCH_RUNS];      // exchange mode: producer workgroups (xW each)
+    uint32_t band_end[BATCH_RUNS];        // exchange mode: count workgroups (xP each)
     uint32_t nruns;
 };
 
@@ -154,7 +185,8 @@ hipError_t launch_wealth_small_batch(const WealthSmallBatch &b, uint32_t n_steps
 hipError_t launch_wealth_batch(const WealthBatch &b, uint32_t n_steps, uint32_t block,
                                hipStream_t st);
 // SIR, pipelined: head, n_steps-1 bodies and a tail, each one launch for the chunk.
-hipError_t launch_sir_batch(const SirBatch &b, uint32_t n_steps, bool box, uint32_t block,
+// mode: 1 gather, 2 box, 3 exchange (every run of the chunk in that mode).
+hipError_t launch_sir_batch(const SirBatch &b, uint32_t n_steps, uint32_t mode, uint32_t block,
                             hipStream_t st);
 void sir_fill(SirParams &p);
 

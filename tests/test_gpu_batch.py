@@ -78,14 +78,14 @@ def test_mixed_batch_matches_oracle(A, O):
         p.release()
 
 
-@pytest.mark.parametrize("count", [1, 2, "mixed"])
+@pytest.mark.parametrize("count", [1, 2, 3, "mixed"])
 def test_many_runs_chunked_into_launches(A, O, count):
     say(f"case 53 SIR runs in one batch, count mode {count}")
     specs = [dict(model=2, n=100 + 37 * i, L=0, stream=100 + i,
                   beta=((15 + 19 * (i % 16)), 1500)) for i in range(53)]
     pops = [make(A, s) for s in specs]
     for i, p in enumerate(pops):
-        p.tune(sir_count=(1 + i % 2) if count == "mixed" else count)
+        p.tune(sir_count=(1 + i % 3) if count == "mixed" else count)
     A.step_batch(pops, 17)
     for p, s in zip(pops, specs):
         ref = oracle_run(O, s, 17)
@@ -136,7 +136,7 @@ def test_full_sir_sweep_batched(A, sweep_golden):
     pops = [A.Population(A.SIR, r["n"], L=r["L"], seed=r["seed"], stream_id=r["stream"],
                          beta=r["beta"], gamma=r["gamma"]) for r in runs]
     for i, p in enumerate(pops):
-        p.tune(sir_count=1 + (i % 2))       # both count modes inside one sweep
+        p.tune(sir_count=1 + (i % 3))       # every count mode inside one sweep
     A.step_batch(pops, sweep_golden["steps"])
     for p, want in zip(pops, sweep_golden["runs"]):
         inv = p.invariants()

@@ -183,7 +183,7 @@ def test_full_walk_1m(A, O, golden):
     assert np.array_equal(x[more], ox) and np.array_equal(y[more], oy)
 
 
-@pytest.mark.parametrize("form,count", [(1, 1), (1, 2), (2, 0)])
+@pytest.mark.parametrize("form,count", [(1, 1), (1, 2), (1, 3), (2, 0)])
 def test_full_sir_1m(A, golden, form, count):
     g = golden["sir_1m"]
     c = g["config"]
@@ -246,7 +246,7 @@ def _sir_tuned(A, n, L, steps, chunks, tunings, seed=2, stream=6, beta=(1, 10), 
 
 SIR_FORMS = [dict(sir_form=1), dict(sir_form=1, block=64), dict(sir_form=1, block=1024),
              dict(sir_form=1, sir_count=1), dict(sir_form=1, sir_count=2),
-             dict(sir_form=1, sir_count=2, block=128),
+             dict(sir_form=1, sir_count=2, block=128), dict(sir_form=1, sir_count=3),
              dict(sir_form=2, max_groups_per_thread=1), dict(sir_form=2, max_groups_per_thread=2),
              dict(sir_form=2, max_groups_per_thread=8), dict(sir_form=0)]
 
@@ -255,7 +255,12 @@ SIR_FORMS = [dict(sir_form=1), dict(sir_form=1, block=64), dict(sir_form=1, bloc
 @pytest.mark.parametrize("tu", SIR_FORMS)
 def test_sir_launch_forms_match_oracle(A, O, n, L, tu):
     say(f"case sir form {tu} n={n} L={L}")
-    got, inv = _sir_tuned(A, n, L, 23, [23], [tu])
+    try:
+        got, inv = _sir_tuned(A, n, L, 23, [23], [tu])
+    except A.AmberError as e:
+        if e.status == A.E_UNSUPPORTED and tu.get("sir_count") == 3 and L < 12:
+            pytest.skip("exchange mode needs at least 3 bands (grid side >= 3)")
+        raise
     ref = O.OracleRun(O.SIR, n, L, seed=2, stream=6, beta=(1, 10), gamma=(1, 30)).step(23)
     assert_same(got, inv, ref, 23)
 
@@ -265,7 +270,7 @@ def test_sir_forms_mixed_across_calls(A, O):
     chunks = [1, 5, 1, 7, 2, 1, 9, 1, 4, 3]
     tunings = [dict(sir_form=2), dict(sir_form=1), dict(sir_form=1, sir_count=2), dict(sir_form=2),
                dict(sir_form=1, block=128), dict(sir_form=2, max_groups_per_thread=4),
-               dict(sir_form=0), dict(sir_count=2), dict(sir_count=1), dict(sir_count=2)]
+               dict(sir_form=0), dict(sir_count=3), dict(sir_count=1), dict(sir_count=2)]
     say("case sir mixed forms")
     got, inv = _sir_tuned(A, n, L, sum(chunks), chunks, tunings)
     ref = O.OracleRun(O.SIR, n, L, seed=2, stream=6, beta=(1, 10), gamma=(1, 30)).step(sum(chunks))
@@ -288,9 +293,38 @@ def test_block_size_invariance(A, O, model, n, block):
 def test_tuning_validation(A):
     pop = A.Population(A.RANDOM_WALK, 100, L=10)
     for bad in [dict(block=32), dict(block=1088), dict(block=100), dict(sir_form=3),
-                dict(max_groups_per_thread=3), dict(sir_count=3)]:
+                dict(max_groups_per_thread=3), dict(sir_count=4), dict(wealth_form=3)]:
         with pytest.raises(A.AmberError):
             pop.tune(**bad)
     st, t = A.amber_get_tuning(pop.handle)
     assert st == A.OK and t.block == 256
     pop.release()
+
+
+@pytest.mark.parametrize("n,w0,steps", [(8193, 1, 7), (12305, 3, 5), (100003, 1, 6),
+                                        (1 << 20, 1, 4), ((1 << 21) + 5, 1, 3)])
+@pytest.mark.parametrize("form", [1, 2])
+def test_wealth_forms_match_oracle(A, O, n, w0, steps, form):
+    say(f"case wealth form={form} n={n} w0={w0} steps={steps}")
+    pop = A.Population(A.WEALTH, n, seed=5, stream_id=n, wealth_init=w0)
+    pop.tune(wealth_form=form)
+    pop.step(steps)
+    got, inv = pop.read(), pop.invariants()
+    pop.release()
+    ref = O.OracleRun(O.WEALTH, n, seed=5, stream=n, wealth_init=w0).step(steps)
+    assert_same(got, inv, ref, steps)
+
+
+def test_wealth_forms_mixed_across_calls(A, O):
+    n = 300007
+    chunks = [1, 3, 1, 2, 5, 1]
+    forms = [2, 1, 2, 2, 1, 0]
+    say("case wealth mixed forms")
+    pop = A.Population(A.WEALTH, n, seed=8, stream_id=1, wealth_init=2)
+    for c, f in zip(chunks, forms):
+        pop.tune(wealth_form=f)
+        pop.step(c)
+    got, inv = pop.read(), pop.invariants()
+    pop.release()
+    ref = O.OracleRun(O.WEALTH, n, seed=8, stream=1, wealth_init=2).step(sum(chunks))
+    assert_same(got, inv, ref, sum(chunks))
