@@ -623,13 +623,43 @@ amber_status_t run_batch(amber_pop *const *pops, uint32_t n, uint32_t n_steps)
     amber_status_t rc = join_streams(pops, n, true);
     if (rc != AMBER_OK) return rc;
 
-    std::vector<amber_pop *> walk, wealth_small, wealth_big, sir;
+    std::vector<amber_pop *> walk, wealth_small, wealth_big, wealth_x12, wealth_x14, sir;
     for (uint32_t i = 0; i < n; ++i) {
         amber_pop *p = pops[i];
         if (p->r.model == AMBER_RANDOM_WALK) walk.push_back(p);
         else if (p->r.model == AMBER_SIR) sir.push_back(p);
         else if (p->r.n <= wealth_small_max_agents()) wealth_small.push_back(p);
+        else if (p->r.xbits == 12 && p->tuning.wealth_form != 1) wealth_x12.push_back(p);
+        else if (p->r.xbits == 14 && p->tuning.wealth_form != 1) wealth_x14.push_back(p);
         else wealth_big.push_back(p);
+    }
+    for (int which = 0; which < 2; ++which) {
+        const std::vector<amber_pop *> &runs = which ? wealth_x14 : wealth_x12;
+        const uint32_t bits = which ? 14u : 12u;
+        for (size_t c = 0; c < runs.size(); c += BATCH_RUNS) {
+            WealthXBatch b{};
+            uint32_t blocks = 0;
+            for (size_t k = c; k < runs.size() && k < c + BATCH_RUNS; ++k) {
+                amber_pop *p = runs[k];
+                const uint32_t j = b.nruns++;
+                WealthXParams &x = b.run[j];
+                x.w = col_i32(p, AMBER_COL_WEALTH);
+                for (int pb = 0; pb < 2; ++pb) {
+                    x.rec[pb] = (uint32_t *)ws_ptr(p, p->r.off_xrec[pb]);
+                    x.tab[pb] = (uint32_t *)ws_ptr(p, p->r.off_xtab[pb]);
+                }
+                x.n = p->r.n;
+                x.P = p->r.xparts;
+                x.k0 = p->r.seed;
+                x.k1 = p->r.stream;
+                b.t0[j] = (uint32_t)p->step;
+                blocks += x.P;
+                b.block_end[j] = blocks;
+            }
+            HIP_TRY(timed(lead, "wealth_exchange_batch",
+                          [&] { return launch_wealth_exchange_batch(b, n_steps, bits, st); }),
+                    "wealth exchange batch kernels");
+        }
     }
     auto blocks_for = [&](uint32_t agents) { return (groups_of_host(agents) + block - 1) / block; };
 

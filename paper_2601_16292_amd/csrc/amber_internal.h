@@ -167,6 +167,17 @@ struct WealthBatch {
     uint32_t nruns;
 };
 
+struct WealthXBatch {
+    WealthXParams run[BATCH_RUNS];
+    uint32_t t0[BATCH_RUNS];
+    uint32_t block_end[BATCH_RUNS];       // over partitions (one workgroup each)
+    uint32_t nruns;
+};
+// Partition-exchange wealth, batched: every run of the chunk uses the same
+// partition size 2^bits; launches as in the single-run path, one per step.
+hipError_t launch_wealth_exchange_batch(const WealthXBatch &b, uint32_t n_steps, uint32_t bits,
+                                        hipStream_t st);
+
 struct SirBatch {
     SirParams run[BATCH_RUNS];   // groups, quads and t_base filled in
     uint32_t t0[BATCH_RUNS];

@@ -143,3 +143,23 @@ def test_full_sir_sweep_batched(A, sweep_golden):
         for k in ("digest", "n_s", "n_i", "n_r", "step"):
             assert inv[k] == want[k], (want["stream"], k)
         p.release()
+
+
+def test_wealth_batch_forms_match_oracle(A, O):
+    """Large wealth runs in one batch, some on the atomic path and some on the
+    partition exchange (both partition sizes), at uneven step indices."""
+    say("case wealth batch forms")
+    specs = [dict(model=0, n=n, stream=200 + i, w0=1 + i % 3)
+             for i, n in enumerate([9001, 20000, 65537, 300001, (1 << 21) + 77, 12345, 40000])]
+    pops = [make(A, s) for s in specs]
+    for i, p in enumerate(pops):
+        p.tune(wealth_form=1 if i % 3 == 1 else 0)
+        if i % 2:
+            p.step(2)
+    A.step_batch(pops, 5)
+    for i, (p, s) in enumerate(zip(pops, specs)):
+        steps = 5 + (2 if i % 2 else 0)
+        ref = oracle_run(O, s, steps)
+        (w,) = p.read()
+        assert np.array_equal(w, ref.w), (i, s)
+        p.release()
