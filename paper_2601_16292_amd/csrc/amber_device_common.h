@@ -459,6 +459,79 @@ __device__ __forceinline__ uint32_t neighbour_k(const uint32_t *__restrict__ g, 
     return block_count(g, L, cx, cy);
 }
 
+// k of the susceptible agents among 4 (0 for the others).  Every load of the
+// four agents is issued before any result is used, so a wavefront waits for
+// one memory round trip instead of one per agent; a non-susceptible agent
+// reads its own cell (a valid address) and its sum is discarded.  Gather
+// mode reads each of the three rows as one 12-byte load starting at
+// clamp(x-1, 0, L-3); an agent on the first or last column (1 in L/2 of
+// agents) adds the wrapped cell with one more load.
+template <bool BOX>
+__device__ __forceinline__ void neighbour_k4(const uint32_t *__restrict__ g, int32_t L,
+                                             const uint32_t st[4], const int4 &X, const int4 &Y,
+                                             uint32_t k[4])
+{
+    const int32_t xs[4] = {X.x, X.y, X.z, X.w};
+    const int32_t ys[4] = {Y.x, Y.y, Y.z, Y.w};
+    bool use[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) use[j] = st[j] == ST_S && on_grid(xs[j], ys[j], L);
+    if (BOX) {
+        uint32_t v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t c = use[j] ? (uint32_t)ys[j] * L + (uint32_t)xs[j] : 0u;
+            v[j] = g[c];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) k[j] = use[j] ? v[j] : 0u;
+        return;
+    }
+    if (L < 3) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) k[j] = use[j] ? block_count(g, L, xs[j], ys[j]) : 0u;
+        return;
+    }
+    Cells3 r[4][3];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int32_t x = use[j] ? xs[j] : 1, y = use[j] ? ys[j] : 1;
+        const int32_t s0 = x == 0 ? 0 : (x == L - 1 ? L - 3 : x - 1);
+        const int32_t ym = y == 0 ? L - 1 : y - 1;
+        const int32_t yp = y == L - 1 ? 0 : y + 1;
+        r[j][0] = *(const Cells3 *)(g + (uint32_t)ym * L + s0);
+        r[j][1] = *(const Cells3 *)(g + (uint32_t)y * L + s0);
+        r[j][2] = *(const Cells3 *)(g + (uint32_t)yp * L + s0);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        uint32_t sum = 0;
+        const int32_t x = xs[j];
+        if (!use[j]) {
+            k[j] = 0;
+            continue;
+        }
+        if (x != 0 && x != L - 1) {
+#pragma unroll
+            for (int rr = 0; rr < 3; ++rr) sum += r[j][rr].a + r[j][rr].b + r[j][rr].c;
+        } else {
+            // first column: rows hold cells 0,1,2 and the wrapped cell is L-1;
+            // last column: rows hold L-3,L-2,L-1 and the wrapped cell is 0
+            const int32_t y = ys[j];
+            const int32_t ym = y == 0 ? L - 1 : y - 1;
+            const int32_t yp = y == L - 1 ? 0 : y + 1;
+            const uint32_t wrap = x == 0 ? (uint32_t)(L - 1) : 0u;
+            const uint32_t rows[3] = {(uint32_t)ym, (uint32_t)y, (uint32_t)yp};
+#pragma unroll
+            for (int rr = 0; rr < 3; ++rr) {
+                const uint32_t pair = x == 0 ? r[j][rr].a + r[j][rr].b : r[j][rr].b + r[j][rr].c;
+                sum += pair + g[rows[rr] * L + wrap];
+            }
+        }
+        k[j] = sum;
+    }
+}
+
 // transition(t) of agents 4q..4q+3: returns the new state word.
 template <bool BOX>
 __device__ __forceinline__ uint32_t sir_transition4(const SirParams &p,
@@ -474,12 +547,7 @@ __device__ __forceinline__ uint32_t sir_transition4(const SirParams &p,
         st[j] = (a + j < p.n) ? (S >> (8 * j)) & 0xffu : (uint32_t)ST_R;   // padding never changes
         any_sus |= st[j] == ST_S;
     }
-    if (any_sus) {
-        if (st[0] == ST_S) k[0] = neighbour_k<BOX>(count, p.L, X.x, Y.x);
-        if (st[1] == ST_S) k[1] = neighbour_k<BOX>(count, p.L, X.y, Y.y);
-        if (st[2] == ST_S) k[2] = neighbour_k<BOX>(count, p.L, X.z, Y.z);
-        if (st[3] == ST_S) k[3] = neighbour_k<BOX>(count, p.L, X.w, Y.w);
-    }
+    if (any_sus) neighbour_k4<BOX>(count, p.L, st, X, Y, k);
 #pragma unroll
     for (int j = 0; j < 4; ++j) need |= (st[j] == ST_S && k[j] > 0) || st[j] == ST_I;
     if (!need) return S;
