@@ -26,7 +26,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, vendor figure
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2601_16292_amd", "csrc", f)
-                  for f in ("amber_device.hip",)]
+                  for f in ("amber_device.hip", "amber_device_common.h", "amber_internal.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.json")
 
 
@@ -76,7 +76,7 @@ def timed_steps(torch, pop, steps, chunk):
     return max(wall, ev0.elapsed_time(ev1) / 1e3)
 
 
-def sir_bench(torch, A, W, K, chunk, form, count=0, tuning=None):
+def sir_bench(torch, A, W, K, chunk, form, count=0, tuning=None, block=256):
     from paper_2601_16292_amd import workloads as WL
     c = WL.SIR_1M
 
@@ -86,7 +86,7 @@ def sir_bench(torch, A, W, K, chunk, form, count=0, tuning=None):
         if tuning:
             p.tune(**tuning)
         else:
-            p.tune(sir_form=form, sir_count=count)
+            p.tune(block=block, sir_form=form, sir_count=count)
         return p
 
     pop = mk()
@@ -308,6 +308,8 @@ def main():
     ap.add_argument("--sir-count", choices=["auto", "gather", "box", "exchange"], default="auto")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="use --sir-form/--sir-count instead of the autotuner's choice")
+    ap.add_argument("--block", type=int, default=256,
+                    help="threads per workgroup when --no-autotune is given")
     ap.add_argument("--no-sweep", action="store_true", help="skip the 256-replicate sweep")
     ap.add_argument("--roofline-big", action="store_true",
                     help="also time the per-step kernels at an out-of-cache size")
@@ -356,7 +358,7 @@ def main():
                          force=True, log=log)
         log(f"bench: autotuned {tuning}")
     secs, inv, times, infected = sir_bench(torch, A, args.warmup, args.steps, args.chunk, form,
-                                           count, tuning)
+                                           count, tuning, args.block)
     value = n * args.steps / secs
     log(f"bench: {value:.4g} agent-steps/s, {secs * 1e3 / args.steps:.4f} ms/step, kernels {times}")
 
@@ -397,7 +399,8 @@ def main():
                    "n_agents": n, "grid_side": L, "timed_steps": f"{args.warmup}..{args.warmup + args.steps - 1}",
                    "chunk": args.chunk or args.steps,
                    "tuning": tuning if tuning else {"sir_form": args.sir_form,
-                                                     "sir_count": args.sir_count}},
+                                                     "sir_count": args.sir_count,
+                                                     "block": args.block}},
         "final_invariants": {k: inv[k] for k in ("step", "n_s", "n_i", "n_r", "digest")},
         "kernels": kernels,
         "roofline": roof,

@@ -238,9 +238,13 @@ typedef struct {
     double   total_ms;
 } amber_kernel_time_t;
 
-/* Measurement aid: while enabled, every kernel the handle enqueues is
- * bracketed by HIP events on the handle's stream.  Enabling waits for the
- * stream and clears the totals.  Off by default; results are unaffected. */
+/* Measurement aid: while enabled, the kernels the handle enqueues are timed
+ * with HIP events on the handle's stream.  Consecutive launches of one kernel
+ * within one call share a single pair of events (one before the first, one
+ * after the last), so total_ms / launches is the back-to-back time per launch
+ * and no event sits between them; a kernel launched alone gets its own pair.
+ * Enabling waits for the stream and clears the totals.  Off by default;
+ * results are unaffected. */
 AMBER_API amber_status_t amber_profile_enable(amber_pop_t *pop, int enable);
 
 /* Waits for the stream, folds the recorded events into per-kernel totals and

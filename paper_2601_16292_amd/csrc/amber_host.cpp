@@ -309,9 +309,11 @@ struct KernelTimer {
     bool on = false;
     struct Pending {
         uint32_t kernel;
+        uint32_t count;          // launches between start and stop
         hipEvent_t start, stop;
     };
     std::vector<Pending> pending;
+    bool chain = false;          // the last pending pair may be extended
     std::vector<hipEvent_t> pool;
     std::vector<std::string> names;
     std::vector<uint64_t> launches;
@@ -397,21 +399,50 @@ amber_status_t check_device_flag(amber_pop *p, uint32_t flag)
                                 "the run's state is invalid");
 }
 
-// Launch one kernel through f(), bracketed by timing events when enabled.
+// Record the stop event of the open run of launches, if any.
+hipError_t timer_close(amber_pop *p)
+{
+    KernelTimer &tm = p->timer;
+    if (!tm.chain) return hipSuccess;
+    tm.chain = false;
+    return hipEventRecord(tm.pending.back().stop, p->stream);
+}
+
+// Launch one kernel through f(), timed with events when enabled.  A run of
+// launches of one kernel shares one pair of events: the start goes before the
+// first and the stop after the last, once the run ends.
 template <class F>
 hipError_t timed(amber_pop *p, const char *name, F &&f)
 {
     KernelTimer &tm = p->timer;
     if (!tm.on) return f();
+    const uint32_t k = tm.id(name);
+    hipError_t e;
+    if (tm.chain && !tm.pending.empty() && tm.pending.back().kernel == k) {
+        // same kernel again, nothing enqueued in between: extend the open run
+        if ((e = f()) != hipSuccess) return e;
+        tm.pending.back().count += 1;
+        return hipSuccess;
+    }
+    if ((e = timer_close(p)) != hipSuccess) return e;
     hipEvent_t a, b;
-    hipError_t e = tm.event(&a);
-    if (e != hipSuccess) return e;
+    if ((e = tm.event(&a)) != hipSuccess) return e;
     if ((e = tm.event(&b)) != hipSuccess) return e;
     if ((e = hipEventRecord(a, p->stream)) != hipSuccess) return e;
+    tm.pending.push_back({k, 0u, a, b});
+    tm.chain = true;
     if ((e = f()) != hipSuccess) return e;
-    if ((e = hipEventRecord(b, p->stream)) != hipSuccess) return e;
-    tm.pending.push_back({tm.id(name), a, b});
+    tm.pending.back().count = 1;
     return hipSuccess;
+}
+
+// Untimed work follows (or may follow) on the stream: close the open run, so
+// the next timed launch opens a new pair of events.
+hipError_t timer_cut(amber_pop *p)
+{
+    hipError_t e = timer_close(p);
+    p->timer.chain = false;
+    return e;
 }
 
 int32_t *col_i32(amber_pop *p, amber_col_t c) { return (int32_t *)p->b.col[c]; }
@@ -542,7 +573,9 @@ amber_status_t enqueue_steps(amber_pop *p, uint32_t n_steps)
                                                            blocks, st);
                           }),
                     "sir persistent kernel");
-            HIP_TRY(launch_sir_clear(sp, 1u << ((n_steps - 1) % 3), st), "sir clear kernel");
+            HIP_TRY(timed(p, "sir_clear",
+                          [&] { return launch_sir_clear(sp, 1u << ((n_steps - 1) % 3), st); }),
+                    "sir clear kernel");
         } else if (tu.sir_count == 3 && !r.sx_P) {
             return fail(AMBER_E_UNSUPPORTED, "the exchange count mode does not fit this run "
                                              "(grid side %u, %u agents)", r.L, r.n);
@@ -561,7 +594,9 @@ amber_status_t enqueue_steps(amber_pop *p, uint32_t n_steps)
             HIP_TRY(timed(p, "sir_tail_box",
                           [&] { return launch_sir_tail(sp, t0 + n_steps - 1, true, tu, st); }),
                     "sir tail kernel");
-            HIP_TRY(launch_sir_clear(sp, 4u, st), "sir clear kernel");
+            HIP_TRY(timed(p, "sir_clear",
+                          [&] { return launch_sir_clear(sp, 4u, st); }),
+                    "sir clear kernel");
         } else if (sir_box_mode(p)) {
             HIP_TRY(timed(p, "sir_head", [&] { return launch_sir_head(sp, t0, true, tu, st); }),
                     "sir head kernel");
@@ -577,7 +612,9 @@ amber_status_t enqueue_steps(amber_pop *p, uint32_t n_steps)
             HIP_TRY(timed(p, "sir_tail_box",
                           [&] { return launch_sir_tail(sp, t0 + n_steps - 1, true, tu, st); }),
                     "sir tail kernel");
-            HIP_TRY(launch_sir_clear(sp, (1u << ((n_steps - 1) & 1)) | 4u, st), "sir clear kernel");
+            HIP_TRY(timed(p, "sir_clear",
+                          [&] { return launch_sir_clear(sp, (1u << ((n_steps - 1) & 1)) | 4u, st); }),
+                    "sir clear kernel");
         } else {
             HIP_TRY(timed(p, "sir_head", [&] { return launch_sir_head(sp, t0, false, tu, st); }),
                     "sir head kernel");
@@ -588,7 +625,9 @@ amber_status_t enqueue_steps(amber_pop *p, uint32_t n_steps)
             HIP_TRY(timed(p, "sir_tail",
                           [&] { return launch_sir_tail(sp, t0 + n_steps - 1, false, tu, st); }),
                     "sir tail kernel");
-            HIP_TRY(launch_sir_clear(sp, 1u << ((n_steps - 1) % 3), st), "sir clear kernel");
+            HIP_TRY(timed(p, "sir_clear",
+                          [&] { return launch_sir_clear(sp, 1u << ((n_steps - 1) % 3), st); }),
+                    "sir clear kernel");
         }
     }
     return AMBER_OK;
@@ -870,7 +909,9 @@ amber_status_t amber_step(amber_pop_t *pop, uint32_t n_steps)
     if (pop->step + n_steps > 0xffffffffull)
         return fail(AMBER_E_INVALID, "step index would exceed 2^32-1");
     amber_status_t st = enqueue_steps(pop, n_steps);
+    const hipError_t te = timer_cut(pop);
     if (st != AMBER_OK) return st;
+    if (te != hipSuccess) return hip_fail(te, "timing event");
     pop->step += n_steps;
     return AMBER_OK;
 }
@@ -889,7 +930,13 @@ amber_status_t amber_step_batch(amber_pop_t *const *pops, uint32_t n, uint32_t n
     }
     if (n == 0 || n_steps == 0) return AMBER_OK;
     amber_status_t st = run_batch(pops, n, n_steps);
+    hipError_t te = hipSuccess;
+    for (uint32_t i = 0; i < n; ++i) {
+        const hipError_t e = timer_cut(pops[i]);
+        if (te == hipSuccess) te = e;
+    }
     if (st != AMBER_OK) return st;
+    if (te != hipSuccess) return hip_fail(te, "timing event");
     for (uint32_t i = 0; i < n; ++i) pops[i]->step += n_steps;
     return AMBER_OK;
 }
@@ -1013,7 +1060,7 @@ amber_status_t amber_profile_enable(amber_pop_t *pop, int enable)
 {
     if (!is_live(pop)) return fail(AMBER_E_STATE, "unknown or released handle");
     KernelTimer &tm = pop->timer;
-    if (enable && !tm.on) {
+    if (enable) {
         HIP_TRY(hipStreamSynchronize(pop->stream), "stream synchronize");
         for (auto &p : tm.pending) {
             tm.pool.push_back(p.start);
@@ -1037,7 +1084,7 @@ amber_status_t amber_profile_read(amber_pop_t *pop, amber_kernel_time_t *out, ui
     for (auto &p : tm.pending) {
         float ms = 0.f;
         HIP_TRY(hipEventElapsedTime(&ms, p.start, p.stop), "hipEventElapsedTime");
-        tm.launches[p.kernel] += 1;
+        tm.launches[p.kernel] += p.count;
         tm.total_ms[p.kernel] += ms;
         tm.pool.push_back(p.start);
         tm.pool.push_back(p.stop);
