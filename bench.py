@@ -26,7 +26,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, vendor figure
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2601_16292_amd", "csrc", f)
-                  for f in ("amber_device.hip", "amber_device_common.h", "amber_internal.h")]
+                  for f in ("amber_device.hip", "amber_device_common.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.json")
 
 
@@ -50,6 +50,12 @@ def sir_step_bytes(n, L, infected):
     (2 B/agent), the L*L count grid cleared once and read once (8 B/cell) and
     one 8-B read-modify-write per infected agent."""
     return 18 * n + 8 * L * L + 8 * infected
+
+
+def tile_step_bytes(n, L):
+    """Bytes one step of the tiled SIR mode must move: each agent's 8-byte
+    record read and written, and the L*L count grid written and read once."""
+    return 16 * n + 8 * L * L
 
 
 def wealth_step_bytes(n, donors):
@@ -76,7 +82,7 @@ def timed_steps(torch, pop, steps, chunk):
     return max(wall, ev0.elapsed_time(ev1) / 1e3)
 
 
-def sir_bench(torch, A, W, K, chunk, form, count=0, tuning=None, block=256):
+def sir_bench(torch, A, W, K, chunk, form, count=0, tuning=None, block=256, tile=0):
     from paper_2601_16292_amd import workloads as WL
     c = WL.SIR_1M
 
@@ -86,7 +92,7 @@ def sir_bench(torch, A, W, K, chunk, form, count=0, tuning=None, block=256):
         if tuning:
             p.tune(**tuning)
         else:
-            p.tune(block=block, sir_form=form, sir_count=count)
+            p.tune(block=block, sir_form=form, sir_count=count, sir_tile=tile)
         return p
 
     pop = mk()
@@ -305,7 +311,10 @@ def main():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--sir-form", choices=["auto", "pipelined", "persistent"], default="auto")
-    ap.add_argument("--sir-count", choices=["auto", "gather", "box", "exchange"], default="auto")
+    ap.add_argument("--sir-count", choices=["auto", "gather", "box", "exchange", "tiled"],
+                    default="auto")
+    ap.add_argument("--sir-tile", type=int, default=0, choices=[0, 32, 64],
+                    help="tile side of the tiled count mode (0 = automatic)")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="use --sir-form/--sir-count instead of the autotuner's choice")
     ap.add_argument("--block", type=int, default=256,
@@ -348,7 +357,7 @@ def main():
 
     n, L = 1_000_000, 1000
     form = {"auto": 0, "pipelined": 1, "persistent": 2}[args.sir_form]
-    count = {"auto": 0, "gather": 1, "box": 2, "exchange": 3}[args.sir_count]
+    count = {"auto": 0, "gather": 1, "box": 2, "exchange": 3, "tiled": 4}[args.sir_count]
     log(f"bench: SIR N={n} L={L} warmup={args.warmup} steps={args.steps} form={args.sir_form} "
         f"count={args.sir_count}")
     tuning = None
@@ -358,7 +367,7 @@ def main():
                          force=True, log=log)
         log(f"bench: autotuned {tuning}")
     secs, inv, times, infected = sir_bench(torch, A, args.warmup, args.steps, args.chunk, form,
-                                           count, tuning, args.block)
+                                           count, tuning, args.block, args.sir_tile)
     value = n * args.steps / secs
     log(f"bench: {value:.4g} agent-steps/s, {secs * 1e3 / args.steps:.4f} ms/step, kernels {times}")
 
@@ -372,6 +381,10 @@ def main():
     if "sir_xbody" in times:                                # exchange mode: grid bytes go to sir_xcount
         priced["sir_xbody"] = sum(b - 8 * L * L for b in step_bytes)
         priced["sir_xcount"] = 8 * L * L * len(step_bytes)
+    if "sir_tile_body" in times:
+        # tiled mode keeps 8-byte records instead of the columns: priced on the
+        # bytes it must move (records read and written, count grid written and read)
+        priced["sir_tile_body"] = tile_step_bytes(n, L) * (len(step_bytes) - 1)
     if "sir_body_box" in times:                             # box mode: grid bytes go to sir_box
         priced["sir_body_box"] = sum(b - 8 * L * L for b in step_bytes[1:])
         priced["sir_box"] = 8 * L * L * len(step_bytes)
@@ -400,6 +413,7 @@ def main():
                    "chunk": args.chunk or args.steps,
                    "tuning": tuning if tuning else {"sir_form": args.sir_form,
                                                      "sir_count": args.sir_count,
+                                                     "sir_tile": args.sir_tile,
                                                      "block": args.block}},
         "final_invariants": {k: inv[k] for k in ("step", "n_s", "n_i", "n_r", "digest")},
         "kernels": kernels,

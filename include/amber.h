@@ -218,13 +218,21 @@ typedef struct {
                                   per band into the box-summed grid, with no
                                   global atomics (AMBER_E_UNSUPPORTED when the
                                   grid is too small or too wide for it; inside
-                                  amber_step_batch such runs use mode 1)          */
+                                  amber_step_batch such runs use mode 1),
+                                  4 = tiled: during a call the agents live as
+                                  records sorted by grid tile, one workgroup per
+                                  tile bins and sums the counts in LDS (needs a
+                                  grid side of at least 2 x tile + 2, else
+                                  AMBER_E_UNSUPPORTED; inside amber_step_batch
+                                  such runs use the automatic mode)              */
     uint32_t wealth_form;      /* WEALTH above 8192 agents: 0 = automatic,
                                   1 = global atomic scatter-add, 2 = partition
                                   exchange (recipient ids counting-sorted by
                                   destination in LDS, counted by the owner;
                                   AMBER_E_UNSUPPORTED above 2^24 agents)         */
-    uint32_t reserved[3];
+    uint32_t sir_tile;         /* tiled count mode: tile side 32 or 64 cells
+                                  (0 = automatic)                                 */
+    uint32_t reserved[2];
 } amber_tuning_t;
 
 /* Set / get a handle's launch-shape knobs (host only). */

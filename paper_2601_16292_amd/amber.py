@@ -73,11 +73,12 @@ class PopInfo(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("block", ctypes.c_uint32), ("sir_form", ctypes.c_uint32),
                 ("max_groups_per_thread", ctypes.c_uint32), ("sir_count", ctypes.c_uint32),
-                ("wealth_form", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 3)]
+                ("wealth_form", ctypes.c_uint32), ("sir_tile", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 2)]
 
 
 SIR_AUTO, SIR_PIPELINED, SIR_PERSISTENT = 0, 1, 2
-COUNT_AUTO, COUNT_GATHER, COUNT_BOX, COUNT_EXCHANGE = 0, 1, 2, 3
+COUNT_AUTO, COUNT_GATHER, COUNT_BOX, COUNT_EXCHANGE, COUNT_TILED = 0, 1, 2, 3, 4
 WEALTH_AUTO, WEALTH_ATOMIC, WEALTH_EXCHANGE = 0, 1, 2
 
 
@@ -220,8 +221,8 @@ def amber_pop_info(handle):
 
 
 def amber_set_tuning(handle, block=256, sir_form=SIR_AUTO, max_groups_per_thread=0,
-                     sir_count=COUNT_AUTO, wealth_form=WEALTH_AUTO):
-    t = Tuning(block, sir_form, max_groups_per_thread, sir_count, wealth_form)
+                     sir_count=COUNT_AUTO, wealth_form=WEALTH_AUTO, sir_tile=0):
+    t = Tuning(block, sir_form, max_groups_per_thread, sir_count, wealth_form, sir_tile)
     return lib().amber_set_tuning(handle, ctypes.byref(t))
 
 
@@ -331,9 +332,9 @@ class Population:
         return [outs[c] for c in MODEL_COLUMNS[self.model]]
 
     def tune(self, block=256, sir_form=SIR_AUTO, max_groups_per_thread=0, sir_count=COUNT_AUTO,
-             wealth_form=WEALTH_AUTO):
+             wealth_form=WEALTH_AUTO, sir_tile=0):
         check(amber_set_tuning(self.handle, block, sir_form, max_groups_per_thread, sir_count,
-                               wealth_form))
+                               wealth_form, sir_tile))
         return self
 
     def profile(self, enable=True):

@@ -208,6 +208,10 @@ struct Resolved {
     uint32_t sx_h = 0, sx_P = 0, sx_W = 0;          // SIR exchange count mode (0 = unavailable)
     uint64_t off_sxrec = 0, off_sxtab = 0;
     uint64_t off_xrec[2] = {0, 0}, off_xtab[2] = {0, 0};
+    // SIR tiled count mode (tile_tiles = 0: unavailable)
+    uint32_t tile_tiles = 0;                        // tiles of the smallest side the buffers fit
+    uint64_t off_trec[2] = {0, 0}, off_thdr[2] = {0, 0}, off_tring[2] = {0, 0};
+    uint64_t off_tcur = 0, off_tctr = 0;
     uint64_t ws_bytes = 0;
 };
 
@@ -280,6 +284,24 @@ amber_status_t resolve(const amber_run_desc_t *d, Resolved &r, bool want_table)
                 ws += align_up((uint64_t)r.sx_W * XSEG_WORDS * 4, 256);
                 r.off_sxtab = ws;
                 ws += align_up((uint64_t)r.sx_W * r.sx_P * 4, 256);
+            }
+            const uint32_t nt = sir_tile_count(L, TILE_MIN);
+            if (nt) {
+                // records, headers and ring arrays of both generations, sized
+                // for the smallest tile side (larger tiles need less)
+                r.tile_tiles = nt * nt;
+                for (int b = 0; b < 2; ++b) {
+                    r.off_trec[b] = ws;
+                    ws += align_up((uint64_t)r.n * 8, 256);
+                    r.off_thdr[b] = ws;
+                    ws += align_up((uint64_t)r.tile_tiles * TILE_HDR * 4, 256);
+                    r.off_tring[b] = ws;
+                    ws += align_up(sir_tile_ring_words(L) * 4, 256);
+                }
+                r.off_tcur = ws;
+                ws += align_up((uint64_t)r.tile_tiles * 4, 256);
+                r.off_tctr = ws;
+                ws += 512;
             }
         }
     }
@@ -395,6 +417,9 @@ amber_status_t check_device_flag(amber_pop *p, uint32_t flag)
     const uint32_t zero = 0;
     HIP_TRY(hipMemcpy((uint8_t *)p->b.workspace + ERR_FLAG_OFFSET, &zero, 4, hipMemcpyHostToDevice),
             "error flag clear");
+    if (flag & ERR_TILE_LISTS)
+        return fail(AMBER_E_DEVICE, "the tiled SIR mode found its record lists out of range; "
+                                    "the run's state is invalid");
     return fail(AMBER_E_DEVICE, "a device-wide barrier of the persistent SIR form timed out; "
                                 "the run's state is invalid");
 }
@@ -475,12 +500,81 @@ SirParams sir_params(amber_pop *p)
 }
 
 // SIR neighbour-count mode of the pipelined form: 1 gather, 2 box, 3 exchange.
+uint32_t sir_auto_count_mode(const amber_pop *p)
+{
+    return (uint64_t)p->r.L * p->r.L > (16ull << 20) ? 2u : 1u;
+}
+
+// Tile side of the tiled mode for this run (0 when it does not fit).
+uint32_t sir_tile_side(const amber_pop *p)
+{
+    const uint32_t want = p->tuning.sir_tile ? p->tuning.sir_tile : TILE_MIN;
+    const uint32_t nt = sir_tile_count(p->r.L, want);
+    if (!nt || !p->r.tile_tiles) return 0;
+    const uint64_t rs = 4ull * want + 8;
+    if ((uint64_t)nt * nt > p->r.tile_tiles ||
+        (uint64_t)nt * nt * rs > sir_tile_ring_words(p->r.L))
+        return 0;
+    return want;
+}
+
 uint32_t sir_count_mode(const amber_pop *p)
 {
     const uint32_t want = p->tuning.sir_count;
     if (want == 3) return p->r.sx_P ? 3u : 0u;    // 0: unavailable, caller reports it
+    if (want == 4) return sir_tile_side(p) ? 4u : 0u;
     if (want == 1 || want == 2) return want;
-    return (uint64_t)p->r.L * p->r.L > (16ull << 20) ? 2u : 1u;
+    return sir_auto_count_mode(p);
+}
+
+// Count mode of a run inside amber_step_batch (the batched kernels have the
+// gather, box and exchange modes).
+uint32_t sir_batch_count_mode(const amber_pop *p)
+{
+    const uint32_t m = sir_count_mode(p);
+    if (m == 4) return sir_auto_count_mode(p);
+    return m == 0 ? 1u : m;     // exchange requested but unavailable: gather
+}
+
+TileParams tile_params(amber_pop *p, uint32_t T)
+{
+    const Resolved &r = p->r;
+    TileParams tp{};
+    tp.x = col_i32(p, AMBER_COL_X);
+    tp.y = col_i32(p, AMBER_COL_Y);
+    tp.s = (uint8_t *)p->b.col[AMBER_COL_STATE];
+    tp.t_inf = (const uint32_t *)ws_ptr(p, r.off_table);
+    tp.table_len = (uint32_t)r.t_inf.size();
+    tp.t_rec = r.t_rec;
+    tp.n = r.n;
+    tp.k0 = r.seed;
+    tp.k1 = r.stream;
+    tp.L = (int32_t)r.L;
+    tp.T = T;
+    tp.tshift = T == 64 ? 6u : 5u;
+    tp.nT = sir_tile_count(r.L, T);
+    tp.rs = 4 * T + 8;
+    for (int b = 0; b < 2; ++b) {
+        tp.rec[b] = (uint2 *)ws_ptr(p, r.off_trec[b]);
+        tp.hdr[b] = (uint32_t *)ws_ptr(p, r.off_thdr[b]);
+        tp.C[b] = (uint32_t *)ws_ptr(p, r.off_count[b]);
+        tp.ring[b] = (uint32_t *)ws_ptr(p, r.off_tring[b]);
+    }
+    tp.cursor = (uint32_t *)ws_ptr(p, r.off_tcur);
+    tp.ctr = (uint32_t *)ws_ptr(p, r.off_tctr);
+    tp.err = (uint32_t *)ws_ptr(p, ERR_FLAG_OFFSET);
+    return tp;
+}
+
+// Threads per tile workgroup: the tuned block, raised so that a tile of
+// average occupancy plus a margin fits one round of 8 records per thread.
+uint32_t tile_block(const amber_pop *p, const TileParams &tp)
+{
+    const uint64_t tiles = (uint64_t)tp.nT * tp.nT;
+    const uint64_t want = (p->r.n * 5ull / 4 + tiles - 1) / tiles / 8 + 1;
+    uint32_t b = 64;
+    while (b < want && b < 1024) b *= 2;
+    return std::max(b, p->tuning.block);
 }
 
 // Automatic choice: the box mode once the grid no longer fits the
@@ -579,6 +673,27 @@ amber_status_t enqueue_steps(amber_pop *p, uint32_t n_steps)
         } else if (tu.sir_count == 3 && !r.sx_P) {
             return fail(AMBER_E_UNSUPPORTED, "the exchange count mode does not fit this run "
                                              "(grid side %u, %u agents)", r.L, r.n);
+        } else if (tu.sir_count == 4 && !sir_tile_side(p)) {
+            return fail(AMBER_E_UNSUPPORTED, "the tiled count mode needs a grid side of at least "
+                                             "2 x tile + 2 (grid side %u, tile %u)",
+                        r.L, tu.sir_tile ? tu.sir_tile : TILE_MIN);
+        } else if (sir_count_mode(p) == 4) {
+            const TileParams tp = tile_params(p, sir_tile_side(p));
+            const uint32_t blk = tile_block(p, tp);
+            HIP_TRY(timed(p, "sir_tile_sort", [&] { return launch_sir_tile_sort(tp, st); }),
+                    "sir tile sort kernels");
+            for (uint32_t i = 0; i <= n_steps; ++i) {
+                const char *name = i == 0 ? "sir_tile_head"
+                                          : (i == n_steps ? "sir_tile_tail" : "sir_tile_body");
+                HIP_TRY(timed(p, name,
+                              [&] { return launch_sir_tile_step(tp, t0, i, n_steps, blk, st); }),
+                        "sir tile step kernel");
+            }
+            // the two count grids it used go back to zero, as the other modes expect
+            const uint64_t words = (r.off_count[2] - r.off_count[0]) / 4;
+            HIP_TRY(timed(p, "sir_clear",
+                          [&] { return launch_zero_words(tp.C[0], words, st); }),
+                    "sir clear kernel");
         } else if (sir_count_mode(p) == 3) {
             HIP_TRY(timed(p, "sir_xbody", [&] { return launch_sir_xbody(sp, t0, false, st); }),
                     "sir exchange body kernel");
@@ -760,9 +875,7 @@ amber_status_t run_batch(amber_pop *const *pops, uint32_t n, uint32_t n_steps)
     for (uint32_t mode = 1; mode <= 3; ++mode) {
         std::vector<amber_pop *> runs;
         for (amber_pop *p : sir) {
-            uint32_t m = sir_count_mode(p);
-            if (m == 0) m = 1;     // exchange requested but unavailable: gather (same results)
-            if (m == mode) runs.push_back(p);
+            if (sir_batch_count_mode(p) == mode) runs.push_back(p);
         }
         for (size_t c = 0; c < runs.size(); c += BATCH_RUNS) {
             SirBatch b{};
@@ -1033,8 +1146,11 @@ amber_status_t amber_set_tuning(amber_pop_t *pop, const amber_tuning_t *t)
         t->max_groups_per_thread != 2 && t->max_groups_per_thread != 4 &&
         t->max_groups_per_thread != 8)
         return fail(AMBER_E_INVALID, "max_groups_per_thread must be 0, 1, 2, 4 or 8");
-    if (t->sir_count > 3) return fail(AMBER_E_INVALID, "sir_count must be 0, 1, 2 or 3");
+    if (t->sir_count > 4) return fail(AMBER_E_INVALID, "sir_count must be 0, 1, 2, 3 or 4");
     if (t->wealth_form > 2) return fail(AMBER_E_INVALID, "wealth_form must be 0, 1 or 2");
+    if (t->sir_tile != 0 && t->sir_tile != 32 && t->sir_tile != 64)
+        return fail(AMBER_E_INVALID, "sir_tile must be 0, 32 or 64");
+    pop->tuning.sir_tile = t->sir_tile;
     pop->tuning.wealth_form = t->wealth_form;
     pop->tuning.block = t->block;
     pop->tuning.sir_form = t->sir_form;
@@ -1053,6 +1169,7 @@ amber_status_t amber_get_tuning(const amber_pop_t *pop, amber_tuning_t *t)
     t->max_groups_per_thread = pop->tuning.max_g;
     t->sir_count = pop->tuning.sir_count;
     t->wealth_form = pop->tuning.wealth_form;
+    t->sir_tile = pop->tuning.sir_tile;
     return AMBER_OK;
 }
 

@@ -73,8 +73,10 @@ struct Tuning {
     uint32_t sir_form = 0;     // 0 = automatic, 1 = pipelined, 2 = persistent
     uint32_t max_g = 8;        // persistent form: largest groups-per-thread to try
     uint32_t sir_count = 0;    // 0 = automatic, 1 = gather 3x3 cells, 2 = box-summed grid,
-                               // 3 = exchange (sorted records, per-band counts)
+                               // 3 = exchange (sorted records, per-band counts),
+                               // 4 = tiled (tile-sorted working copy, counts in LDS)
     uint32_t wealth_form = 0;  // 0 = automatic, 1 = atomic scatter, 2 = partition exchange
+    uint32_t sir_tile = 0;     // tiled mode: tile side 32 or 64 (0 = automatic)
 };
 
 hipError_t launch_init_wealth(int32_t *w, int32_t *inc0, int32_t *inc1, uint32_t n,
@@ -137,6 +139,46 @@ hipError_t launch_sir_xcount(SirParams p, hipStream_t st);
 uint32_t sir_persistent_groups_per_thread(uint32_t n, uint32_t max_g, uint32_t *blocks);
 hipError_t launch_sir_persistent(SirParams p, uint32_t *sync_words, uint32_t *err, uint32_t t0,
                                  uint32_t n_steps, uint32_t g, uint32_t blocks, hipStream_t st);
+
+// SIR, tiled count mode.  The grid is cut into nT x nT tiles of T x T cells
+// (T = 32 or 64); the last tile of each axis is L - (nT-1)*T cells wide,
+// which nT = (L-2)/T + 1 keeps within [2, T+1].  The mode needs nT >= 3.
+// During a call each agent is one record {id, lx | ly << 10 | state << 20}
+// (lx, ly relative to the tile holding the agent) in its tile's record list;
+// one workgroup per tile runs each step.  Two generations g = 0, 1 of every
+// buffer alternate with the step of the call.
+constexpr uint32_t TILE_HDR = 10;         // per tile: output base, 9 group counts
+constexpr uint32_t TILE_MIN = 32;         // smallest tile side (sizes the buffers)
+struct TileParams {
+    int32_t *x;
+    int32_t *y;
+    uint8_t *s;
+    const uint32_t *t_inf;
+    uint32_t table_len, t_rec, n, k0, k1;
+    int32_t L;
+    uint32_t T, tshift, nT;
+    uint32_t rs;               // ring words per tile: 4T + 8
+    uint2 *rec[2];             // records, n per generation
+    uint32_t *hdr[2];          // TILE_HDR words per tile
+    uint32_t *C[2];            // L*L interior infected counts
+    uint32_t *ring[2];         // rs words per tile: infected counts on the ring around it
+    uint32_t *cursor;          // one word per tile (initial sort)
+    uint32_t *ctr;             // record allocators: ctr[0] and ctr[64]
+    uint32_t *err;             // sticky device error word: bit ERR_TILE_LISTS
+};
+// Bits of the sticky device error word at ERR_FLAG_OFFSET.
+constexpr uint32_t ERR_BARRIER = 1u;      // a persistent-form barrier wait gave up
+constexpr uint32_t ERR_TILE_LISTS = 2u;   // tiled mode: record lists out of range
+// Tile count per axis for side T (0 when the grid is too small for it).
+uint32_t sir_tile_count(uint32_t L, uint32_t T);
+// Words of the tiled buffers for grid side L with the smallest tile side.
+uint64_t sir_tile_ring_words(uint32_t L);
+// A call of n steps: sort (columns -> records, generation 0), then step(i)
+// for i = 0 .. n with i = 0 the head (move + bin only) and i = n the tail
+// (transition, then records -> columns).
+hipError_t launch_sir_tile_sort(const TileParams &p, hipStream_t st);
+hipError_t launch_sir_tile_step(const TileParams &p, uint32_t t0, uint32_t i, uint32_t n,
+                                uint32_t block, hipStream_t st);
 
 // ------------------------------------------------------------------ batches
 // Run tables of the batched launches, passed by value as kernel arguments.
