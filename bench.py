@@ -284,6 +284,29 @@ def roofline_big(torch, A, log2n):
         res[f"sir_body_{label}"] = entry
         pop.release()
         torch.cuda.empty_cache()
+
+    # SIR tiled mode: records sorted by tile, counts in LDS.  Priced on the
+    # bytes it must move (16 B per agent, 8 B per cell); step_GBs prices the
+    # same launch with the method's algorithmic bytes, as for the other modes
+    for tile in (32, 64):
+        pop = A.Population(A.SIR, n, L=0, beta=(1, 20), gamma=(1, 100))
+        L = pop.info().grid_side
+        pop.tune(sir_form=1, sir_count=4, sir_tile=tile)
+        pop.step(30)
+        i_t = pop.invariants()["n_i"]
+        pop.profile(True)
+        pop.step(2)        # the body is step 31
+        times = pop.kernel_times()
+        entry = priced("sir_tile_body", times, tile_step_bytes(n, L))
+        step_bytes = 18 * n + 8 * L * L + 8 * i_t
+        avg = times["sir_tile_body"][1] / times["sir_tile_body"][0] / 1e3
+        entry["step_GBs"] = round(step_bytes / avg / 1e9, 1)
+        entry["step_frac_of_hbm_peak"] = round(step_bytes / avg / 1e9 / PEAK_HBM_GBS, 4)
+        entry["call_kernels_us"] = {k: round(v[1] / max(1, v[0]) * 1e3, 1) for k, v in times.items()}
+        entry.update({"grid_side": L, "infected": i_t, "tile": tile})
+        res[f"sir_body_tiled{tile}"] = entry
+        pop.release()
+        torch.cuda.empty_cache()
     return res
 
 

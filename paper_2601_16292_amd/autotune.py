@@ -40,6 +40,10 @@ def candidates(model, n):
         for count in (A.COUNT_GATHER, A.COUNT_BOX, A.COUNT_EXCHANGE):
             for block in (128, 256, 512):
                 out.append(dict(sir_form=A.SIR_PIPELINED, sir_count=count, block=block))
+        for tile, blocks in ((32, (256, 512)), (64, (512, 1024))):
+            for block in blocks:
+                out.append(dict(sir_form=A.SIR_PIPELINED, sir_count=A.COUNT_TILED,
+                                sir_tile=tile, block=block))
         for g in (2, 4, 8):
             out.append(dict(sir_form=A.SIR_PERSISTENT, max_groups_per_thread=g))
         return out

@@ -210,6 +210,7 @@ struct Resolved {
     uint64_t off_xrec[2] = {0, 0}, off_xtab[2] = {0, 0};
     // SIR tiled count mode (tile_tiles = 0: unavailable)
     uint32_t tile_tiles = 0;                        // tiles of the smallest side the buffers fit
+    uint64_t tile_rec = 0;                          // record slots per generation
     uint64_t off_trec[2] = {0, 0}, off_thdr[2] = {0, 0}, off_tring[2] = {0, 0};
     uint64_t off_tcur = 0, off_tctr = 0;
     uint64_t ws_bytes = 0;
@@ -286,13 +287,20 @@ amber_status_t resolve(const amber_run_desc_t *d, Resolved &r, bool want_table)
                 ws += align_up((uint64_t)r.sx_W * r.sx_P * 4, 256);
             }
             const uint32_t nt = sir_tile_count(L, TILE_MIN);
-            if (nt) {
-                // records, headers and ring arrays of both generations, sized
-                // for the smallest tile side (larger tiles need less)
+            if (nt && r.n <= TILE_MAX_AGENTS) {
+                // records (slots of every tile side plus the overflow area),
+                // headers and ring arrays of both generations; headers and
+                // rings are sized for the smallest tile side
                 r.tile_tiles = nt * nt;
+                uint64_t slots = 0;
+                for (uint32_t T = TILE_MIN; T <= 64; T *= 2) {
+                    const uint64_t k = sir_tile_count(L, T);
+                    if (k) slots = std::max<uint64_t>(slots, k * k * sir_tile_cap(r.n, (uint32_t)(k * k)));
+                }
+                r.tile_rec = slots + r.n;
                 for (int b = 0; b < 2; ++b) {
                     r.off_trec[b] = ws;
-                    ws += align_up((uint64_t)r.n * 8, 256);
+                    ws += align_up(r.tile_rec * 8, 256);
                     r.off_thdr[b] = ws;
                     ws += align_up((uint64_t)r.tile_tiles * TILE_HDR * 4, 256);
                     r.off_tring[b] = ws;
@@ -500,10 +508,16 @@ SirParams sir_params(amber_pop *p)
 }
 
 // SIR neighbour-count mode of the pipelined form: 1 gather, 2 box, 3 exchange.
+// Automatic choice for grids that fit in the last-level cache: the 3x3
+// gathers.  Beyond it every gathered cell and every binning atomic costs its
+// own memory line: the box mode then (one read per agent instead of nine),
+// and inside a plain call the tiled mode ahead of both (no random access).
 uint32_t sir_auto_count_mode(const amber_pop *p)
 {
     return (uint64_t)p->r.L * p->r.L > (16ull << 20) ? 2u : 1u;
 }
+
+uint32_t sir_tile_side(const amber_pop *p);
 
 // Tile side of the tiled mode for this run (0 when it does not fit).
 uint32_t sir_tile_side(const amber_pop *p)
@@ -512,8 +526,9 @@ uint32_t sir_tile_side(const amber_pop *p)
     const uint32_t nt = sir_tile_count(p->r.L, want);
     if (!nt || !p->r.tile_tiles) return 0;
     const uint64_t rs = 4ull * want + 8;
-    if ((uint64_t)nt * nt > p->r.tile_tiles ||
-        (uint64_t)nt * nt * rs > sir_tile_ring_words(p->r.L))
+    const uint64_t tiles = (uint64_t)nt * nt;
+    if (tiles > p->r.tile_tiles || tiles * rs > sir_tile_ring_words(p->r.L) ||
+        tiles * sir_tile_cap(p->r.n, (uint32_t)tiles) + p->r.n > p->r.tile_rec)
         return 0;
     return want;
 }
@@ -524,7 +539,8 @@ uint32_t sir_count_mode(const amber_pop *p)
     if (want == 3) return p->r.sx_P ? 3u : 0u;    // 0: unavailable, caller reports it
     if (want == 4) return sir_tile_side(p) ? 4u : 0u;
     if (want == 1 || want == 2) return want;
-    return sir_auto_count_mode(p);
+    const uint32_t m = sir_auto_count_mode(p);
+    return m == 2 && sir_tile_side(p) ? 4u : m;
 }
 
 // Count mode of a run inside amber_step_batch (the batched kernels have the
@@ -554,6 +570,8 @@ TileParams tile_params(amber_pop *p, uint32_t T)
     tp.tshift = T == 64 ? 6u : 5u;
     tp.nT = sir_tile_count(r.L, T);
     tp.rs = 4 * T + 8;
+    tp.cap = sir_tile_cap(r.n, tp.nT * tp.nT);
+    tp.ovf0 = tp.nT * tp.nT * tp.cap;
     for (int b = 0; b < 2; ++b) {
         tp.rec[b] = (uint2 *)ws_ptr(p, r.off_trec[b]);
         tp.hdr[b] = (uint32_t *)ws_ptr(p, r.off_thdr[b]);
@@ -577,10 +595,8 @@ uint32_t tile_block(const amber_pop *p, const TileParams &tp)
     return std::max(b, p->tuning.block);
 }
 
-// Automatic choice: the box mode once the grid no longer fits the
-// last-level cache, where each of the nine gathered cells would cost its own
-// memory line; else the 3x3 gathers.  The exchange mode (no global atomics)
-// runs on request or when the autotuner measures it faster.
+// The exchange mode (no global atomics) runs on request or when the
+// autotuner measures it faster.
 bool sir_box_mode(const amber_pop *p) { return sir_count_mode(p) == 2; }
 
 amber_status_t enqueue_steps(amber_pop *p, uint32_t n_steps)

@@ -146,8 +146,12 @@ hipError_t launch_sir_persistent(SirParams p, uint32_t *sync_words, uint32_t *er
 // During a call each agent is one record {id, lx | ly << 10 | state << 20}
 // (lx, ly relative to the tile holding the agent) in its tile's record list;
 // one workgroup per tile runs each step.  Two generations g = 0, 1 of every
-// buffer alternate with the step of the call.
-constexpr uint32_t TILE_HDR = 10;         // per tile: output base, 9 group counts
+// buffer alternate with the step of the call.  A tile's list of v records
+// is virtual: index u < cap sits at tile * cap + u, the rest in an overflow
+// range at ovf + (u - cap) allocated from the generation's overflow area
+// (which starts at nT^2 * cap and holds up to n records).
+constexpr uint32_t TILE_HDR = 10;         // per tile: overflow base, 9 group counts
+constexpr uint32_t TILE_MAX_AGENTS = 1u << 30;
 constexpr uint32_t TILE_MIN = 32;         // smallest tile side (sizes the buffers)
 struct TileParams {
     int32_t *x;
@@ -158,12 +162,14 @@ struct TileParams {
     int32_t L;
     uint32_t T, tshift, nT;
     uint32_t rs;               // ring words per tile: 4T + 8
-    uint2 *rec[2];             // records, n per generation
+    uint32_t cap;              // record slots per tile
+    uint32_t ovf0;             // first overflow slot: nT^2 * cap
+    uint2 *rec[2];             // records, nT^2 * cap + n per generation
     uint32_t *hdr[2];          // TILE_HDR words per tile
     uint32_t *C[2];            // L*L interior infected counts
     uint32_t *ring[2];         // rs words per tile: infected counts on the ring around it
     uint32_t *cursor;          // one word per tile (initial sort)
-    uint32_t *ctr;             // record allocators: ctr[0] and ctr[64]
+    uint32_t *ctr;             // overflow allocators: ctr[0] and ctr[64]
     uint32_t *err;             // sticky device error word: bit ERR_TILE_LISTS
 };
 // Bits of the sticky device error word at ERR_FLAG_OFFSET.
@@ -173,6 +179,8 @@ constexpr uint32_t ERR_TILE_LISTS = 2u;   // tiled mode: record lists out of ran
 uint32_t sir_tile_count(uint32_t L, uint32_t T);
 // Words of the tiled buffers for grid side L with the smallest tile side.
 uint64_t sir_tile_ring_words(uint32_t L);
+// Record slots per tile for n agents on nt tiles: twice the mean plus 64.
+uint32_t sir_tile_cap(uint32_t n, uint32_t nt);
 // A call of n steps: sort (columns -> records, generation 0), then step(i)
 // for i = 0 .. n with i = 0 the head (move + bin only) and i = n the tail
 // (transition, then records -> columns).

@@ -42,11 +42,6 @@ constexpr uint32_t TILE_LDS_BINS = 32768;        // initial sort: tiles counted 
 constexpr uint32_t SORT_PER = 8;                 // initial sort: agents per thread
 constexpr uint32_t STEP_MAXA = 8;                // records a thread holds per round
 
-__device__ __forceinline__ uint32_t tile_w(const TileParams &p, uint32_t i)
-{
-    return i + 1 == p.nT ? (uint32_t)p.L - (p.nT - 1) * p.T : p.T;
-}
-
 __device__ __forceinline__ uint32_t tile_of(const TileParams &p, int32_t v)
 {
     const uint32_t i = (uint32_t)v >> p.tshift;
@@ -92,36 +87,11 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t m)
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-// Adds the active lanes of the wavefront to ctr[key] with one LDS atomic per
-// distinct key and returns each lane's rank among the lanes of its key.
-// Every lane of the wavefront must call it.
-__device__ __forceinline__ uint32_t wave_add(uint32_t key, bool active, uint32_t *ctr)
+// Slot of index u of a tile's record list (slots [fix, fix + cap), then the
+// overflow range at ovf).
+__device__ __forceinline__ uint32_t rec_slot(uint32_t u, uint32_t cap, uint32_t fix, uint32_t ovf)
 {
-    uint64_t pending = __ballot(active);
-    uint32_t rank = 0;
-    const uint32_t lane = __lane_id();
-    while (pending) {
-        const uint32_t leader = (uint32_t)__builtin_ctzll(pending);
-        const uint32_t k = (uint32_t)__shfl((int)key, (int)leader);
-        const uint64_t same = __ballot(active && key == k);
-        uint32_t base = 0;
-        if (lane == leader) base = atomicAdd(&ctr[k], (uint32_t)__popcll(same));
-        base = (uint32_t)__shfl((int)base, (int)leader);
-        if (active && key == k) rank = base + lanes_below(same);
-        pending &= ~same;
-    }
-    return rank;
-}
-
-// Record v of the tile's input (chunk d holds virtual indices
-// [pre[d], pre[d+1])).
-__device__ __forceinline__ uint2 load_rec(const uint2 *__restrict__ rec, const uint32_t *start,
-                                          const uint32_t *pre, uint32_t v)
-{
-    uint32_t d = 0;
-#pragma unroll
-    for (int k = 1; k < 9; ++k) d += v >= pre[k] ? 1u : 0u;
-    return rec[start[d] + (v - pre[d])];
+    return u < cap ? fix + u : ovf + (u - cap);
 }
 
 // Move of step t for agent id at local (lx, ly): returns the new local
@@ -162,176 +132,318 @@ __device__ __forceinline__ uint32_t tile_transition(const TileParams &p, const u
     return u < p.t_rec ? (uint32_t)ST_R : (uint32_t)ST_I;
 }
 
+// Region entry (row stride RW) that ring entry k of the 9-tile neighbourhood
+// adds to, and the ring word it reads, for the tile (ti, tj) of size w x h.
+// Entries: the tile's own ring (2(w+2) + 2h), the facing column of the left
+// and right tiles (h each), the facing row of the tiles above and below
+// (w + 2 each), then 24 single cells near the corners.  Any other ring cell
+// of a neighbour lies outside the tile and its ring.
+struct RingSeg {
+    const uint32_t *src;
+    uint32_t dst;
+};
+
+template <uint32_t RW>
+__device__ __forceinline__ RingSeg ring_entry(const uint32_t *R, uint32_t rs, uint32_t nT,
+                                              uint32_t k, uint32_t ti, uint32_t tj, uint32_t li,
+                                              uint32_t ri, uint32_t uj, uint32_t dj, uint32_t w,
+                                              uint32_t h, uint32_t wl, uint32_t wr, uint32_t hu,
+                                              uint32_t hd)
+{
+    auto ring = [&](uint32_t i, uint32_t j) { return R + (size_t)(j * nT + i) * rs; };
+    const uint32_t n_self = 2 * (w + 2) + 2 * h;
+    if (k < n_self) {
+        int32_t lx, ly;
+        ring_cell(k, w, h, lx, ly);
+        return {ring(ti, tj) + k, (uint32_t)(ly + 1) * RW + (uint32_t)(lx + 1)};
+    }
+    uint32_t q = k - n_self;
+    if (q < h) return {ring(li, tj) + 2 * (wl + 2) + h + q, (q + 1) * RW + 1};
+    q -= h;
+    if (q < h) return {ring(ri, tj) + 2 * (wr + 2) + q, (q + 1) * RW + w};
+    q -= h;
+    if (q < w + 2) return {ring(ti, uj) + w + 2 + q, RW + q};
+    q -= w + 2;
+    if (q < w + 2) return {ring(ti, dj) + q, h * RW + q};
+    q -= w + 2;
+    const uint32_t b = (h + 1) * RW;        // bottom ring row
+    switch (q) {
+    case 0: return {ring(li, tj) + wl, 0};
+    case 1: return {ring(li, tj) + wl + 1, 1};
+    case 2: return {ring(li, tj) + wl + 2 + wl, b};
+    case 3: return {ring(li, tj) + wl + 2 + wl + 1, b + 1};
+    case 4: return {ring(ri, tj), w};
+    case 5: return {ring(ri, tj) + 1, w + 1};
+    case 6: return {ring(ri, tj) + wr + 2, b + w};
+    case 7: return {ring(ri, tj) + wr + 3, b + w + 1};
+    case 8: return {ring(ti, uj) + 2 * (w + 2) + hu - 1, 0};
+    case 9: return {ring(ti, uj) + 2 * (w + 2) + 2 * hu - 1, w + 1};
+    case 10: return {ring(ti, dj) + 2 * (w + 2), b};
+    case 11: return {ring(ti, dj) + 2 * (w + 2) + hd, b + w + 1};
+    case 12: return {ring(li, uj) + wl + 2 + wl + 1, RW + 1};
+    case 13: return {ring(li, uj) + wl + 2 + wl, RW};
+    case 14: return {ring(li, uj) + 2 * (wl + 2) + 2 * hu - 1, 1};
+    case 15: return {ring(ri, uj) + wr + 2, RW + w};
+    case 16: return {ring(ri, uj) + wr + 3, RW + w + 1};
+    case 17: return {ring(ri, uj) + 2 * (wr + 2) + hu - 1, w};
+    case 18: return {ring(li, dj) + wl + 1, h * RW + 1};
+    case 19: return {ring(li, dj) + wl, h * RW};
+    case 20: return {ring(li, dj) + 2 * (wl + 2) + hd, b + 1};
+    case 21: return {ring(ri, dj), h * RW + w};
+    case 22: return {ring(ri, dj) + 1, h * RW + w + 1};
+    default: return {ring(ri, dj) + 2 * (wr + 2), b + w};
+    }
+}
+
 // One step on one tile.  TRANS: apply the transition of step t - 1 first
 // (not on the first launch of a call).  MOVE: move and bin step t and write
 // the next records (not on the last launch, which writes the columns).
 // Input generation gen, output generation gen ^ 1.
+//
+// Output slots: every wavefront counts its records per destination group
+// (pass 1); the counts become per-wavefront bases inside each group, and
+// pass 2 hands out consecutive slots from those bases (ballot ranks).
+// Global loads of one phase are all issued before any of them is used.
 template <uint32_t T, bool TRANS, bool MOVE>
 __global__ void __launch_bounds__(1024) k_tile_step(TileParams p, uint32_t t, uint32_t gen)
 {
     constexpr uint32_t RW = T + 3;                 // widest tile (T + 1) plus its ring
+    constexpr uint32_t MAXW = 16;                  // wavefronts per workgroup
     __shared__ uint32_t reg[TRANS ? RW * RW : 1];  // counts of step t - 1
     __shared__ uint32_t hist[MOVE ? RW * RW : 1];  // infected of step t
-    __shared__ uint32_t c_start[9], c_cnt[9], c_pre[10], gcnt[9], gcur[9], goff[9];
-    __shared__ uint32_t s_base;
+    __shared__ uint32_t wcnt[MOVE ? MAXW * 9 : 1]; // per-wavefront group counts
+    __shared__ uint32_t wbase[MOVE ? MAXW * 9 : 1];// per-wavefront group bases
+    __shared__ uint32_t c_start[9], c_fix[9], c_ovf[9], c_cnt[9], gtot[9];
+    __shared__ uint32_t s_ovf, s_store;
     const uint32_t tid = threadIdx.x, NT = blockDim.x;
-    const uint32_t tile = blockIdx.x;
-    const uint32_t ti = tile % p.nT, tj = tile / p.nT;
+    const uint32_t lane = tid & 63u, wave = tid >> 6, nw = NT >> 6;
+    const uint32_t nT = p.nT, tile = blockIdx.x;
+    const uint32_t tj = tile / nT, ti = tile - tj * nT;
+    const uint32_t last = (uint32_t)p.L - (nT - 1) * T;
+    const uint32_t li = ti ? ti - 1 : nT - 1, ri = ti + 1 < nT ? ti + 1 : 0u;
+    const uint32_t uj = tj ? tj - 1 : nT - 1, dj = tj + 1 < nT ? tj + 1 : 0u;
+    const uint32_t w = ti + 1 == nT ? last : T, h = tj + 1 == nT ? last : T;
     const int32_t x0 = (int32_t)(ti * T), y0 = (int32_t)(tj * T);
-    const uint32_t w = tile_w(p, ti), h = tile_w(p, tj);
 
     if (tid < 9) {
-        // chunk tid: what tile (ti - ddx, tj - ddy) sent with offset (ddx, ddy)
-        const uint32_t si = (ti + p.nT + 1 - tid % 3) % p.nT;
-        const uint32_t sj = (tj + p.nT + 1 - tid / 3) % p.nT;
-        const uint32_t *H = p.hdr[gen] + (size_t)(sj * p.nT + si) * TILE_HDR;
-        uint32_t off = H[0];
-        for (uint32_t g = 0; g < tid; ++g) off += H[1 + g];
+        // chunk tid: what tile (ti - ddx, tj - ddy) sent with offset
+        // (ddx, ddy) = (tid % 3 - 1, tid / 3 - 1): its group tid
+        const uint32_t cx = tid % 3, cy = tid / 3;
+        const uint32_t si = cx == 0 ? ri : (cx == 1 ? ti : li);
+        const uint32_t sj = cy == 0 ? dj : (cy == 1 ? tj : uj);
+        const uint32_t src = sj * nT + si;
+        const uint32_t *H = p.hdr[gen] + (size_t)src * TILE_HDR;
+        uint32_t hv[TILE_HDR];
+#pragma unroll
+        for (uint32_t i = 0; i < TILE_HDR; ++i) hv[i] = H[i];
+        uint32_t off = 0, cnt = 0;
+#pragma unroll
+        for (uint32_t g = 0; g < 9; ++g) {
+            off += g < tid ? hv[1 + g] : 0u;
+            cnt = g == tid ? hv[1 + g] : cnt;
+        }
         c_start[tid] = off;
-        c_cnt[tid] = H[1 + tid];
-        gcnt[tid] = 0;
-        gcur[tid] = 0;
+        c_fix[tid] = src * p.cap;
+        c_ovf[tid] = hv[0];
+        c_cnt[tid] = cnt;
     }
-    if (MOVE)
+    if (MOVE) {
         for (uint32_t k = tid; k < RW * RW; k += NT) hist[k] = 0;
-    if (TRANS) {
-        const uint32_t *C = p.C[gen ^ 1];
-        const uint32_t rw = w + 2, cells = rw * (h + 2);
-        for (uint32_t k = tid; k < cells; k += NT) {
-            const uint32_t ry = k / rw, rx = k - ry * rw;
-            int32_t gx = x0 + (int32_t)rx - 1, gy = y0 + (int32_t)ry - 1;
-            gx = gx < 0 ? gx + p.L : (gx >= p.L ? gx - p.L : gx);
-            gy = gy < 0 ? gy + p.L : (gy >= p.L ? gy - p.L : gy);
-            reg[ry * RW + rx] = C[(size_t)gy * (uint32_t)p.L + (uint32_t)gx];
-        }
+        for (uint32_t k = tid; k < nw * 9; k += NT) wcnt[k] = 0;
     }
     __syncthreads();
-    if (tid == 0) {
-        // the chunks must lie inside the record buffer and sum to at most n;
-        // if not, the tile takes no records and the error word says so
-        uint32_t acc = 0;
-        bool ok = true;
-        for (int d = 0; d < 9; ++d) {
-            c_pre[d] = acc;
-            acc += c_cnt[d];
-            ok = ok && c_cnt[d] <= p.n && c_start[d] <= p.n - c_cnt[d];
-        }
-        if (!ok || acc > p.n) {
-            acc = 0;
-            for (int d = 0; d < 9; ++d) c_pre[d] = 0;
-            __hip_atomic_fetch_or(p.err, ERR_TILE_LISTS, __ATOMIC_RELAXED,
-                                  __HIP_MEMORY_SCOPE_AGENT);
-        }
-        c_pre[9] = acc;
+
+    // chunk prefix (every thread) and its check: the chunks must lie inside
+    // the record buffer and sum to at most n, else the tile takes no records
+    uint32_t pre[10];
+    bool ok = true;
+    pre[0] = 0;
+#pragma unroll
+    for (uint32_t d = 0; d < 9; ++d) {
+        const uint32_t c = c_cnt[d], st = c_start[d];
+        pre[d + 1] = pre[d] + c;
+        ok = ok && c <= p.n && st <= p.n - c;
+        if (ok && c && st + c > p.cap)     // the chunk reaches the overflow range
+            ok = c_ovf[d] >= p.ovf0 && c_ovf[d] - p.ovf0 <= p.n - (st + c - p.cap);
     }
-    if (TRANS) {
-        // ring partial counts of the 9 tiles around (this one included)
-        const uint32_t *R = p.ring[gen ^ 1];
-        for (uint32_t k = tid; k < 9 * p.rs; k += NT) {
-            const uint32_t a = k / p.rs, r = k - a * p.rs;
-            const uint32_t ai = (ti + p.nT + a % 3 - 1) % p.nT;
-            const uint32_t aj = (tj + p.nT + a / 3 - 1) % p.nT;
-            const uint32_t aw = tile_w(p, ai), ah = tile_w(p, aj);
-            if (r >= ring_size(aw, ah)) continue;
-            const uint32_t v = R[(size_t)(aj * p.nT + ai) * p.rs + r];
-            if (v == 0) continue;
-            int32_t lx, ly;
-            ring_cell(r, aw, ah, lx, ly);
-            int32_t bx = (int32_t)(ai * T) + lx - x0, by = (int32_t)(aj * T) + ly - y0;
-            if (bx < -1) bx += p.L;
-            else if (bx > (int32_t)w) bx -= p.L;
-            if (by < -1) by += p.L;
-            else if (by > (int32_t)h) by -= p.L;
-            if (bx >= -1 && bx <= (int32_t)w && by >= -1 && by <= (int32_t)h)
-                atomicAdd(&reg[(uint32_t)(by + 1) * RW + (uint32_t)(bx + 1)], v);
-        }
-    }
-    __syncthreads();
-    const uint32_t n_in = c_pre[9];
+    ok = ok && pre[9] <= p.n;
+    const uint32_t n_in = ok ? pre[9] : 0u;
+    if (!ok && tid == 0)
+        __hip_atomic_fetch_or(p.err, ERR_TILE_LISTS, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const uint2 *in = p.rec[gen];
+    auto load = [&](uint32_t v) {
+        uint32_t d = 0, pd = 0;
+#pragma unroll
+        for (uint32_t k = 1; k < 9; ++k)
+            if (v >= pre[k]) {
+                d = k;
+                pd = pre[k];
+            }
+        return in[rec_slot(c_start[d] + (v - pd), p.cap, c_fix[d], c_ovf[d])];
+    };
+
+    if (MOVE && tid == 0) {
+        // records beyond the tile's slots go to an overflow range (rare; one
+        // atomic per overflowing tile)
+        const uint32_t over = n_in > p.cap ? n_in - p.cap : 0u;
+        uint32_t ovf = 0, store = 1;
+        if (over) {
+            const uint32_t b = atomicAdd(p.ctr + 64 * (gen ^ 1), over);
+            if (b > p.n - over) {    // more records than agents: write none
+                __hip_atomic_fetch_or(p.err, ERR_TILE_LISTS, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
+                store = 0;
+            }
+            ovf = p.ovf0 + b;
+        }
+        s_ovf = ovf;
+        s_store = store;
+        if (tile == 0) p.ctr[64 * gen] = 0;     // overflow allocator of the next launch
+    }
+    if (TRANS) {
+        // counts of the tile and its ring, rows by wavefront
+        const uint32_t *C = p.C[gen ^ 1];
+        for (uint32_t ry = wave; ry < h + 2; ry += nw) {
+            int32_t gy = y0 + (int32_t)ry - 1;
+            gy = gy < 0 ? gy + p.L : (gy >= p.L ? gy - p.L : gy);
+            const uint32_t *row = C + (size_t)gy * (uint32_t)p.L;
+            for (uint32_t rx = lane; rx < w + 2; rx += 64) {
+                int32_t gx = x0 + (int32_t)rx - 1;
+                gx = gx < 0 ? gx + p.L : (gx >= p.L ? gx - p.L : gx);
+                reg[ry * RW + rx] = row[gx];
+            }
+        }
+    }
+
+    const uint32_t round_cap = NT * STEP_MAXA;
+    const bool one = n_in <= round_cap;
+    uint32_t rid[STEP_MAXA], rpk[STEP_MAXA], rmv[STEP_MAXA];
+    auto fetch = [&](uint32_t r0) {
+#pragma unroll
+        for (uint32_t j = 0; j < STEP_MAXA; ++j) {
+            const uint32_t v = r0 + j * NT + tid;
+            if (v < n_in) {
+                const uint2 r = load(v);
+                rid[j] = r.x;
+                rpk[j] = r.y;
+            }
+        }
+    };
+
+    if (MOVE) {
+        // pass 1: records per destination group and wavefront
+        uint32_t *mine = wcnt + wave * 9;
+        uint32_t stay = 0;                          // wavefront-uniform
+        for (uint32_t r0 = 0; r0 < n_in; r0 += round_cap) {
+            fetch(r0);
+#pragma unroll
+            for (uint32_t j = 0; j < STEP_MAXA; ++j) {
+                if (r0 + j * NT + wave * 64 >= n_in) break;     // whole wavefront past the end
+                const bool act = r0 + j * NT + tid < n_in;
+                uint32_t g = STAY;
+                if (act) {
+                    rmv[j] = move_of(p, rid[j], rpk[j], t, w, h);
+                    g = rmv[j] >> 20;
+                    if ((rpk[j] & 1023u) >= w || ((rpk[j] >> 10) & 1023u) >= h)
+                        __hip_atomic_fetch_or(p.err, ERR_TILE_LISTS, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+                }
+                stay += (uint32_t)__popcll(__ballot(act && g == STAY));
+                uint64_t other = __ballot(act && g != STAY);
+                while (other) {
+                    const uint32_t leader = (uint32_t)__builtin_ctzll(other);
+                    const uint32_t k = (uint32_t)__builtin_amdgcn_readlane((int)g, (int)leader);
+                    const uint64_t same = __ballot(act && g == k);
+                    if (lane == leader) mine[k] += (uint32_t)__popcll(same);
+                    other &= ~same;
+                }
+            }
+        }
+        if (lane == 0) mine[STAY] = stay;
+    } else {
+        fetch(0);   // the tail holds its records while the counts come in
+    }
+    __syncthreads();
+
+    if (TRANS) {
+        // ring partial counts that land on the tile or its ring
+        const uint32_t wl = li + 1 == nT ? last : T, wr = ri + 1 == nT ? last : T;
+        const uint32_t hu = uj + 1 == nT ? last : T, hd = dj + 1 == nT ? last : T;
+        const uint32_t total = 2 * (w + 2) + 2 * h + 2 * h + 2 * (w + 2) + 24;
+        for (uint32_t k = tid; k < total; k += NT) {
+            const RingSeg e = ring_entry<RW>(p.ring[gen ^ 1], p.rs, nT, k, ti, tj, li, ri, uj,
+                                             dj, w, h, wl, wr, hu, hd);
+            const uint32_t v = *e.src;
+            if (v) atomicAdd(&reg[e.dst], v);
+        }
+    }
+    if (MOVE && tid < 9) {
+        uint32_t tot = 0;
+        for (uint32_t k = 0; k < nw; ++k) tot += wcnt[k * 9 + tid];
+        gtot[tid] = tot;
+    }
+    __syncthreads();
 
     if (!MOVE) {
         // last launch of the call: transition, then back to the columns
-        for (uint32_t v = tid; v < n_in; v += NT) {
-            const uint2 r = load_rec(in, c_start, c_pre, v);
-            const uint32_t lx = r.y & 1023u, ly = (r.y >> 10) & 1023u;
-            uint32_t s = (r.y >> 20) & 3u;
-            if (r.x >= p.n || lx >= w || ly >= h) {
-                __hip_atomic_fetch_or(p.err, ERR_TILE_LISTS, __ATOMIC_RELAXED,
-                                      __HIP_MEMORY_SCOPE_AGENT);
-                continue;
+        for (uint32_t r0 = 0; r0 < n_in; r0 += round_cap) {
+            if (r0) fetch(r0);
+#pragma unroll
+            for (uint32_t j = 0; j < STEP_MAXA; ++j) {
+                const uint32_t v = r0 + j * NT + tid;
+                if (v >= n_in) break;
+                const uint32_t lx = rpk[j] & 1023u, ly = (rpk[j] >> 10) & 1023u;
+                if (rid[j] >= p.n || lx >= w || ly >= h) {
+                    __hip_atomic_fetch_or(p.err, ERR_TILE_LISTS, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+                    continue;
+                }
+                uint32_t s = (rpk[j] >> 20) & 3u;
+                if (TRANS) s = tile_transition<RW>(p, reg, rid[j], s, lx, ly, t - 1);
+                p.x[rid[j]] = x0 + (int32_t)lx;
+                p.y[rid[j]] = y0 + (int32_t)ly;
+                p.s[rid[j]] = (uint8_t)s;
             }
-            if (TRANS) s = tile_transition<RW>(p, reg, r.x, s, lx, ly, t - 1);
-            p.x[r.x] = x0 + (int32_t)lx;
-            p.y[r.x] = y0 + (int32_t)ly;
-            p.s[r.x] = (uint8_t)s;
         }
         return;
     }
 
-    // pass 1: group sizes (records stay in registers when they fit one round)
-    const uint32_t cap = NT * STEP_MAXA;
-    uint32_t rid[STEP_MAXA], rpk[STEP_MAXA], rmv[STEP_MAXA];
-    for (uint32_t r0 = 0; r0 < n_in; r0 += cap) {
-#pragma unroll
-        for (uint32_t j = 0; j < STEP_MAXA; ++j) {
-            const uint32_t v = r0 + tid + j * NT;
-            const bool act = v < n_in;
-            uint32_t g = STAY;
-            if (act) {
-                const uint2 r = load_rec(in, c_start, c_pre, v);
-                rid[j] = r.x;
-                rpk[j] = r.y;
-                rmv[j] = move_of(p, r.x, r.y, t, w, h);
-                g = rmv[j] >> 20;
-                if ((r.y & 1023u) >= w || ((r.y >> 10) & 1023u) >= h)
-                    __hip_atomic_fetch_or(p.err, ERR_TILE_LISTS, __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_AGENT);
-            }
-            wave_add(g, act, gcnt);
-        }
+    // per-wavefront bases inside each group of the tile's list
+    if (tid < nw * 9) {
+        const uint32_t k = tid / 9, g = tid - k * 9;
+        uint32_t b = 0;
+        for (uint32_t q = 0; q < g; ++q) b += gtot[q];
+        for (uint32_t q = 0; q < k; ++q) b += wcnt[q * 9 + g];
+        wbase[tid] = b;
     }
-    __syncthreads();
     if (tid == 0) {
-        uint32_t acc = 0;
-        for (int g = 0; g < 9; ++g) {
-            goff[g] = acc;
-            acc += gcnt[g];
-        }
-        uint32_t base = atomicAdd(p.ctr + 64 * (gen ^ 1), n_in);
-        if (base > p.n - n_in) {       // more records than agents: write none
-            __hip_atomic_fetch_or(p.err, ERR_TILE_LISTS, __ATOMIC_RELAXED,
-                                  __HIP_MEMORY_SCOPE_AGENT);
-            base = 0xffffffffu;
-        }
-        s_base = base;
         uint32_t *H = p.hdr[gen ^ 1] + (size_t)tile * TILE_HDR;
-        H[0] = base;
-        for (int g = 0; g < 9; ++g) H[1 + g] = gcnt[g];
-        if (tile == 0) p.ctr[64 * gen] = 0;     // allocator of the next launch's output
+        H[0] = s_ovf;
+        for (int g = 0; g < 9; ++g) H[1 + g] = gtot[g];
     }
     __syncthreads();
 
     // pass 2: transition, bin, write
-    const bool one = n_in <= cap;
-    const uint32_t base = s_base;
-    const bool store = base != 0xffffffffu;
+    const bool store = s_store != 0;
+    const uint32_t fix = tile * p.cap, ovf = s_ovf;
     uint2 *out = p.rec[gen ^ 1];
-    const uint32_t wl = tile_w(p, (ti + p.nT - 1) % p.nT);   // width of the tile to the left
-    const uint32_t hb = tile_w(p, (tj + p.nT - 1) % p.nT);   // height of the tile above
-    for (uint32_t r0 = 0; r0 < n_in; r0 += cap) {
+    const uint32_t wl = li + 1 == nT ? last : T;   // width of the tile to the left
+    const uint32_t hb = uj + 1 == nT ? last : T;   // height of the tile above
+    uint32_t *mine = wbase + wave * 9;
+    uint32_t stay_run = mine[STAY];
+    for (uint32_t r0 = 0; r0 < n_in; r0 += round_cap) {
+        if (!one) {
+            fetch(r0);
+#pragma unroll
+            for (uint32_t j = 0; j < STEP_MAXA; ++j)
+                if (r0 + j * NT + tid < n_in) rmv[j] = move_of(p, rid[j], rpk[j], t, w, h);
+        }
 #pragma unroll
         for (uint32_t j = 0; j < STEP_MAXA; ++j) {
-            const uint32_t v = r0 + tid + j * NT;
-            const bool act = v < n_in;
+            if (r0 + j * NT + wave * 64 >= n_in) break;
+            const bool act = r0 + j * NT + tid < n_in;
             uint32_t g = STAY, pk = 0;
             if (act) {
-                if (!one) {
-                    const uint2 r = load_rec(in, c_start, c_pre, v);
-                    rid[j] = r.x;
-                    rpk[j] = r.y;
-                    rmv[j] = move_of(p, r.x, r.y, t, w, h);
-                }
                 uint32_t s = (rpk[j] >> 20) & 3u;
                 if (TRANS)
                     s = tile_transition<RW>(p, reg, rid[j], s, rpk[j] & 1023u,
@@ -345,18 +457,32 @@ __global__ void __launch_bounds__(1024) k_tile_step(TileParams p, uint32_t t, ui
                 const uint32_t dy = gy == 0 ? hb - 1 : (gy == 2 ? 0u : cy - 1);
                 pk = dx | (dy << 10) | (s << 20);
             }
-            const uint32_t rank = wave_add(g, act, gcur);
-            if (act && store) out[base + goff[g] + rank] = make_uint2(rid[j], pk);
+            uint32_t slot = 0;
+            const uint64_t ms = __ballot(act && g == STAY);
+            if (act && g == STAY) slot = stay_run + lanes_below(ms);
+            stay_run += (uint32_t)__popcll(ms);
+            uint64_t other = __ballot(act && g != STAY);
+            while (other) {
+                const uint32_t leader = (uint32_t)__builtin_ctzll(other);
+                const uint32_t k = (uint32_t)__builtin_amdgcn_readlane((int)g, (int)leader);
+                const uint64_t same = __ballot(act && g == k);
+                const uint32_t b0 = mine[k];
+                if (act && g == k) slot = b0 + lanes_below(same);
+                if (lane == leader) mine[k] = b0 + (uint32_t)__popcll(same);
+                other &= ~same;
+            }
+            if (act && store) out[rec_slot(slot, p.cap, fix, ovf)] = make_uint2(rid[j], pk);
         }
     }
     __syncthreads();
 
-    // counts of step t: interior to the grid, ring to the tile's ring array
+    // counts of step t: interior to the grid (rows by wavefront), ring to the
+    // tile's ring array
     uint32_t *C = p.C[gen];
-    for (uint32_t k = tid; k < w * h; k += NT) {
-        const uint32_t ly = k / w, lx = k - ly * w;
-        C[(size_t)((uint32_t)y0 + ly) * (uint32_t)p.L + (uint32_t)x0 + lx] =
-            hist[(ly + 1) * RW + lx + 1];
+    for (uint32_t ly = wave; ly < h; ly += nw) {
+        uint32_t *row = C + (size_t)((uint32_t)y0 + ly) * (uint32_t)p.L + (uint32_t)x0;
+        const uint32_t *src = hist + (ly + 1) * RW + 1;
+        for (uint32_t lx = lane; lx < w; lx += 64) row[lx] = src[lx];
     }
     uint32_t *R = p.ring[gen] + (size_t)tile * p.rs;
     const uint32_t rsz = ring_size(w, h);
@@ -402,7 +528,9 @@ __global__ void __launch_bounds__(1024) k_tile_hist(TileParams p)
     }
 }
 
-// One workgroup: cursor[] (counts) -> record bases, generation-0 headers.
+// One workgroup: cursor[] (counts) -> generation-0 headers (the overflow
+// ranges of tiles with more records than slots are laid out in tile order),
+// cursor[] back to zero for the ranks.
 __global__ void __launch_bounds__(1024) k_tile_scan(TileParams p)
 {
     __shared__ uint32_t part[1024];
@@ -412,10 +540,12 @@ __global__ void __launch_bounds__(1024) k_tile_scan(TileParams p)
     __syncthreads();
     for (uint32_t c0 = 0; c0 < nt; c0 += 4 * 1024) {
         uint32_t v[4], sum = 0;
+        uint32_t cnt[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const uint32_t i = c0 + tid * 4 + j;
-            v[j] = i < nt ? p.cursor[i] : 0u;
+            cnt[j] = i < nt ? p.cursor[i] : 0u;
+            v[j] = cnt[j] > p.cap ? cnt[j] - p.cap : 0u;     // records past the tile's slots
             sum += v[j];
         }
         part[tid] = sum;
@@ -432,9 +562,9 @@ __global__ void __launch_bounds__(1024) k_tile_scan(TileParams p)
             const uint32_t i = c0 + tid * 4 + j;
             if (i < nt) {
                 uint32_t *H = p.hdr[0] + (size_t)i * TILE_HDR;
-                H[0] = b;
-                for (uint32_t g = 0; g < 9; ++g) H[1 + g] = g == STAY ? v[j] : 0u;
-                p.cursor[i] = b;
+                H[0] = p.ovf0 + b;
+                for (uint32_t g = 0; g < 9; ++g) H[1 + g] = g == STAY ? cnt[j] : 0u;
+                p.cursor[i] = 0;
             }
             b += v[j];
         }
@@ -468,7 +598,7 @@ __global__ void __launch_bounds__(1024) k_tile_scatter(TileParams p)
         }
         __syncthreads();
         for (uint32_t b = tid; b < nt; b += NT)
-            if (h[b]) h[b] = atomicAdd(&p.cursor[b], h[b]);   // count -> first slot
+            if (h[b]) h[b] = atomicAdd(&p.cursor[b], h[b]);   // count -> first rank
         __syncthreads();
     }
 #pragma unroll
@@ -476,8 +606,9 @@ __global__ void __launch_bounds__(1024) k_tile_scatter(TileParams p)
         const uint32_t a = a0 + j * NT + tid;
         if (a >= p.n) continue;
         const int32_t x = p.x[a], y = p.y[a];
-        const uint32_t tx = tile_of(p, x), ty = tile_of(p, y);
-        const uint32_t slot = LDS ? h[bin[j]] + rank[j] : atomicAdd(&p.cursor[ty * p.nT + tx], 1u);
+        const uint32_t tx = tile_of(p, x), ty = tile_of(p, y), b = ty * p.nT + tx;
+        const uint32_t r = LDS ? h[bin[j]] + rank[j] : atomicAdd(&p.cursor[b], 1u);
+        const uint32_t slot = rec_slot(r, p.cap, b * p.cap, p.hdr[0][(size_t)b * TILE_HDR]);
         const uint32_t lx = (uint32_t)x - tx * p.T, ly = (uint32_t)y - ty * p.T;
         p.rec[0][slot] = make_uint2(a, lx | (ly << 10) | ((uint32_t)p.s[a] << 20));
     }
@@ -499,6 +630,12 @@ hipError_t step_launch(const TileParams &p, uint32_t t, uint32_t gen, uint32_t p
 uint32_t sir_tile_count(uint32_t L, uint32_t T)
 {
     return L >= 2 * T + 2 ? (L - 2) / T + 1 : 0u;
+}
+
+uint32_t sir_tile_cap(uint32_t n, uint32_t nt)
+{
+    const uint64_t mean = ((uint64_t)n + nt - 1) / nt;
+    return (uint32_t)((2 * mean + 64 + 63) / 64 * 64);
 }
 
 uint64_t sir_tile_ring_words(uint32_t L)
