@@ -95,7 +95,8 @@ __device__ __forceinline__ uint32_t rec_slot(uint32_t u, uint32_t cap, uint32_t 
 }
 
 // Move of step t for agent id at local (lx, ly): returns the new local
-// position (+1, 10 bits each) and the destination group (bits 20..23).
+// position (+1, 10 bits each), the destination group (bits 20..23) and its
+// tile offsets + 1 in x (bits 24..25) and y (bits 26..27).
 __device__ __forceinline__ uint32_t move_of(const TileParams &p, uint32_t id, uint32_t pk,
                                             uint32_t t, uint32_t w, uint32_t h)
 {
@@ -105,7 +106,8 @@ __device__ __forceinline__ uint32_t move_of(const TileParams &p, uint32_t id, ui
     const int32_t ny = (int32_t)((pk >> 10) & 1023u) + (int32_t)((MOVE_DY1 >> sh) & 3u) - 1;
     const uint32_t gx = nx < 0 ? 0u : (nx >= (int32_t)w ? 2u : 1u);
     const uint32_t gy = ny < 0 ? 0u : (ny >= (int32_t)h ? 2u : 1u);
-    return (uint32_t)(nx + 1) | ((uint32_t)(ny + 1) << 10) | ((gy * 3 + gx) << 20);
+    return (uint32_t)(nx + 1) | ((uint32_t)(ny + 1) << 10) | ((gy * 3 + gx) << 20) | (gx << 24) |
+           (gy << 26);
 }
 
 // Transition of step t_prev for an agent at local (lx, ly) of the tile, with
@@ -131,6 +133,21 @@ __device__ __forceinline__ uint32_t tile_transition(const TileParams &p, const u
     }
     return u < p.t_rec ? (uint32_t)ST_R : (uint32_t)ST_I;
 }
+
+// Buffers of one launch: input generation gen, output generation gen ^ 1;
+// counts are read from the previous launch and written for the next.
+struct StepIO {
+    const uint2 *rec_in;
+    uint2 *rec_out;
+    const uint32_t *hdr_in;
+    uint32_t *hdr_out;
+    const uint32_t *C_in;
+    uint32_t *C_out;
+    const uint32_t *ring_in;
+    uint32_t *ring_out;
+    uint32_t *ovf_out;         // overflow allocator of the output generation
+    uint32_t *ovf_reset;       // allocator the previous launch used: back to zero
+};
 
 // Region entry (row stride RW) that ring entry k of the 9-tile neighbourhood
 // adds to, and the ring word it reads, for the tile (ti, tj) of size w x h.
@@ -205,7 +222,7 @@ __device__ __forceinline__ RingSeg ring_entry(const uint32_t *R, uint32_t rs, ui
 // pass 2 hands out consecutive slots from those bases (ballot ranks).
 // Global loads of one phase are all issued before any of them is used.
 template <uint32_t T, bool TRANS, bool MOVE>
-__global__ void __launch_bounds__(1024) k_tile_step(TileParams p, uint32_t t, uint32_t gen)
+__global__ void __launch_bounds__(1024) k_tile_step(TileParams p, StepIO io, uint32_t t)
 {
     constexpr uint32_t RW = T + 3;                 // widest tile (T + 1) plus its ring
     constexpr uint32_t MAXW = 16;                  // wavefronts per workgroup
@@ -216,7 +233,8 @@ __global__ void __launch_bounds__(1024) k_tile_step(TileParams p, uint32_t t, ui
     __shared__ uint32_t c_start[9], c_fix[9], c_ovf[9], c_cnt[9], gtot[9];
     __shared__ uint32_t s_ovf, s_store;
     const uint32_t tid = threadIdx.x, NT = blockDim.x;
-    const uint32_t lane = tid & 63u, wave = tid >> 6, nw = NT >> 6;
+    const uint32_t lane = tid & 63u, nw = NT >> 6;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wavefront-uniform
     const uint32_t nT = p.nT, tile = blockIdx.x;
     const uint32_t tj = tile / nT, ti = tile - tj * nT;
     const uint32_t last = (uint32_t)p.L - (nT - 1) * T;
@@ -232,7 +250,7 @@ __global__ void __launch_bounds__(1024) k_tile_step(TileParams p, uint32_t t, ui
         const uint32_t si = cx == 0 ? ri : (cx == 1 ? ti : li);
         const uint32_t sj = cy == 0 ? dj : (cy == 1 ? tj : uj);
         const uint32_t src = sj * nT + si;
-        const uint32_t *H = p.hdr[gen] + (size_t)src * TILE_HDR;
+        const uint32_t *H = io.hdr_in + (size_t)src * TILE_HDR;
         uint32_t hv[TILE_HDR];
 #pragma unroll
         for (uint32_t i = 0; i < TILE_HDR; ++i) hv[i] = H[i];
@@ -270,15 +288,19 @@ __global__ void __launch_bounds__(1024) k_tile_step(TileParams p, uint32_t t, ui
     const uint32_t n_in = ok ? pre[9] : 0u;
     if (!ok && tid == 0)
         __hip_atomic_fetch_or(p.err, ERR_TILE_LISTS, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const uint2 *in = p.rec[gen];
+    const uint2 *in = io.rec_in;
     auto load = [&](uint32_t v) {
-        uint32_t d = 0, pd = 0;
+        uint32_t d = STAY, pd = pre[STAY];
+        if (v < pre[STAY] || v >= pre[STAY + 1]) {   // a record that moved in (few)
+            d = 0;
+            pd = 0;
 #pragma unroll
-        for (uint32_t k = 1; k < 9; ++k)
-            if (v >= pre[k]) {
-                d = k;
-                pd = pre[k];
-            }
+            for (uint32_t k = 1; k < 9; ++k)
+                if (v >= pre[k]) {
+                    d = k;
+                    pd = pre[k];
+                }
+        }
         return in[rec_slot(c_start[d] + (v - pd), p.cap, c_fix[d], c_ovf[d])];
     };
 
@@ -288,7 +310,7 @@ __global__ void __launch_bounds__(1024) k_tile_step(TileParams p, uint32_t t, ui
         const uint32_t over = n_in > p.cap ? n_in - p.cap : 0u;
         uint32_t ovf = 0, store = 1;
         if (over) {
-            const uint32_t b = atomicAdd(p.ctr + 64 * (gen ^ 1), over);
+            const uint32_t b = atomicAdd(io.ovf_out, over);
             if (b > p.n - over) {    // more records than agents: write none
                 __hip_atomic_fetch_or(p.err, ERR_TILE_LISTS, __ATOMIC_RELAXED,
                                       __HIP_MEMORY_SCOPE_AGENT);
@@ -298,11 +320,11 @@ __global__ void __launch_bounds__(1024) k_tile_step(TileParams p, uint32_t t, ui
         }
         s_ovf = ovf;
         s_store = store;
-        if (tile == 0) p.ctr[64 * gen] = 0;     // overflow allocator of the next launch
+        if (tile == 0) *io.ovf_reset = 0;      // overflow allocator of the next launch
     }
     if (TRANS) {
         // counts of the tile and its ring, rows by wavefront
-        const uint32_t *C = p.C[gen ^ 1];
+        const uint32_t *C = io.C_in;
         for (uint32_t ry = wave; ry < h + 2; ry += nw) {
             int32_t gy = y0 + (int32_t)ry - 1;
             gy = gy < 0 ? gy + p.L : (gy >= p.L ? gy - p.L : gy);
@@ -343,7 +365,7 @@ __global__ void __launch_bounds__(1024) k_tile_step(TileParams p, uint32_t t, ui
                 uint32_t g = STAY;
                 if (act) {
                     rmv[j] = move_of(p, rid[j], rpk[j], t, w, h);
-                    g = rmv[j] >> 20;
+                    g = (rmv[j] >> 20) & 15u;
                     if ((rpk[j] & 1023u) >= w || ((rpk[j] >> 10) & 1023u) >= h)
                         __hip_atomic_fetch_or(p.err, ERR_TILE_LISTS, __ATOMIC_RELAXED,
                                               __HIP_MEMORY_SCOPE_AGENT);
@@ -371,7 +393,7 @@ __global__ void __launch_bounds__(1024) k_tile_step(TileParams p, uint32_t t, ui
         const uint32_t hu = uj + 1 == nT ? last : T, hd = dj + 1 == nT ? last : T;
         const uint32_t total = 2 * (w + 2) + 2 * h + 2 * h + 2 * (w + 2) + 24;
         for (uint32_t k = tid; k < total; k += NT) {
-            const RingSeg e = ring_entry<RW>(p.ring[gen ^ 1], p.rs, nT, k, ti, tj, li, ri, uj,
+            const RingSeg e = ring_entry<RW>(io.ring_in, p.rs, nT, k, ti, tj, li, ri, uj,
                                              dj, w, h, wl, wr, hu, hd);
             const uint32_t v = *e.src;
             if (v) atomicAdd(&reg[e.dst], v);
@@ -417,7 +439,7 @@ __global__ void __launch_bounds__(1024) k_tile_step(TileParams p, uint32_t t, ui
         wbase[tid] = b;
     }
     if (tid == 0) {
-        uint32_t *H = p.hdr[gen ^ 1] + (size_t)tile * TILE_HDR;
+        uint32_t *H = io.hdr_out + (size_t)tile * TILE_HDR;
         H[0] = s_ovf;
         for (int g = 0; g < 9; ++g) H[1 + g] = gtot[g];
     }
@@ -426,7 +448,7 @@ __global__ void __launch_bounds__(1024) k_tile_step(TileParams p, uint32_t t, ui
     // pass 2: transition, bin, write
     const bool store = s_store != 0;
     const uint32_t fix = tile * p.cap, ovf = s_ovf;
-    uint2 *out = p.rec[gen ^ 1];
+    uint2 *out = io.rec_out;
     const uint32_t wl = li + 1 == nT ? last : T;   // width of the tile to the left
     const uint32_t hb = uj + 1 == nT ? last : T;   // height of the tile above
     uint32_t *mine = wbase + wave * 9;
@@ -450,9 +472,9 @@ __global__ void __launch_bounds__(1024) k_tile_step(TileParams p, uint32_t t, ui
                                             (rpk[j] >> 10) & 1023u, t - 1);
                 const uint32_t m = rmv[j];
                 const uint32_t cx = m & 1023u, cy = (m >> 10) & 1023u;   // new local + 1
-                g = m >> 20;
+                g = (m >> 20) & 15u;
                 if (s == ST_I && cx <= w + 1 && cy <= h + 1) atomicAdd(&hist[cy * RW + cx], 1u);
-                const uint32_t gx = g % 3, gy = g / 3;
+                const uint32_t gx = (m >> 24) & 3u, gy = (m >> 26) & 3u;
                 const uint32_t dx = gx == 0 ? wl - 1 : (gx == 2 ? 0u : cx - 1);
                 const uint32_t dy = gy == 0 ? hb - 1 : (gy == 2 ? 0u : cy - 1);
                 pk = dx | (dy << 10) | (s << 20);
@@ -478,13 +500,13 @@ __global__ void __launch_bounds__(1024) k_tile_step(TileParams p, uint32_t t, ui
 
     // counts of step t: interior to the grid (rows by wavefront), ring to the
     // tile's ring array
-    uint32_t *C = p.C[gen];
+    uint32_t *C = io.C_out;
     for (uint32_t ly = wave; ly < h; ly += nw) {
         uint32_t *row = C + (size_t)((uint32_t)y0 + ly) * (uint32_t)p.L + (uint32_t)x0;
         const uint32_t *src = hist + (ly + 1) * RW + 1;
         for (uint32_t lx = lane; lx < w; lx += 64) row[lx] = src[lx];
     }
-    uint32_t *R = p.ring[gen] + (size_t)tile * p.rs;
+    uint32_t *R = io.ring_out + (size_t)tile * p.rs;
     const uint32_t rsz = ring_size(w, h);
     for (uint32_t r = tid; r < rsz; r += NT) {
         int32_t lx, ly;
@@ -618,10 +640,21 @@ template <uint32_t T>
 hipError_t step_launch(const TileParams &p, uint32_t t, uint32_t gen, uint32_t phase,
                        uint32_t block, hipStream_t st)
 {
+    StepIO io;
+    io.rec_in = p.rec[gen];
+    io.rec_out = p.rec[gen ^ 1];
+    io.hdr_in = p.hdr[gen];
+    io.hdr_out = p.hdr[gen ^ 1];
+    io.C_in = p.C[gen ^ 1];        // counts of the previous launch
+    io.C_out = p.C[gen];
+    io.ring_in = p.ring[gen ^ 1];
+    io.ring_out = p.ring[gen];
+    io.ovf_out = p.ctr + 64 * (gen ^ 1);
+    io.ovf_reset = p.ctr + 64 * gen;
     const dim3 grid(p.nT * p.nT), thr(block);
-    if (phase == 0) hipLaunchKernelGGL((k_tile_step<T, false, true>), grid, thr, 0, st, p, t, gen);
-    else if (phase == 1) hipLaunchKernelGGL((k_tile_step<T, true, true>), grid, thr, 0, st, p, t, gen);
-    else hipLaunchKernelGGL((k_tile_step<T, true, false>), grid, thr, 0, st, p, t, gen);
+    if (phase == 0) hipLaunchKernelGGL((k_tile_step<T, false, true>), grid, thr, 0, st, p, io, t);
+    else if (phase == 1) hipLaunchKernelGGL((k_tile_step<T, true, true>), grid, thr, 0, st, p, io, t);
+    else hipLaunchKernelGGL((k_tile_step<T, true, false>), grid, thr, 0, st, p, io, t);
     return hipGetLastError();
 }
 
