@@ -243,18 +243,22 @@ def roofline_big(torch, A, log2n):
     pop.release()
     torch.cuda.empty_cache()
 
-    # wealth: 8 B per agent + 8 B per donor
-    pop = A.Population(A.WEALTH, n, wealth_init=1)
-    pop.step(2)
-    (w,) = pop.read()
-    donors = int((w > 0).sum())
-    del w
-    pop.profile(True)
-    pop.step(1)
-    res["wealth_step"] = priced("wealth_step", pop.kernel_times(), 8 * n + 8 * donors)
-    res["wealth_step"]["donors"] = donors
-    pop.release()
-    torch.cuda.empty_cache()
+    # wealth at n: partition exchange (2^15-agent partitions) and the global
+    # atomic scatter; 8 B per agent + 8 B per donor
+    for form, name, label in ((2, "wealth_exchange", "wealth_exchange"),
+                              (1, "wealth_step", "wealth_step")):
+        pop = A.Population(A.WEALTH, n, wealth_init=1)
+        pop.tune(wealth_form=form)
+        pop.step(2)
+        (w,) = pop.read()
+        donors = int((w > 0).sum())
+        del w
+        pop.profile(True)
+        pop.step(3)
+        res[label] = priced(name, pop.kernel_times(), 8 * n + 8 * donors)
+        res[label]["donors_after_step_2"] = donors
+        pop.release()
+        torch.cuda.empty_cache()
 
     # SIR pipelined body: 18 B per agent + 8 B per cell + 8 B per infected,
     # in both count modes (gather: the body reads the 3x3 block of the count

@@ -229,7 +229,7 @@ typedef struct {
                                   1 = global atomic scatter-add, 2 = partition
                                   exchange (recipient ids counting-sorted by
                                   destination in LDS, counted by the owner;
-                                  AMBER_E_UNSUPPORTED above 2^24 agents)         */
+                                  AMBER_E_UNSUPPORTED above 2^27 agents)         */
     uint32_t sir_tile;         /* tiled count mode: tile side 32 or 64 cells
                                   (0 = automatic)                                 */
     uint32_t reserved[2];

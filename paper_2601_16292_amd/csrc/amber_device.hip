@@ -113,6 +113,15 @@ __global__ __launch_bounds__(1024) void k_wealth_x(WealthXParams x, uint32_t t, 
                                         (mode & 2u) != 0, hist, pcount, poff, praw);
 }
 
+__global__ __launch_bounds__(1024) void k_wealth_x15(WealthXParams x, uint32_t t, uint32_t parity_in,
+                                                     uint32_t mode)
+{
+    __shared__ int32_t hist[1u << 15];
+    __shared__ uint32_t buf[WX15_BUF];
+    wealth_exchange_partition15(x, blockIdx.x, t, parity_in, (mode & 1u) != 0, (mode & 2u) != 0,
+                                hist, buf);
+}
+
 // head: move + bin(t)
 template <bool BOX>
 __global__ void k_sir_head(SirParams p, uint32_t t)
@@ -565,6 +574,7 @@ uint32_t wealth_exchange_bits(uint32_t n)
 {
     if (n <= (1u << 21)) return 12;            // up to 512 partitions of 4096 agents
     if (n <= (1u << 24)) return 14;            // up to 1024 partitions of 16384 agents
+    if (n <= (1u << 27)) return 15;            // up to 4096 partitions of 32768 agents
     return 0;                                  // too many partitions: atomic path
 }
 
@@ -577,6 +587,9 @@ hipError_t launch_wealth_exchange(const WealthXParams &x, uint32_t t, uint32_t p
     } else if (bits == 14) {
         if (x.P > 1024) return hipErrorInvalidValue;
         hipLaunchKernelGGL((k_wealth_x<14, 1024>), dim3(x.P), dim3(1024), 0, st, x, t, parity_in, mode);
+    } else if (bits == 15) {
+        if (x.P > WX15_PMAX) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_wealth_x15, dim3(x.P), dim3(1024), 0, st, x, t, parity_in, mode);
     } else {
         return hipErrorInvalidValue;
     }

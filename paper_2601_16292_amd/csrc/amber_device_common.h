@@ -304,6 +304,107 @@ __device__ __forceinline__ void wealth_exchange_partition(const WealthXParams &x
     for (uint32_t d = tid; d < P; d += 1024) tab_out[d] = (poff[d] << 16) | pcount[d];
 }
 
+// Partitions of 2^15 agents (populations above 2^24, up to 2^27 agents in
+// 4096 partitions).  The histogram takes 128 KB of LDS, so the fold reads
+// the sources' table entries 1024 at a time, and the producer scans its
+// per-destination counts in place (one array of P + 1 words).  buf holds
+// at least WX15_BUF words.
+constexpr uint32_t WX15_PMAX = 4096;
+constexpr uint32_t WX15_BUF = 5120;
+__device__ __forceinline__ void wealth_exchange_partition15(const WealthXParams &x, uint32_t p,
+                                                            uint32_t t, uint32_t parity_in,
+                                                            bool consume, bool produce,
+                                                            int32_t *hist, uint32_t *buf)
+{
+    constexpr uint32_t XB = 15, XR = 1u << XB, G = XR / 4096;   // 8 groups per thread
+    const uint32_t tid = threadIdx.x;
+    const uint32_t P = x.P;
+    const uint32_t groups = groups_of(x.n);
+    for (uint32_t i = tid; i < XR; i += 1024) hist[i] = 0;
+    if (consume) {
+        const uint32_t *tab = x.tab[parity_in];
+        const uint32_t *rec = x.rec[parity_in];
+        uint32_t *cnt = buf, *pre = buf + 1024, *raw = buf + 2048;
+        for (uint32_t c0 = 0; c0 < P; c0 += 1024) {
+            __syncthreads();                      // the previous chunk is folded
+            const uint32_t s = c0 + tid;
+            const uint32_t e = s < P ? tab[(size_t)s * P + p] : 0u;
+            raw[tid] = e;
+            cnt[tid] = e & 0xffffu;
+            __syncthreads();
+            block_exclusive_scan_1024(cnt, pre, 1024);
+            const uint32_t total = pre[1023] + cnt[1023];
+            const uint32_t ns = P - c0 < 1024 ? P - c0 : 1024u;
+            for (uint32_t i = tid; i < total; i += 1024) {
+                uint32_t lo = 0, hi = ns;             // last source with pre[s] <= i
+                while (hi - lo > 1) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (pre[mid] <= i) lo = mid;
+                    else hi = mid;
+                }
+                const uint32_t r = rec[(size_t)(c0 + lo) * XR + (raw[lo] >> 16) + (i - pre[lo])];
+                atomicAdd(&hist[r - p * XR], 1);
+            }
+        }
+    }
+    __syncthreads();
+    uint32_t *pcount = buf;                       // P counts, then P + 1 offsets
+    for (uint32_t i = tid; i <= P; i += 1024) pcount[i] = 0;
+    __syncthreads();
+    uint32_t rcp[G][4], rank[G][4];
+#pragma unroll
+    for (uint32_t g = 0; g < G; ++g) {
+        const uint32_t local = g * 1024 + tid;                 // group within the partition
+        const uint32_t q = p * (XR / 4) + local;
+        int4 V = make_int4(0, 0, 0, 0);
+        if (q < groups) {
+            const int4 W = ((const int4 *)x.w)[q];
+            V = make_int4(W.x + hist[4 * local], W.y + hist[4 * local + 1],
+                          W.z + hist[4 * local + 2], W.w + hist[4 * local + 3]);
+        }
+        if (!produce) {
+            if (q < groups) ((int4 *)x.w)[q] = V;
+            continue;
+        }
+        const uint32_t a = 4 * q;
+        const int32_t v[4] = {V.x, V.y, V.z, V.w};
+        bool d[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            d[j] = q < groups && v[j] > 0 && a + j < x.n;
+            rcp[g][j] = 0xffffffffu;
+        }
+        if (d[0] | d[1]) {
+            const uint4 r = philox(2 * q, t, P_RECIPIENT, x.k0, x.k1);
+            if (d[0]) rcp[g][0] = recipient(r.x, r.y, x.n);
+            if (d[1]) rcp[g][1] = recipient(r.z, r.w, x.n);
+        }
+        if (d[2] | d[3]) {
+            const uint4 r = philox(2 * q + 1, t, P_RECIPIENT, x.k0, x.k1);
+            if (d[2]) rcp[g][2] = recipient(r.x, r.y, x.n);
+            if (d[3]) rcp[g][3] = recipient(r.z, r.w, x.n);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            rank[g][j] = d[j] ? atomicAdd(&pcount[rcp[g][j] >> XB], 1u) : 0u;
+        if (q < groups)
+            ((int4 *)x.w)[q] = make_int4(v[0] - d[0], v[1] - d[1], v[2] - d[2], v[3] - d[3]);
+    }
+    if (!produce) return;
+    __syncthreads();
+    block_exclusive_scan<1024, 5>(pcount, pcount, P + 1);      // counts -> offsets, total last
+    uint32_t *rec_out = x.rec[parity_in ^ 1u] + (size_t)p * XR;
+#pragma unroll
+    for (uint32_t g = 0; g < G; ++g)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (rcp[g][j] != 0xffffffffu)
+                rec_out[pcount[rcp[g][j] >> XB] + rank[g][j]] = rcp[g][j];
+    uint32_t *tab_out = x.tab[parity_in ^ 1u] + (size_t)p * P;
+    for (uint32_t d = tid; d < P; d += 1024)
+        tab_out[d] = (pcount[d] << 16) | (pcount[d + 1] - pcount[d]);
+}
+
 // Small populations: one workgroup runs every step with the wealth column and
 // the increments in LDS; two barriers per step separate the donor/scatter
 // phase from the apply phase.  A thread owns agent pairs (one RECIPIENT

@@ -316,6 +316,23 @@ def test_wealth_forms_match_oracle(A, O, n, w0, steps, form):
     assert_same(got, inv, ref, steps)
 
 
+@pytest.mark.parametrize("n,w0,steps,chunks", [((1 << 24) + 12345, 1, 3, [3]),
+                                               ((1 << 25) + 7, 2, 4, [1, 3]),
+                                               (40_000_001, 1, 3, [2, 1])])
+def test_wealth_exchange_above_2p24(A, O, n, w0, steps, chunks):
+    """Partitions of 2^15 agents: more than 1024 partitions (the fold reads
+    its table column in chunks) and the fold-only call boundary."""
+    say(f"case wealth exchange 2^15 partitions n={n} chunks={chunks}")
+    pop = A.Population(A.WEALTH, n, seed=3, stream_id=7, wealth_init=w0)
+    pop.tune(wealth_form=2)
+    for c in chunks:
+        pop.step(c)
+    got, inv = pop.read(), pop.invariants()
+    pop.release()
+    ref = O.OracleRun(O.WEALTH, n, seed=3, stream=7, wealth_init=w0).step(steps)
+    assert_same(got, inv, ref, steps)
+
+
 def test_wealth_forms_mixed_across_calls(A, O):
     n = 300007
     chunks = [1, 3, 1, 2, 5, 1]
