@@ -701,15 +701,38 @@ __device__ __forceinline__ uint32_t *bin_target(const SirParams &p, uint32_t t)
 }
 
 // head(t): move + bin(t) of group q.
+// Column accesses of the per-step SIR kernels are streaming: marked
+// non-temporal so they do not push the count grid (gathered at random) out
+// of the L2.
+typedef int32_t i32x4_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ int4 load_nt4(const int32_t *p, uint32_t q)
+{
+    const i32x4_t v = __builtin_nontemporal_load((const i32x4_t *)p + q);
+    return make_int4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void store_nt4(int32_t *p, uint32_t q, const int4 &v)
+{
+    const i32x4_t w = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(w, (i32x4_t *)p + q);
+}
+__device__ __forceinline__ uint32_t load_nt1(const uint8_t *p, uint32_t q)
+{
+    return __builtin_nontemporal_load((const uint32_t *)p + q);
+}
+__device__ __forceinline__ void store_nt1(uint8_t *p, uint32_t q, uint32_t v)
+{
+    __builtin_nontemporal_store(v, (uint32_t *)p + q);
+}
+
 template <bool BOX>
 __device__ __forceinline__ void sir_head_group(const SirParams &p, uint32_t q, uint32_t t)
 {
-    int4 X = ((const int4 *)p.x)[q];
-    int4 Y = ((const int4 *)p.y)[q];
-    const uint32_t S = ((const uint32_t *)p.s)[q];
+    int4 X = load_nt4(p.x, q);
+    int4 Y = load_nt4(p.y, q);
+    const uint32_t S = load_nt1(p.s, q);
     sir_move4(p, q, t, X, Y);
-    ((int4 *)p.x)[q] = X;
-    ((int4 *)p.y)[q] = Y;
+    store_nt4(p.x, q, X);
+    store_nt4(p.y, q, Y);
     sir_bin4(p, bin_target<BOX>(p, t), q, S, X, Y);
 }
 
@@ -717,14 +740,14 @@ __device__ __forceinline__ void sir_head_group(const SirParams &p, uint32_t q, u
 template <bool BOX>
 __device__ __forceinline__ void sir_body_group(const SirParams &p, uint32_t q, uint32_t t)
 {
-    int4 X = ((const int4 *)p.x)[q];
-    int4 Y = ((const int4 *)p.y)[q];
-    const uint32_t S = ((const uint32_t *)p.s)[q];
+    int4 X = load_nt4(p.x, q);
+    int4 Y = load_nt4(p.y, q);
+    const uint32_t S = load_nt1(p.s, q);
     const uint32_t S2 = sir_transition4<BOX>(p, kin<BOX>(p, t - 1), q, t - 1, S, X, Y);
     sir_move4(p, q, t, X, Y);
-    ((int4 *)p.x)[q] = X;
-    ((int4 *)p.y)[q] = Y;
-    if (S2 != S) ((uint32_t *)p.s)[q] = S2;
+    store_nt4(p.x, q, X);
+    store_nt4(p.y, q, Y);
+    if (S2 != S) store_nt1(p.s, q, S2);
     sir_bin4(p, bin_target<BOX>(p, t), q, S2, X, Y);
 }
 
@@ -732,11 +755,11 @@ __device__ __forceinline__ void sir_body_group(const SirParams &p, uint32_t q, u
 template <bool BOX>
 __device__ __forceinline__ void sir_tail_group(const SirParams &p, uint32_t q, uint32_t t)
 {
-    const int4 X = ((const int4 *)p.x)[q];
-    const int4 Y = ((const int4 *)p.y)[q];
-    const uint32_t S = ((const uint32_t *)p.s)[q];
+    const int4 X = load_nt4(p.x, q);
+    const int4 Y = load_nt4(p.y, q);
+    const uint32_t S = load_nt1(p.s, q);
     const uint32_t S2 = sir_transition4<BOX>(p, kin<BOX>(p, t), q, t, S, X, Y);
-    if (S2 != S) ((uint32_t *)p.s)[q] = S2;
+    if (S2 != S) store_nt1(p.s, q, S2);
 }
 
 // ------------------------------------------------------------------ SIR, exchange count mode
