@@ -122,20 +122,68 @@ __global__ __launch_bounds__(1024) void k_wealth_x15(WealthXParams x, uint32_t t
                                 hist, buf);
 }
 
-// head: move + bin(t)
+// head: move + bin(t).  The gather-mode head also clears demand map 2 and
+// counts the states of the call's first step (demand-driven binning); its
+// last workgroup holds no agents and does the bookkeeping.
 template <bool BOX>
 __global__ void k_sir_head(SirParams p, uint32_t t)
 {
+    if (BOX) {
+        const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+        if (q < p.groups) sir_head_group<BOX>(p, q, t);
+        return;
+    }
+    const uint32_t nb = gridDim.x - 1;
+    if (blockIdx.x == nb) {
+        sir_demand_book(p, 0);
+        return;
+    }
+    __shared__ uint32_t s_wc[2 * 16];              // per-wavefront S and I counts
     const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q < p.groups) sir_head_group<BOX>(p, q, t);
+    zero_quads((uint32_t *)p.dmap[2], p.dquads, q, nb * blockDim.x);
+    uint32_t S = 0;
+    if (q < p.groups) {
+        int4 X = load_nt4(p.x, q);
+        int4 Y = load_nt4(p.y, q);
+        S = load_nt1(p.s, q);
+        sir_move4(p, q, t, X, Y);
+        store_nt4(p.x, q, X);
+        store_nt4(p.y, q, Y);
+        sir_bin_mark4(p, grid_of(p, t), q, S, X, Y, 0u, nullptr, nullptr);
+    }
+    sir_count_states(p, 0, q, S, q < p.groups, s_wc);
 }
 
-// body (gather mode): transition(t-1), then move + bin(t); clears the grid of t+1.
+// body (gather mode): transition(t-1), then move + bin(t), binning only on
+// the demand map's cells when F_i is set and marking the next map when
+// F_{i+1} is; clears the count grid of t+1 and the demand map of t+2.  The
+// last workgroup holds no agents and does the bookkeeping.
 __global__ void k_sir_body(SirParams p, uint32_t t)
 {
+    const uint32_t i = t - p.t_base;
+    const uint32_t nb = gridDim.x - 1;
+    if (blockIdx.x == nb) {
+        sir_demand_book(p, i);
+        return;
+    }
+    __shared__ uint32_t s_wc[2 * 16];              // per-wavefront S and I counts
     const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-    zero_quads(grid_of(p, t + 1), p.quads, q, gridDim.x * blockDim.x);
-    if (q < p.groups) sir_body_group<false>(p, q, t);
+    const uint32_t mode = sir_demand_modes(p, i);
+    zero_quads(grid_of(p, t + 1), p.quads, q, nb * blockDim.x);
+    zero_quads((uint32_t *)p.dmap[(i + 2) % 3], p.dquads, q, nb * blockDim.x);
+    uint32_t S2 = 0;
+    if (q < p.groups) {
+        int4 X = load_nt4(p.x, q);
+        int4 Y = load_nt4(p.y, q);
+        const uint32_t S = load_nt1(p.s, q);
+        S2 = sir_transition4<false>(p, grid_of(p, t - 1), q, t - 1, S, X, Y);
+        sir_move4(p, q, t, X, Y);
+        store_nt4(p.x, q, X);
+        store_nt4(p.y, q, Y);
+        if (S2 != S) store_nt1(p.s, q, S2);
+        sir_bin_mark4(p, grid_of(p, t), q, S2, X, Y, mode, p.dmap[i % 3], p.dmap[(i + 1) % 3]);
+    }
+    sir_count_states(p, i, q, S2, q < p.groups, s_wc);
 }
 
 // body (box mode): transition(t-1) from K, then move + bin(t).
@@ -197,6 +245,9 @@ __global__ void k_sir_clear(SirParams p, uint32_t mask)
     const uint32_t stride = gridDim.x * blockDim.x;
     for (int b = 0; b < 3; ++b)
         if (mask & (1u << b)) zero_quads(p.count[b], p.quads, i, stride);
+    // the demand-binning step counts and flags start the next call at zero
+    if (p.nsi && i < 4 * 2 * NSI_SLOTS) p.nsi[i * NSI_STRIDE] = 0;
+    if (p.nsi && i < 4) p.nsi[NSI_FLAGS + i] = 0;
 }
 
 // ------------------------------------------------------------------ SIR, persistent form
@@ -609,6 +660,7 @@ void sir_fill(SirParams &p)
 {
     p.groups = groups_of(p.n);
     p.quads = div_up((uint32_t)p.L * (uint32_t)p.L, 4);
+    p.dquads = div_up((uint32_t)p.L * (uint32_t)p.L, 16);
 }
 
 hipError_t launch_sir_head(SirParams p, uint32_t t, bool box, const Tuning &tu, hipStream_t st)
@@ -616,8 +668,9 @@ hipError_t launch_sir_head(SirParams p, uint32_t t, bool box, const Tuning &tu, 
     sir_fill(p);
     if (box)
         hipLaunchKernelGGL(k_sir_head<true>, grid_for(p.groups, tu.block), dim3(tu.block), 0, st, p, t);
-    else
-        hipLaunchKernelGGL(k_sir_head<false>, grid_for(p.groups, tu.block), dim3(tu.block), 0, st, p, t);
+    else   // one extra workgroup for the demand-binning bookkeeping
+        hipLaunchKernelGGL(k_sir_head<false>, dim3(grid_for(p.groups, tu.block).x + 1),
+                           dim3(tu.block), 0, st, p, t);
     return hipGetLastError();
 }
 
@@ -626,8 +679,9 @@ hipError_t launch_sir_body(SirParams p, uint32_t t, bool box, const Tuning &tu, 
     sir_fill(p);
     if (box)
         hipLaunchKernelGGL(k_sir_body_box, grid_for(p.groups, tu.block), dim3(tu.block), 0, st, p, t);
-    else
-        hipLaunchKernelGGL(k_sir_body, grid_for(p.groups, tu.block), dim3(tu.block), 0, st, p, t);
+    else   // one extra workgroup for the demand-binning bookkeeping
+        hipLaunchKernelGGL(k_sir_body, dim3(grid_for(p.groups, tu.block).x + 1), dim3(tu.block), 0,
+                           st, p, t);
     return hipGetLastError();
 }
 
@@ -686,6 +740,7 @@ hipError_t launch_sir_clear(SirParams p, uint32_t mask, hipStream_t st)
     sir_fill(p);
     uint32_t blocks = div_up(p.quads, 256);
     if (blocks > 2048) blocks = 2048;
+    if (blocks < div_up(4 * 2 * NSI_SLOTS, 256)) blocks = div_up(4 * 2 * NSI_SLOTS, 256);   // counts too
     hipLaunchKernelGGL(k_sir_clear, dim3(blocks), dim3(256), 0, st, p, mask);
     return hipGetLastError();
 }

@@ -762,6 +762,141 @@ __device__ __forceinline__ void sir_tail_group(const SirParams &p, uint32_t q, u
     if (S2 != S) store_nt1(p.s, q, S2);
 }
 
+// ------------------------------------------------------------------ SIR, demand-driven binning
+// The gather mode bins an infected agent into the count grid only where some
+// susceptible agent will read the count.  Susceptible agents never come back
+// and move one cell per step, so the 5 x 5 block around a susceptible
+// agent's post-move cell of step i covers its whole 3 x 3 block of step i+1.
+// Launch i of a call (call-relative) may therefore mark, in demand map
+// (i+1) % 3, the 5 x 5 blocks of its susceptible agents, so that launch i+1
+// bins only the infected agents whose cell is marked.  Marking costs 25 byte
+// stores per susceptible agent and saves one global atomic per infected
+// agent off the marked cells.
+//
+// Flag F_j (targeted binning at step j) is decided by launch j-2 from the
+// complete S and I counts of step j-3 (sir_targeted).  Launch j-1 marks iff
+// F_j and launch j bins on marked cells iff F_j, so the two always agree;
+// F_0 = F_1 = F_2 = 0.  Every count that is read is exact; counts nobody
+// reads are not produced.
+
+// Targeted binning pays a dependent byte load per infected agent in place
+// of a fire-and-forget atomic: worth it while the atomics are many (at least
+// a tenth of the agents infected) and the susceptible agents few.
+__device__ __forceinline__ bool sir_targeted(uint32_t ns, uint32_t ni, uint32_t n)
+{
+    return 32ull * ns <= (uint64_t)ni && 10ull * ni >= (uint64_t)n;
+}
+
+// Counts of call-relative step j: slot k of S at [k * NSI_STRIDE], of I at
+// [(NSI_SLOTS + k) * NSI_STRIDE].
+__device__ __forceinline__ uint32_t *sir_counts_of(const SirParams &p, uint32_t j)
+{
+    return p.nsi + (j & 3u) * 2 * NSI_SLOTS * NSI_STRIDE;
+}
+
+// Bookkeeping of launch i, run by one extra workgroup that holds no agents
+// (so the latency of reading the counts stays off the agents' path):
+// publish F_{i+2} and zero the counts of step i+1 (last read by launch i-1).
+__device__ __forceinline__ void sir_demand_book(const SirParams &p, uint32_t i)
+{
+    if (threadIdx.x < 64) {
+        uint32_t flag = 0;
+        if (i >= 1) {
+            const uint32_t *c = sir_counts_of(p, i - 1);
+            uint32_t a = c[threadIdx.x * NSI_STRIDE];
+            uint32_t b = c[(NSI_SLOTS + threadIdx.x) * NSI_STRIDE];
+            for (int off = 32; off >= 1; off >>= 1) {
+                a += __shfl_xor(a, off, 64);
+                b += __shfl_xor(b, off, 64);
+            }
+            flag = sir_targeted(a, b, p.n) ? 1u : 0u;
+        }
+        if (threadIdx.x == 0) p.nsi[NSI_FLAGS + ((i + 2) & 3u)] = flag;
+    }
+    for (uint32_t k = threadIdx.x; k < 2 * NSI_SLOTS; k += blockDim.x)
+        sir_counts_of(p, i + 1)[k * NSI_STRIDE] = 0;
+}
+
+// Modes of launch i: bit 0 = mark demand map (i+1) % 3 (F_{i+1}), bit 1 =
+// bin only marked cells (F_i).
+__device__ __forceinline__ uint32_t sir_demand_modes(const SirParams &p, uint32_t i)
+{
+    const uint32_t mark = p.nsi[NSI_FLAGS + ((i + 1) & 3u)];
+    const uint32_t bin = p.nsi[NSI_FLAGS + (i & 3u)];
+    return (mark ? 1u : 0u) | (bin ? 2u : 0u);
+}
+
+// Adds the S and I agents of the group's states (packed S) to the counts of
+// step i: wavefront sums from ballots into per-wavefront LDS words (s_wc,
+// 2 per wavefront), a workgroup sum after one barrier, then one atomic per
+// workgroup and kind into one of NSI_SLOTS lines.  Every thread of the
+// workgroup must call it.
+__device__ __forceinline__ void sir_count_states(const SirParams &p, uint32_t i, uint32_t q,
+                                                 uint32_t S, bool valid, uint32_t *s_wc)
+{
+    uint32_t cs = 0, ci = 0;
+    if (valid) {
+#pragma unroll
+        for (uint32_t k = 0; k < 4; ++k) {
+            const uint32_t st = (S >> (8 * k)) & 0xffu;
+            const bool in = 4 * q + k < p.n;
+            cs += in && st == ST_S;
+            ci += in && st == ST_I;
+        }
+    }
+    uint32_t ws = 0, wi = 0;
+#pragma unroll
+    for (uint32_t b = 0; b < 3; ++b) {
+        ws += (uint32_t)__popcll(__ballot((cs >> b) & 1u)) << b;
+        wi += (uint32_t)__popcll(__ballot((ci >> b) & 1u)) << b;
+    }
+    if ((threadIdx.x & 63u) == 0) {
+        s_wc[2 * (threadIdx.x >> 6)] = ws;
+        s_wc[2 * (threadIdx.x >> 6) + 1] = wi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t ts = 0, ti = 0;
+        for (uint32_t w = 0; w < (blockDim.x >> 6); ++w) {
+            ts += s_wc[2 * w];
+            ti += s_wc[2 * w + 1];
+        }
+        const uint32_t slot = blockIdx.x % NSI_SLOTS;
+        uint32_t *c = sir_counts_of(p, i);
+        if (ts) atomicAdd(&c[slot * NSI_STRIDE], ts);
+        if (ti) atomicAdd(&c[(NSI_SLOTS + slot) * NSI_STRIDE], ti);
+    }
+}
+
+__device__ __forceinline__ void mark_demand(uint8_t *__restrict__ d, int32_t L, int32_t x, int32_t y)
+{
+    if (!on_grid(x, y, L)) return;
+    for (int32_t dy = -2; dy <= 2; ++dy) {
+        const int32_t yy = (y + dy + 2 * L) % L;
+        uint8_t *row = d + (size_t)yy * (uint32_t)L;
+        for (int32_t dx = -2; dx <= 2; ++dx) row[(x + dx + 2 * L) % L] = 1;
+    }
+}
+
+// Binning (all infected agents, or only those on marked cells) and marking
+// of one group after its transition and move.
+__device__ __forceinline__ void sir_bin_mark4(const SirParams &p, uint32_t *__restrict__ count,
+                                              uint32_t q, uint32_t S, const int4 &X, const int4 &Y,
+                                              uint32_t mode, const uint8_t *__restrict__ dcur,
+                                              uint8_t *__restrict__ dnext)
+{
+    const uint32_t a = 4 * q;
+    const int32_t xs[4] = {X.x, X.y, X.z, X.w}, ys[4] = {Y.x, Y.y, Y.z, Y.w};
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k) {
+        const uint32_t st = (S >> (8 * k)) & 0xffu;
+        if (a + k >= p.n || !on_grid(xs[k], ys[k], p.L)) continue;
+        const uint32_t c = (uint32_t)ys[k] * (uint32_t)p.L + (uint32_t)xs[k];
+        if (st == ST_I && (!(mode & 2u) || dcur[c])) atomicAdd(&count[c], 1u);
+        if (st == ST_S && (mode & 1u)) mark_demand(dnext, p.L, xs[k], ys[k]);
+    }
+}
+
 // ------------------------------------------------------------------ SIR, exchange count mode
 // Binning without global atomics.  The grid is cut into bands of xh rows
 // (xP >= 3 bands).  The body kernel (256 threads, 1024 agents per workgroup)

@@ -204,6 +204,7 @@ struct Resolved {
     std::vector<uint32_t> t_inf;
     // workspace layout (byte offsets)
     uint64_t off_inc0 = 0, off_inc1 = 0, off_table = 0, off_count[3] = {0, 0, 0}, off_sync = 0;
+    uint64_t off_nsi = 0, off_dmap[3] = {0, 0, 0};
     uint32_t xbits = 0, xparts = 0;                 // wealth partition exchange (0 = unavailable)
     uint32_t sx_h = 0, sx_P = 0, sx_W = 0;          // SIR exchange count mode (0 = unavailable)
     uint64_t off_sxrec = 0, off_sxtab = 0;
@@ -277,6 +278,12 @@ amber_status_t resolve(const amber_run_desc_t *d, Resolved &r, bool want_table)
             for (int b = 0; b < 3; ++b) {
                 r.off_count[b] = ws;
                 ws += align_up(cells, 256);
+            }
+            r.off_nsi = ws;
+            ws += align_up((uint64_t)NSI_WORDS * 4, 256);
+            for (int b = 0; b < 3; ++b) {
+                r.off_dmap[b] = ws;
+                ws += align_up((uint64_t)L * L, 256);
             }
             r.off_sync = ws;
             ws += align_up((uint64_t)SYNC_WORDS * 4, 256);
@@ -488,7 +495,11 @@ SirParams sir_params(amber_pop *p)
     sp.x = col_i32(p, AMBER_COL_X);
     sp.y = col_i32(p, AMBER_COL_Y);
     sp.s = (uint8_t *)p->b.col[AMBER_COL_STATE];
-    for (int b = 0; b < 3; ++b) sp.count[b] = (uint32_t *)ws_ptr(p, r.off_count[b]);
+    for (int b = 0; b < 3; ++b) {
+        sp.count[b] = (uint32_t *)ws_ptr(p, r.off_count[b]);
+        sp.dmap[b] = ws_ptr(p, r.off_dmap[b]);
+    }
+    sp.nsi = (uint32_t *)ws_ptr(p, r.off_nsi);
     sp.t_inf = (const uint32_t *)ws_ptr(p, r.off_table);
     sp.table_len = (uint32_t)r.t_inf.size();
     sp.t_rec = r.t_rec;
@@ -1012,6 +1023,9 @@ amber_status_t amber_init_population(const amber_run_desc_t *desc, const amber_b
             if (e == hipSuccess)
                 e = launch_zero_words((uint32_t *)ws_ptr(p, rr.off_count[0]), 3 * cell_words,
                                       p->stream);
+            if (e == hipSuccess)     // the demand-binning counts start at zero
+                e = launch_zero_words((uint32_t *)ws_ptr(p, rr.off_nsi),
+                                      (rr.off_dmap[0] - rr.off_nsi) / 4, p->stream);
             if (e == hipSuccess)
                 p->persist_g = sir_persistent_groups_per_thread(rr.n, 8, &p->persist_blocks);
             if (e == hipSuccess)

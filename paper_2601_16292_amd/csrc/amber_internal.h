@@ -48,12 +48,27 @@ struct SirParams {
     uint32_t k0, k1;           // Philox key (seed, stream)
     uint32_t groups;           // ceil(n / 4), filled by the launcher
     uint32_t quads;            // ceil(L*L / 4), filled by the launcher
+    uint32_t dquads;           // ceil(L*L / 16): 16-byte words of a demand map
     uint32_t t_base;           // first step of the current call (grid rotation origin)
+    // demand-driven binning (gather mode, see sir_body_demand): dmap[g] marks
+    // the cells some susceptible agent may read; nsi holds per-step S and I
+    // counts and the targeted-binning flags
+    uint8_t *dmap[3];
+    uint32_t *nsi;
     // exchange count mode (see sir_exchange_produce): null xrec = unavailable
     uint32_t *xrec;            // xW segments of 3*1024 cell records
     uint32_t *xtab;            // xtab[w*xP + band] = offset << 16 | count
     uint32_t xh, xP, xW;       // rows per band, bands (>= 3), producer workgroups
 };
+
+// Counts area of the demand-driven binning: for each call-relative step
+// parity (4), the S and I counts of that step spread over NSI_SLOTS words
+// each, one word per 128-byte line (atomics on one line serialise like
+// atomics on one word), then one targeted-binning flag per parity.
+constexpr uint32_t NSI_SLOTS = 64;
+constexpr uint32_t NSI_STRIDE = 32;
+constexpr uint32_t NSI_FLAGS = 4 * 2 * NSI_SLOTS * NSI_STRIDE;
+constexpr uint32_t NSI_WORDS = NSI_FLAGS + 4;
 
 // Record slots per producer workgroup of the SIR exchange mode (3 per agent).
 constexpr uint32_t XSEG_WORDS = 3 * 1024;
