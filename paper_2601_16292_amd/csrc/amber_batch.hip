@@ -82,6 +82,8 @@ __global__ __launch_bounds__(1024) void k_wealth_x_batch(WealthXBatch b, uint32_
 
 // ------------------------------------------------------------------ SIR (pipelined)
 
+// In gather mode each run's last workgroup holds no agents and does the
+// demand-binning bookkeeping (as in the single-run kernels).
 template <bool BOX>
 __global__ void k_sir_head_batch(SirBatch b)
 {
@@ -89,7 +91,16 @@ __global__ void k_sir_head_batch(SirBatch b)
     const uint32_t r = batch_run(b.block_end, b.nruns, lb, nb);
     const SirParams &p = b.run[r];
     const uint32_t q = lb * blockDim.x + threadIdx.x;
-    if (q < p.groups) sir_head_group<BOX>(p, q, b.t0[r]);
+    if (BOX) {
+        if (q < p.groups) sir_head_group<BOX>(p, q, b.t0[r]);
+        return;
+    }
+    if (lb == nb - 1) {
+        sir_demand_book(p, 0);
+        return;
+    }
+    __shared__ uint32_t s_wc[2 * 16];
+    sir_head_demand(p, q, (nb - 1) * blockDim.x, b.t0[r], lb, s_wc);
 }
 
 template <bool BOX>
@@ -100,8 +111,16 @@ __global__ void k_sir_body_batch(SirBatch b, uint32_t i)
     const SirParams &p = b.run[r];
     const uint32_t t = b.t0[r] + i;
     const uint32_t q = lb * blockDim.x + threadIdx.x;
-    if (!BOX) zero_quads(grid_of(p, t + 1), p.quads, q, nb * blockDim.x);
-    if (q < p.groups) sir_body_group<BOX>(p, q, t);
+    if (BOX) {
+        if (q < p.groups) sir_body_group<BOX>(p, q, t);
+        return;
+    }
+    if (lb == nb - 1) {
+        sir_demand_book(p, i);
+        return;
+    }
+    __shared__ uint32_t s_wc[2 * 16];
+    sir_body_demand(p, q, (nb - 1) * blockDim.x, t, i, lb, s_wc);
 }
 
 template <bool BOX>
@@ -136,6 +155,7 @@ __global__ void k_sir_clear_batch(SirBatch b, uint32_t mask)
     const uint32_t c = lb * blockDim.x + threadIdx.x;
     for (int g = 0; g < 3; ++g)
         if (mask & (1u << g)) zero_quads(p.count[g], p.quads, c, nb * blockDim.x);
+    if (lb == 0) sir_demand_reset(p, threadIdx.x, blockDim.x);
 }
 
 // Exchange count mode, batched: producer workgroups and band workgroups of

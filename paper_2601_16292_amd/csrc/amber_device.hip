@@ -139,19 +139,8 @@ __global__ void k_sir_head(SirParams p, uint32_t t)
         return;
     }
     __shared__ uint32_t s_wc[2 * 16];              // per-wavefront S and I counts
-    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-    zero_quads((uint32_t *)p.dmap[2], p.dquads, q, nb * blockDim.x);
-    uint32_t S = 0;
-    if (q < p.groups) {
-        int4 X = load_nt4(p.x, q);
-        int4 Y = load_nt4(p.y, q);
-        S = load_nt1(p.s, q);
-        sir_move4(p, q, t, X, Y);
-        store_nt4(p.x, q, X);
-        store_nt4(p.y, q, Y);
-        sir_bin_mark4(p, grid_of(p, t), q, S, X, Y, 0u, nullptr, nullptr);
-    }
-    sir_count_states(p, 0, q, S, q < p.groups, s_wc);
+    sir_head_demand(p, blockIdx.x * blockDim.x + threadIdx.x, nb * blockDim.x, t, blockIdx.x,
+                    s_wc);
 }
 
 // body (gather mode): transition(t-1), then move + bin(t), binning only on
@@ -167,23 +156,8 @@ __global__ void k_sir_body(SirParams p, uint32_t t)
         return;
     }
     __shared__ uint32_t s_wc[2 * 16];              // per-wavefront S and I counts
-    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t mode = sir_demand_modes(p, i);
-    zero_quads(grid_of(p, t + 1), p.quads, q, nb * blockDim.x);
-    zero_quads((uint32_t *)p.dmap[(i + 2) % 3], p.dquads, q, nb * blockDim.x);
-    uint32_t S2 = 0;
-    if (q < p.groups) {
-        int4 X = load_nt4(p.x, q);
-        int4 Y = load_nt4(p.y, q);
-        const uint32_t S = load_nt1(p.s, q);
-        S2 = sir_transition4<false>(p, grid_of(p, t - 1), q, t - 1, S, X, Y);
-        sir_move4(p, q, t, X, Y);
-        store_nt4(p.x, q, X);
-        store_nt4(p.y, q, Y);
-        if (S2 != S) store_nt1(p.s, q, S2);
-        sir_bin_mark4(p, grid_of(p, t), q, S2, X, Y, mode, p.dmap[i % 3], p.dmap[(i + 1) % 3]);
-    }
-    sir_count_states(p, i, q, S2, q < p.groups, s_wc);
+    sir_body_demand(p, blockIdx.x * blockDim.x + threadIdx.x, nb * blockDim.x, t, i, blockIdx.x,
+                    s_wc);
 }
 
 // body (box mode): transition(t-1) from K, then move + bin(t).
@@ -246,8 +220,7 @@ __global__ void k_sir_clear(SirParams p, uint32_t mask)
     for (int b = 0; b < 3; ++b)
         if (mask & (1u << b)) zero_quads(p.count[b], p.quads, i, stride);
     // the demand-binning step counts and flags start the next call at zero
-    if (p.nsi && i < 4 * 2 * NSI_SLOTS) p.nsi[i * NSI_STRIDE] = 0;
-    if (p.nsi && i < 4) p.nsi[NSI_FLAGS + i] = 0;
+    sir_demand_reset(p, i, stride);
 }
 
 // ------------------------------------------------------------------ SIR, persistent form

@@ -832,7 +832,8 @@ __device__ __forceinline__ uint32_t sir_demand_modes(const SirParams &p, uint32_
 // workgroup and kind into one of NSI_SLOTS lines.  Every thread of the
 // workgroup must call it.
 __device__ __forceinline__ void sir_count_states(const SirParams &p, uint32_t i, uint32_t q,
-                                                 uint32_t S, bool valid, uint32_t *s_wc)
+                                                 uint32_t S, bool valid, uint32_t *s_wc,
+                                                 uint32_t block)
 {
     uint32_t cs = 0, ci = 0;
     if (valid) {
@@ -861,7 +862,7 @@ __device__ __forceinline__ void sir_count_states(const SirParams &p, uint32_t i,
             ts += s_wc[2 * w];
             ti += s_wc[2 * w + 1];
         }
-        const uint32_t slot = blockIdx.x % NSI_SLOTS;
+        const uint32_t slot = block % NSI_SLOTS;
         uint32_t *c = sir_counts_of(p, i);
         if (ts) atomicAdd(&c[slot * NSI_STRIDE], ts);
         if (ti) atomicAdd(&c[(NSI_SLOTS + slot) * NSI_STRIDE], ti);
@@ -895,6 +896,60 @@ __device__ __forceinline__ void sir_bin_mark4(const SirParams &p, uint32_t *__re
         if (st == ST_I && (!(mode & 2u) || dcur[c])) atomicAdd(&count[c], 1u);
         if (st == ST_S && (mode & 1u)) mark_demand(dnext, p.L, xs[k], ys[k]);
     }
+}
+
+// Gather-mode head (launch 0 of a call) and body (launch i >= 1) for the
+// workgroup's agent groups, with demand-driven binning: q is the group of
+// this thread, threads the number of agent threads of the run's launch (the
+// stride of the demand-map clear), block the workgroup's index within the
+// run.  Every thread of the workgroup must call them (they end with a
+// workgroup barrier).
+__device__ __forceinline__ void sir_head_demand(const SirParams &p, uint32_t q, uint32_t threads,
+                                                uint32_t t, uint32_t block, uint32_t *s_wc)
+{
+    zero_quads((uint32_t *)p.dmap[2], p.dquads, q, threads);
+    uint32_t S = 0;
+    if (q < p.groups) {
+        int4 X = load_nt4(p.x, q);
+        int4 Y = load_nt4(p.y, q);
+        S = load_nt1(p.s, q);
+        sir_move4(p, q, t, X, Y);
+        store_nt4(p.x, q, X);
+        store_nt4(p.y, q, Y);
+        sir_bin_mark4(p, grid_of(p, t), q, S, X, Y, 0u, nullptr, nullptr);
+    }
+    sir_count_states(p, 0, q, S, q < p.groups, s_wc, block);
+}
+
+__device__ __forceinline__ void sir_body_demand(const SirParams &p, uint32_t q, uint32_t threads,
+                                                uint32_t t, uint32_t i, uint32_t block,
+                                                uint32_t *s_wc)
+{
+    const uint32_t mode = sir_demand_modes(p, i);
+    zero_quads(grid_of(p, t + 1), p.quads, q, threads);
+    zero_quads((uint32_t *)p.dmap[(i + 2) % 3], p.dquads, q, threads);
+    uint32_t S2 = 0;
+    if (q < p.groups) {
+        int4 X = load_nt4(p.x, q);
+        int4 Y = load_nt4(p.y, q);
+        const uint32_t S = load_nt1(p.s, q);
+        S2 = sir_transition4<false>(p, grid_of(p, t - 1), q, t - 1, S, X, Y);
+        sir_move4(p, q, t, X, Y);
+        store_nt4(p.x, q, X);
+        store_nt4(p.y, q, Y);
+        if (S2 != S) store_nt1(p.s, q, S2);
+        sir_bin_mark4(p, grid_of(p, t), q, S2, X, Y, mode, p.dmap[i % 3], p.dmap[(i + 1) % 3]);
+    }
+    sir_count_states(p, i, q, S2, q < p.groups, s_wc, block);
+}
+
+// End of a call: the demand-binning counts and flags start the next call at
+// zero (thread k of the run's first workgroup of a clear launch).
+__device__ __forceinline__ void sir_demand_reset(const SirParams &p, uint32_t k, uint32_t threads)
+{
+    if (!p.nsi) return;
+    for (uint32_t j = k; j < 4 * 2 * NSI_SLOTS; j += threads) p.nsi[j * NSI_STRIDE] = 0;
+    if (k < 4) p.nsi[NSI_FLAGS + k] = 0;
 }
 
 // ------------------------------------------------------------------ SIR, exchange count mode

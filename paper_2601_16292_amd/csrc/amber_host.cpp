@@ -913,7 +913,8 @@ amber_status_t run_batch(amber_pop *const *pops, uint32_t n, uint32_t n_steps)
                 b.run[j] = sir_params(p);
                 sir_fill(b.run[j]);
                 b.t0[j] = (uint32_t)p->step;
-                blocks += blocks_for(p->r.n);
+                // gather mode: one more workgroup per run for the demand-binning bookkeeping
+                blocks += blocks_for(p->r.n) + (mode == 1 ? 1u : 0u);
                 b.block_end[j] = blocks;
                 cblocks += (b.run[j].quads + 255) / 256;
                 b.cell_block_end[j] = cblocks;

@@ -94,3 +94,23 @@ def test_demand_binning_mixed_with_other_modes(A, O):
     for g, r in zip(got, ref.columns()):
         assert np.array_equal(g, r)
     assert inv["digest"] == ref.digest()
+
+
+def test_demand_binning_in_batches(A, O):
+    """The same cases stepped together through amber_step_batch (chunked
+    into two calls): every run equals the oracle."""
+    say("case demand binning batched")
+    pops = []
+    for k, (n, L, beta, gamma, chunks) in enumerate(CASES):
+        p = A.Population(A.SIR, n, L=L, seed=11, stream_id=3 + k, beta=beta, gamma=gamma)
+        p.tune(sir_form=A.SIR_PIPELINED, sir_count=A.COUNT_GATHER)
+        pops.append(p)
+    A.step_batch(pops, 37)
+    A.step_batch(pops, 23)
+    for k, (p, (n, L, beta, gamma, chunks)) in enumerate(zip(pops, CASES)):
+        ref = O.OracleRun(O.SIR, n, L, seed=11, stream=3 + k, beta=beta, gamma=gamma).step(60)
+        got, inv = p.read(), p.invariants()
+        for g, r in zip(got, ref.columns()):
+            assert np.array_equal(g, r), (n, L)
+        assert inv["digest"] == ref.digest()
+        p.release()
