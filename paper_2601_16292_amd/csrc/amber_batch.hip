@@ -66,9 +66,9 @@ __global__ void k_wealth_fold_batch(WealthBatch b, uint32_t parity)
     if (q < groups_of(b.n[r])) wealth_fold_group((int4 *)b.base[r], (int4 *)b.inc[parity][r], q);
 }
 
-template <int XB, int PMAX>
-__global__ __launch_bounds__(1024) void k_wealth_x_batch(WealthXBatch b, uint32_t i,
-                                                         uint32_t parity_in, uint32_t mode)
+template <int XB, int PMAX, int NT>
+__global__ __launch_bounds__(NT) void k_wealth_x_batch(WealthXBatch b, uint32_t i,
+                                                       uint32_t parity_in, uint32_t mode)
 {
     __shared__ int32_t hist[1u << XB];
     __shared__ uint32_t pcount[PMAX];
@@ -76,8 +76,9 @@ __global__ __launch_bounds__(1024) void k_wealth_x_batch(WealthXBatch b, uint32_
     __shared__ uint32_t praw[PMAX];
     uint32_t lb, nb;
     const uint32_t r = batch_run(b.block_end, b.nruns, lb, nb);
-    wealth_exchange_partition<XB, PMAX>(b.run[r], lb, b.t0[r] + i, parity_in, (mode & 1u) != 0,
-                                        (mode & 2u) != 0, hist, pcount, poff, praw);
+    wealth_exchange_partition<XB, PMAX, NT>(b.run[r], lb, b.t0[r] + i, parity_in,
+                                            (mode & 1u) != 0, (mode & 2u) != 0, hist, pcount, poff,
+                                            praw);
 }
 
 // ------------------------------------------------------------------ SIR (pipelined)
@@ -213,7 +214,7 @@ hipError_t launch_wealth_batch(const WealthBatch &b, uint32_t n_steps, uint32_t 
     return hipGetLastError();
 }
 
-template <int XB, int PMAX>
+template <int XB, int PMAX, int NT>
 static hipError_t wealth_x_batch_steps(const WealthXBatch &b, uint32_t n_steps, hipStream_t st)
 {
     const uint32_t blocks = b.block_end[b.nruns - 1];
@@ -221,7 +222,7 @@ static hipError_t wealth_x_batch_steps(const WealthXBatch &b, uint32_t n_steps, 
         // i < n_steps: step i (mode 2 first, then 3); i == n_steps: final fold
         const uint32_t mode = i == n_steps ? 1u : (i ? 3u : 2u);
         const uint32_t parity_in = i == n_steps ? ((n_steps - 1) & 1u) : ((i + 1) & 1u);
-        hipLaunchKernelGGL((k_wealth_x_batch<XB, PMAX>), dim3(blocks), dim3(1024), 0, st, b, i,
+        hipLaunchKernelGGL((k_wealth_x_batch<XB, PMAX, NT>), dim3(blocks), dim3(NT), 0, st, b, i,
                            parity_in, mode);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -233,9 +234,10 @@ hipError_t launch_wealth_exchange_batch(const WealthXBatch &b, uint32_t n_steps,
                                         hipStream_t st)
 {
     for (uint32_t r = 0; r < b.nruns; ++r)
-        if (b.run[r].P > (bits == 12 ? 512u : 1024u)) return hipErrorInvalidValue;
-    if (bits == 12) return wealth_x_batch_steps<12, 512>(b, n_steps, st);
-    if (bits == 14) return wealth_x_batch_steps<14, 1024>(b, n_steps, st);
+        if (b.run[r].P > (bits == 14 ? 1024u : 512u)) return hipErrorInvalidValue;
+    if (bits == 11) return wealth_x_batch_steps<11, 512, 512>(b, n_steps, st);
+    if (bits == 12) return wealth_x_batch_steps<12, 512, 1024>(b, n_steps, st);
+    if (bits == 14) return wealth_x_batch_steps<14, 1024, 1024>(b, n_steps, st);
     return hipErrorInvalidValue;
 }
 

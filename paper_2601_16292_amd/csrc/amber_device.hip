@@ -101,16 +101,16 @@ __global__ __launch_bounds__(WEALTH_SMALL_THREADS) void k_wealth_small(
 
 // Partition-exchange wealth step (see wealth_exchange_partition).  mode bit 0:
 // fold the records of the previous step; bit 1: take this step's donors.
-template <int XB, int PMAX>
-__global__ __launch_bounds__(1024) void k_wealth_x(WealthXParams x, uint32_t t, uint32_t parity_in,
-                                                   uint32_t mode)
+template <int XB, int PMAX, int NT>
+__global__ __launch_bounds__(NT) void k_wealth_x(WealthXParams x, uint32_t t, uint32_t parity_in,
+                                                 uint32_t mode)
 {
     __shared__ int32_t hist[1u << XB];
     __shared__ uint32_t pcount[PMAX];
     __shared__ uint32_t poff[PMAX];
     __shared__ uint32_t praw[PMAX];
-    wealth_exchange_partition<XB, PMAX>(x, blockIdx.x, t, parity_in, (mode & 1u) != 0,
-                                        (mode & 2u) != 0, hist, pcount, poff, praw);
+    wealth_exchange_partition<XB, PMAX, NT>(x, blockIdx.x, t, parity_in, (mode & 1u) != 0,
+                                            (mode & 2u) != 0, hist, pcount, poff, praw);
 }
 
 __global__ __launch_bounds__(1024) void k_wealth_x15(WealthXParams x, uint32_t t, uint32_t parity_in,
@@ -596,6 +596,7 @@ uint32_t wealth_small_max_agents() { return WEALTH_SMALL_MAX; }
 
 uint32_t wealth_exchange_bits(uint32_t n)
 {
+    if (n <= (1u << 20)) return 11;            // up to 512 partitions of 2048 agents
     if (n <= (1u << 21)) return 12;            // up to 512 partitions of 4096 agents
     if (n <= (1u << 24)) return 14;            // up to 1024 partitions of 16384 agents
     if (n <= (1u << 27)) return 15;            // up to 4096 partitions of 32768 agents
@@ -605,12 +606,18 @@ uint32_t wealth_exchange_bits(uint32_t n)
 hipError_t launch_wealth_exchange(const WealthXParams &x, uint32_t t, uint32_t parity_in,
                                   uint32_t mode, uint32_t bits, hipStream_t st)
 {
-    if (bits == 12) {
+    if (bits == 11) {
         if (x.P > 512) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_wealth_x<12, 512>), dim3(x.P), dim3(1024), 0, st, x, t, parity_in, mode);
+        hipLaunchKernelGGL((k_wealth_x<11, 512, 512>), dim3(x.P), dim3(512), 0, st, x, t, parity_in,
+                           mode);
+    } else if (bits == 12) {
+        if (x.P > 512) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_wealth_x<12, 512, 1024>), dim3(x.P), dim3(1024), 0, st, x, t,
+                           parity_in, mode);
     } else if (bits == 14) {
         if (x.P > 1024) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_wealth_x<14, 1024>), dim3(x.P), dim3(1024), 0, st, x, t, parity_in, mode);
+        hipLaunchKernelGGL((k_wealth_x<14, 1024, 1024>), dim3(x.P), dim3(1024), 0, st, x, t,
+                           parity_in, mode);
     } else if (bits == 15) {
         if (x.P > WX15_PMAX) return hipErrorInvalidValue;
         hipLaunchKernelGGL(k_wealth_x15, dim3(x.P), dim3(1024), 0, st, x, t, parity_in, mode);

@@ -196,7 +196,7 @@ __device__ __forceinline__ void block_exclusive_scan_1024(const uint32_t *in, ui
 
 // ------------------------------------------------------------------ wealth, partition exchange
 // The population is cut into partitions of XR = 2^XB consecutive agents and
-// one 1024-thread workgroup owns each partition.  The kernel of step t
+// one workgroup of NT threads (512 or 1024) owns each partition.  The kernel of step t
 //   (1) folds into its agents the units sent to them at step t-1: the
 //       producers left their recipient ids sorted by destination partition,
 //       so the owner reads only its share and counts it in an LDS histogram;
@@ -210,7 +210,7 @@ __device__ __forceinline__ void block_exclusive_scan_1024(const uint32_t *in, ui
 // with a fold-only launch, so the column holds the state at every call
 // boundary.
 
-template <int XB, int PMAX>
+template <int XB, int PMAX, int NT>
 __device__ __forceinline__ void wealth_exchange_partition(const WealthXParams &x, uint32_t p,
                                                           uint32_t t, uint32_t parity_in,
                                                           bool consume, bool produce,
@@ -218,26 +218,26 @@ __device__ __forceinline__ void wealth_exchange_partition(const WealthXParams &x
                                                           uint32_t *poff, uint32_t *praw)
 {
     constexpr uint32_t XR = 1u << XB;
-    constexpr uint32_t G = XR / 4096;          // 4-agent groups per thread
+    constexpr uint32_t G = XR / (4 * NT);      // 4-agent groups per thread
     const uint32_t tid = threadIdx.x;
     const uint32_t P = x.P;
     const uint32_t groups = groups_of(x.n);
-    for (uint32_t i = tid; i < XR; i += 1024) hist[i] = 0;
+    for (uint32_t i = tid; i < XR; i += NT) hist[i] = 0;
     if (consume) {
         // Load-balanced fold: prefix-sum the per-source counts, then every
         // thread takes a flat record index and finds its source by binary
         // search, so the records are read in parallel and coalesced.
         const uint32_t *tab = x.tab[parity_in];
         const uint32_t *rec = x.rec[parity_in];
-        for (uint32_t s = tid; s < P; s += 1024) {
+        for (uint32_t s = tid; s < P; s += NT) {
             const uint32_t e = tab[(size_t)s * P + p];
             praw[s] = e;
             pcount[s] = e & 0xffffu;
         }
         __syncthreads();
-        block_exclusive_scan_1024(pcount, poff, P);
+        block_exclusive_scan<NT, (PMAX + NT - 1) / NT>(pcount, poff, P);
         const uint32_t total = poff[P - 1] + (praw[P - 1] & 0xffffu);
-        for (uint32_t i = tid; i < total; i += 1024) {
+        for (uint32_t i = tid; i < total; i += NT) {
             uint32_t lo = 0, hi = P;               // last source with poff[s] <= i
             while (hi - lo > 1) {
                 const uint32_t mid = (lo + hi) >> 1;
@@ -248,13 +248,13 @@ __device__ __forceinline__ void wealth_exchange_partition(const WealthXParams &x
             atomicAdd(&hist[r - p * XR], 1);
         }
     }
-    for (uint32_t i = tid; i < P; i += 1024) pcount[i] = 0;
+    for (uint32_t i = tid; i < P; i += NT) pcount[i] = 0;
     __syncthreads();
     int4 V[G];
     uint32_t rcp[G][4], rank[G][4];
 #pragma unroll
     for (uint32_t g = 0; g < G; ++g) {
-        const uint32_t local = g * 1024 + tid;                 // group within the partition
+        const uint32_t local = g * NT + tid;                 // group within the partition
         const uint32_t q = p * (XR / 4) + local;
         V[g] = make_int4(0, 0, 0, 0);
         if (q < groups) {
@@ -292,7 +292,7 @@ __device__ __forceinline__ void wealth_exchange_partition(const WealthXParams &x
     }
     if (!produce) return;
     __syncthreads();
-    block_exclusive_scan_1024(pcount, poff, P);
+    block_exclusive_scan<NT, (PMAX + NT - 1) / NT>(pcount, poff, P);
     uint32_t *rec_out = x.rec[parity_in ^ 1u] + (size_t)p * XR;
 #pragma unroll
     for (uint32_t g = 0; g < G; ++g)
@@ -301,7 +301,7 @@ __device__ __forceinline__ void wealth_exchange_partition(const WealthXParams &x
             if (rcp[g][j] != 0xffffffffu)
                 rec_out[poff[rcp[g][j] >> XB] + rank[g][j]] = rcp[g][j];
     uint32_t *tab_out = x.tab[parity_in ^ 1u] + (size_t)p * P;
-    for (uint32_t d = tid; d < P; d += 1024) tab_out[d] = (poff[d] << 16) | pcount[d];
+    for (uint32_t d = tid; d < P; d += NT) tab_out[d] = (poff[d] << 16) | pcount[d];
 }
 
 // Partitions of 2^15 agents (populations above 2^24, up to 2^27 agents in

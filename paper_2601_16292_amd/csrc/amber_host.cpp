@@ -804,19 +804,25 @@ amber_status_t run_batch(amber_pop *const *pops, uint32_t n, uint32_t n_steps)
     amber_status_t rc = join_streams(pops, n, true);
     if (rc != AMBER_OK) return rc;
 
-    std::vector<amber_pop *> walk, wealth_small, wealth_big, wealth_x12, wealth_x14, sir;
+    // partition-exchange runs grouped by partition size (2^15 partitions use
+    // the atomic kernels inside a batch; results are the same)
+    const uint32_t xsizes[3] = {11, 12, 14};
+    std::vector<amber_pop *> walk, wealth_small, wealth_big, wealth_x[3], sir;
     for (uint32_t i = 0; i < n; ++i) {
         amber_pop *p = pops[i];
         if (p->r.model == AMBER_RANDOM_WALK) walk.push_back(p);
         else if (p->r.model == AMBER_SIR) sir.push_back(p);
         else if (p->r.n <= wealth_small_max_agents()) wealth_small.push_back(p);
-        else if (p->r.xbits == 12 && p->tuning.wealth_form != 1) wealth_x12.push_back(p);
-        else if (p->r.xbits == 14 && p->tuning.wealth_form != 1) wealth_x14.push_back(p);
-        else wealth_big.push_back(p);
+        else {
+            int k = 0;
+            while (k < 3 && (p->tuning.wealth_form == 1 || p->r.xbits != xsizes[k])) ++k;
+            if (k < 3) wealth_x[k].push_back(p);
+            else wealth_big.push_back(p);
+        }
     }
-    for (int which = 0; which < 2; ++which) {
-        const std::vector<amber_pop *> &runs = which ? wealth_x14 : wealth_x12;
-        const uint32_t bits = which ? 14u : 12u;
+    for (int which = 0; which < 3; ++which) {
+        const std::vector<amber_pop *> &runs = wealth_x[which];
+        const uint32_t bits = xsizes[which];
         for (size_t c = 0; c < runs.size(); c += BATCH_RUNS) {
             WealthXBatch b{};
             uint32_t blocks = 0;
