@@ -44,12 +44,31 @@ def kernel_source_sha():
 
 # ------------------------------------------------------------------ algorithmic bytes
 
-def sir_step_bytes(n, L, infected):
+def sir_step_bytes(n, L, infected, susceptible=1):
     """Algorithmic bytes of one SIR step with `infected` agents infected at its
     start: positions read and written (16 B/agent), state read and written
     (2 B/agent), the L*L count grid cleared once and read once (8 B/cell) and
-    one 8-B read-modify-write per infected agent."""
-    return 18 * n + 8 * L * L + 8 * infected
+    one 8-B read-modify-write per infected agent.  With no susceptible agent
+    left no count is read, and the step needs only the columns."""
+    return 18 * n + ((8 * L * L + 8 * infected) if susceptible else 0)
+
+
+def sir_gather_body_bytes(n, L, counts, calls):
+    """Algorithmic bytes of the gather-mode body launches (call-relative steps
+    1 .. len-1 of each call).  counts[k] = (S, I) at the start of timed step
+    k.  Launch j is the first of its call with S = 0 three steps back; it
+    runs every remaining step of the call in registers (one pass over the
+    columns, 18 B/agent), and the later launches of the call move nothing."""
+    total, a = 0, 0
+    for ln in calls:
+        for j in range(1, ln):
+            if j >= 3 and counts[a + j - 3][0] == 0:
+                total += 18 * n
+                break
+            s, i = counts[a + j]
+            total += sir_step_bytes(n, L, i, s)
+        a += ln
+    return total
 
 
 def tile_step_bytes(n, L):
@@ -114,15 +133,17 @@ def sir_bench(torch, A, W, K, chunk, form, count=0, tuning=None, block=256, tile
     times = pop.kernel_times()
     pop.release()
 
-    # infected count at the start of every timed step (for the atomics' bytes)
+    # susceptible and infected counts at the start of every timed step (for
+    # the grid's and the atomics' bytes)
     pop = mk()
     pop.step(W)
-    infected = []
+    counts = []
     for _ in range(K):
-        infected.append(pop.invariants()["n_i"])
+        v = pop.invariants()
+        counts.append((v["n_s"], v["n_i"]))
         pop.step(1)
     pop.release()
-    return secs, inv, times, infected
+    return secs, inv, times, counts
 
 
 def roofline_for(times, bytes_per_kernel_total, traffic):
@@ -393,31 +414,38 @@ def main():
         tuning = AT.tune(A.SIR, n, L=L, steps=args.steps, warmup=args.warmup, torch=torch,
                          force=True, log=log)
         log(f"bench: autotuned {tuning}")
-    secs, inv, times, infected = sir_bench(torch, A, args.warmup, args.steps, args.chunk, form,
-                                           count, tuning, args.block, args.sir_tile)
+    secs, inv, times, counts = sir_bench(torch, A, args.warmup, args.steps, args.chunk, form,
+                                         count, tuning, args.block, args.sir_tile)
     value = n * args.steps / secs
     log(f"bench: {value:.4g} agent-steps/s, {secs * 1e3 / args.steps:.4f} ms/step, kernels {times}")
 
     # algorithmic bytes per launch of each SIR kernel over the timed steps
-    step_bytes = [sir_step_bytes(n, L, i_t) for i_t in infected]
+    calls = [min(args.chunk or args.steps, args.steps - a)
+             for a in range(0, args.steps, args.chunk or args.steps)]
+    step_bytes = [sir_step_bytes(n, L, i_t, s_t) for s_t, i_t in counts]
+    region_bytes = sum(step_bytes)
     priced = {}
     if "sir_persistent" in times:
         priced["sir_persistent"] = sum(step_bytes)          # every step in each launch
-    if "sir_body" in times:
-        priced["sir_body"] = sum(step_bytes[1:])            # one step per body launch
+    if "sir_body" in times:                                 # gather mode, one step per launch
+        priced["sir_body"] = sir_gather_body_bytes(n, L, counts, calls)
+        heads = [sum(calls[:c]) for c in range(len(calls))]
+        region_bytes = priced["sir_body"] + sum(step_bytes[a] for a in heads)
+    live = [s_t > 0 for s_t, _ in counts]                  # steps that read counts
+    cols = [18 * n + (8 * i_t if s_t else 0) for s_t, i_t in counts]
     if "sir_xbody" in times:                                # exchange mode: grid bytes go to sir_xcount
-        priced["sir_xbody"] = sum(b - 8 * L * L for b in step_bytes)
-        priced["sir_xcount"] = 8 * L * L * len(step_bytes)
+        priced["sir_xbody"] = sum(cols)
+        priced["sir_xcount"] = 8 * L * L * sum(live)
     if "sir_tile_body" in times:
         # tiled mode keeps 8-byte records instead of the columns: priced on the
         # bytes it must move (records read and written, count grid written and read)
-        priced["sir_tile_body"] = tile_step_bytes(n, L) * (len(step_bytes) - 1)
+        priced["sir_tile_body"] = sum(16 * n + (8 * L * L if v else 0) for v in live[1:])
     if "sir_body_box" in times:                             # box mode: grid bytes go to sir_box
-        priced["sir_body_box"] = sum(b - 8 * L * L for b in step_bytes[1:])
-        priced["sir_box"] = 8 * L * L * len(step_bytes)
+        priced["sir_body_box"] = sum(cols[1:])
+        priced["sir_box"] = 8 * L * L * sum(live)
     roof = roofline_for(times, priced, load_traffic())
     if roof is not None:
-        roof["timed_region_GBs"] = round(sum(step_bytes) / secs / 1e9, 1)
+        roof["timed_region_GBs"] = round(region_bytes / secs / 1e9, 1)
     kernels = {k: {"launches": v[0], "avg_us": round(v[1] / max(1, v[0]) * 1e3, 3)}
                for k, v in times.items()}
 

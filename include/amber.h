@@ -232,7 +232,16 @@ typedef struct {
                                   AMBER_E_UNSUPPORTED above 2^27 agents)         */
     uint32_t sir_tile;         /* tiled count mode: tile side 32 or 64 cells
                                   (0 = automatic)                                 */
-    uint32_t reserved[2];
+    uint32_t sir_poll;         /* SIR gather mode (sir_count 1), calls of more
+                                  than 32 steps: 0 = early stop on.  Once no
+                                  susceptible agent is left, one launch runs the
+                                  call's remaining steps; amber_step then waits
+                                  on the host every 16 launches until at most 32
+                                  of the call's launches are queued, and stops
+                                  enqueueing once that launch has started.
+                                  1 = off: amber_step never waits and enqueues
+                                  one launch per step.                            */
+    uint32_t reserved;
 } amber_tuning_t;
 
 /* Set / get a handle's launch-shape knobs (host only). */

@@ -74,7 +74,7 @@ class Tuning(ctypes.Structure):
     _fields_ = [("block", ctypes.c_uint32), ("sir_form", ctypes.c_uint32),
                 ("max_groups_per_thread", ctypes.c_uint32), ("sir_count", ctypes.c_uint32),
                 ("wealth_form", ctypes.c_uint32), ("sir_tile", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32 * 2)]
+                ("sir_poll", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 SIR_AUTO, SIR_PIPELINED, SIR_PERSISTENT = 0, 1, 2
@@ -221,8 +221,8 @@ def amber_pop_info(handle):
 
 
 def amber_set_tuning(handle, block=256, sir_form=SIR_AUTO, max_groups_per_thread=0,
-                     sir_count=COUNT_AUTO, wealth_form=WEALTH_AUTO, sir_tile=0):
-    t = Tuning(block, sir_form, max_groups_per_thread, sir_count, wealth_form, sir_tile)
+                     sir_count=COUNT_AUTO, wealth_form=WEALTH_AUTO, sir_tile=0, sir_poll=0):
+    t = Tuning(block, sir_form, max_groups_per_thread, sir_count, wealth_form, sir_tile, sir_poll)
     return lib().amber_set_tuning(handle, ctypes.byref(t))
 
 
@@ -332,9 +332,9 @@ class Population:
         return [outs[c] for c in MODEL_COLUMNS[self.model]]
 
     def tune(self, block=256, sir_form=SIR_AUTO, max_groups_per_thread=0, sir_count=COUNT_AUTO,
-             wealth_form=WEALTH_AUTO, sir_tile=0):
+             wealth_form=WEALTH_AUTO, sir_tile=0, sir_poll=0):
         check(amber_set_tuning(self.handle, block, sir_form, max_groups_per_thread, sir_count,
-                               wealth_form, sir_tile))
+                               wealth_form, sir_tile, sir_poll))
         return self
 
     def profile(self, enable=True):

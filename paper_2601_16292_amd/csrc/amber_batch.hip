@@ -132,7 +132,14 @@ __global__ void k_sir_tail_batch(SirBatch b, uint32_t i)
     const SirParams &p = b.run[r];
     const uint32_t t = b.t0[r] + i;
     const uint32_t q = lb * blockDim.x + threadIdx.x;
-    if (!BOX) zero_quads(grid_of(p, t + 2), p.quads, q, nb * blockDim.x);
+    if (!BOX) {
+        zero_quads(grid_of(p, t + 2), p.quads, q, nb * blockDim.x);
+        if (sir_demand_dirty(p, i)) {               // a body launch ran transition(t)
+            zero_quads(grid_of(p, t), p.quads, q, nb * blockDim.x);
+            zero_quads(grid_of(p, t + 1), p.quads, q, nb * blockDim.x);
+            return;
+        }
+    }
     if (q < p.groups) sir_tail_group<BOX>(p, q, t);
 }
 

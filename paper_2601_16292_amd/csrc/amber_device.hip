@@ -167,11 +167,20 @@ __global__ void k_sir_body_box(SirParams p, uint32_t t)
     if (q < p.groups) sir_body_group<true>(p, q, t);
 }
 
-// tail (gather mode): transition(t); clears the grid of t+2.
-__global__ void k_sir_tail(SirParams p, uint32_t t)
+// tail (gather mode): transition(t); clears the grid of t+2.  When the call
+// ran out of susceptible agents a body launch has already run transition(t),
+// and the tail clears all three grids.  i_last is the call-relative index of
+// the last body launch enqueued.
+__global__ void k_sir_tail(SirParams p, uint32_t t, uint32_t i_last)
 {
     const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-    zero_quads(grid_of(p, t + 2), p.quads, q, gridDim.x * blockDim.x);
+    const uint32_t stride = gridDim.x * blockDim.x;
+    zero_quads(grid_of(p, t + 2), p.quads, q, stride);
+    if (sir_demand_dirty(p, i_last)) {
+        zero_quads(grid_of(p, t), p.quads, q, stride);
+        zero_quads(grid_of(p, t + 1), p.quads, q, stride);
+        return;
+    }
     if (q < p.groups) sir_tail_group<false>(p, q, t);
 }
 
@@ -665,13 +674,15 @@ hipError_t launch_sir_body(SirParams p, uint32_t t, bool box, const Tuning &tu, 
     return hipGetLastError();
 }
 
-hipError_t launch_sir_tail(SirParams p, uint32_t t, bool box, const Tuning &tu, hipStream_t st)
+hipError_t launch_sir_tail(SirParams p, uint32_t t, uint32_t i_last, bool box, const Tuning &tu,
+                           hipStream_t st)
 {
     sir_fill(p);
     if (box)
         hipLaunchKernelGGL(k_sir_tail_box, grid_for(p.groups, tu.block), dim3(tu.block), 0, st, p, t);
     else
-        hipLaunchKernelGGL(k_sir_tail, grid_for(p.groups, tu.block), dim3(tu.block), 0, st, p, t);
+        hipLaunchKernelGGL(k_sir_tail, grid_for(p.groups, tu.block), dim3(tu.block), 0, st, p, t,
+                           i_last);
     return hipGetLastError();
 }
 

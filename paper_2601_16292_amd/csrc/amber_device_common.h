@@ -773,11 +773,20 @@ __device__ __forceinline__ void sir_tail_group(const SirParams &p, uint32_t q, u
 // stores per susceptible agent and saves one global atomic per infected
 // agent off the marked cells.
 //
-// Flag F_j (targeted binning at step j) is decided by launch j-2 from the
-// complete S and I counts of step j-3 (sir_targeted).  Launch j-1 marks iff
-// F_j and launch j bins on marked cells iff F_j, so the two always agree;
+// Flag F_j of step j is decided by launch j-2 from the complete S and I
+// counts of step j-3: 1 = targeted binning (sir_targeted), 2 = no
+// susceptible agent left, 0 = neither.  Launch j-1 marks iff F_j = 1 and
+// launch j bins on marked cells iff F_j = 1, so the two always agree;
 // F_0 = F_1 = F_2 = 0.  Every count that is read is exact; counts nobody
 // reads are not produced.
+//
+// Susceptible agents never come back, so once F_j = 2 no count is read
+// again in the call, and F stays 2.  The agents' remaining steps are then
+// independent of each other: the first launch with F = 2 runs every
+// remaining step of the call for its agents in registers (recoveries and
+// moves, and the tail's transition), and the later launches do nothing.
+// They bin, mark, count and clear nothing; the tail clears all three count
+// grids for the next call (sir_demand_dirty).
 
 // Targeted binning pays a dependent byte load per infected agent in place
 // of a fire-and-forget atomic: worth it while the atomics are many (at least
@@ -809,7 +818,7 @@ __device__ __forceinline__ void sir_demand_book(const SirParams &p, uint32_t i)
                 a += __shfl_xor(a, off, 64);
                 b += __shfl_xor(b, off, 64);
             }
-            flag = sir_targeted(a, b, p.n) ? 1u : 0u;
+            flag = a == 0 ? 2u : sir_targeted(a, b, p.n) ? 1u : 0u;
         }
         if (threadIdx.x == 0) p.nsi[NSI_FLAGS + ((i + 2) & 3u)] = flag;
     }
@@ -817,13 +826,29 @@ __device__ __forceinline__ void sir_demand_book(const SirParams &p, uint32_t i)
         sir_counts_of(p, i + 1)[k * NSI_STRIDE] = 0;
 }
 
-// Modes of launch i: bit 0 = mark demand map (i+1) % 3 (F_{i+1}), bit 1 =
-// bin only marked cells (F_i).
+// Modes of body launch i >= 1: bit 0 = mark demand map (i+1) % 3
+// (F_{i+1} = 1), bit 1 = bin only marked cells (F_i = 1), bit 2 = no
+// susceptible agent left (F_i = 2), bit 3 = an earlier launch has already
+// run the call's remaining steps (F_{i-1} = 2).  Slot (i-1) & 3 is next
+// written by launch i+1.
 __device__ __forceinline__ uint32_t sir_demand_modes(const SirParams &p, uint32_t i)
 {
     const uint32_t mark = p.nsi[NSI_FLAGS + ((i + 1) & 3u)];
-    const uint32_t bin = p.nsi[NSI_FLAGS + (i & 3u)];
-    return (mark ? 1u : 0u) | (bin ? 2u : 0u);
+    const uint32_t cur = p.nsi[NSI_FLAGS + (i & 3u)];
+    const uint32_t prev = p.nsi[NSI_FLAGS + ((i - 1) & 3u)];
+    return (mark == 1u ? 1u : 0u) | (cur == 1u ? 2u : 0u) | (cur == 2u ? 4u : 0u) |
+           (prev == 2u ? 8u : 0u);
+}
+
+// Whether the call ran out of susceptible agents: F of the last body launch
+// enqueued (call-relative index i) is 2.  Then a body launch has run the
+// tail's transition too, and some launches skipped their grid clears.  F_i
+// is not overwritten before the call ends (launch i writes F_{i+2}).  The
+// host stops enqueueing body launches early only after the launch that runs
+// the remaining steps has started, so F_i = 2 then.
+__device__ __forceinline__ bool sir_demand_dirty(const SirParams &p, uint32_t i)
+{
+    return p.nsi[NSI_FLAGS + (i & 3u)] == 2u;
 }
 
 // Adds the S and I agents of the group's states (packed S) to the counts of
@@ -926,6 +951,27 @@ __device__ __forceinline__ void sir_body_demand(const SirParams &p, uint32_t q, 
                                                 uint32_t *s_wc)
 {
     const uint32_t mode = sir_demand_modes(p, i);
+    if (mode & 4u) {                               // the same in every workgroup
+        if ((mode & 8u) || q >= p.groups) return;
+        // steps t .. t_last, then the tail's transition(t_last); no grid is read
+        if (q == 0 && p.stop_word)                 // the host may stop enqueueing launches
+            __hip_atomic_store(p.stop_word, p.stop_seq, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_SYSTEM);
+        int4 X = load_nt4(p.x, q);
+        int4 Y = load_nt4(p.y, q);
+        const uint32_t S0 = load_nt1(p.s, q);
+        uint32_t S = S0;
+        const uint32_t steps = p.t_last - t + 1;
+        for (uint32_t k = 0; k < steps; ++k) {
+            S = sir_transition4<false>(p, grid_of(p, t + k - 1), q, t + k - 1, S, X, Y);
+            sir_move4(p, q, t + k, X, Y);
+        }
+        S = sir_transition4<false>(p, grid_of(p, p.t_last), q, p.t_last, S, X, Y);
+        store_nt4(p.x, q, X);
+        store_nt4(p.y, q, Y);
+        if (S != S0) store_nt1(p.s, q, S);
+        return;
+    }
     zero_quads(grid_of(p, t + 1), p.quads, q, threads);
     zero_quads((uint32_t *)p.dmap[(i + 2) % 3], p.dquads, q, threads);
     uint32_t S2 = 0;

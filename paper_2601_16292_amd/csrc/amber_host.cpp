@@ -394,7 +394,20 @@ struct amber_pop {
     DevInvariants *acc = nullptr;      // inside the workspace
     KernelTimer timer;
     uint32_t persist_g = 0, persist_blocks = 0;   // SIR persistent form fit (0 = none)
+    // SIR gather-mode early stop: pinned word written by the device (host and
+    // device addresses), the number of the last polled call, two poll events
+    uint32_t *stop_host = nullptr, *stop_dev = nullptr;
+    uint32_t call_seq = 0;
+    hipEvent_t poll_ev[2] = {nullptr, nullptr};
+    ~amber_pop()
+    {
+        for (hipEvent_t e : poll_ev)
+            if (e) (void)hipEventDestroy(e);
+        if (stop_host) (void)hipHostFree(stop_host);
+    }
 };
+
+constexpr uint32_t SIR_POLL = 16;      // body launches between early-stop polls
 
 namespace {
 std::mutex g_live_mu;
@@ -670,6 +683,7 @@ amber_status_t enqueue_steps(amber_pop *p, uint32_t n_steps)
         }
     } else {
         SirParams sp = sir_params(p);
+        sp.t_last = t0 + n_steps - 1;
         // Automatic choice: the pipelined form.  The persistent form keeps the
         // state in registers but pays a device-wide barrier per step, which on
         // gfx950 costs more than the launch it saves; it runs only on request.
@@ -734,7 +748,7 @@ amber_status_t enqueue_steps(amber_pop *p, uint32_t n_steps)
                         "sir exchange count kernel");
             }
             HIP_TRY(timed(p, "sir_tail_box",
-                          [&] { return launch_sir_tail(sp, t0 + n_steps - 1, true, tu, st); }),
+                          [&] { return launch_sir_tail(sp, t0 + n_steps - 1, n_steps - 1, true, tu, st); }),
                     "sir tail kernel");
             HIP_TRY(timed(p, "sir_clear",
                           [&] { return launch_sir_clear(sp, 4u, st); }),
@@ -752,20 +766,43 @@ amber_status_t enqueue_steps(amber_pop *p, uint32_t n_steps)
                         "sir box kernel");
             }
             HIP_TRY(timed(p, "sir_tail_box",
-                          [&] { return launch_sir_tail(sp, t0 + n_steps - 1, true, tu, st); }),
+                          [&] { return launch_sir_tail(sp, t0 + n_steps - 1, n_steps - 1, true, tu, st); }),
                     "sir tail kernel");
             HIP_TRY(timed(p, "sir_clear",
                           [&] { return launch_sir_clear(sp, (1u << ((n_steps - 1) & 1)) | 4u, st); }),
                     "sir clear kernel");
         } else {
+            // Early stop: once no susceptible agent is left, one body launch
+            // runs the call's remaining steps and announces it in a pinned
+            // word; the later launches would do nothing.  Every SIR_POLL
+            // launches the host waits until at most 2 x SIR_POLL launches are
+            // queued and stops enqueueing once the word holds this call's
+            // number.  Results do not depend on where it stops.
+            const bool poll = tu.sir_poll == 0 && p->stop_host && n_steps > 2 * SIR_POLL;
+            if (poll) {
+                if (++p->call_seq == 0) ++p->call_seq;
+                sp.stop_word = p->stop_dev;
+                sp.stop_seq = p->call_seq;
+            }
             HIP_TRY(timed(p, "sir_head", [&] { return launch_sir_head(sp, t0, false, tu, st); }),
                     "sir head kernel");
-            for (uint32_t i = 1; i < n_steps; ++i)
+            uint32_t last = n_steps - 1;
+            for (uint32_t i = 1; i < n_steps; ++i) {
                 HIP_TRY(timed(p, "sir_body",
                               [&] { return launch_sir_body(sp, t0 + i, false, tu, st); }),
                         "sir body kernel");
+                if (!poll || i % SIR_POLL != 0) continue;
+                const uint32_t k = i / SIR_POLL;
+                HIP_TRY(hipEventRecord(p->poll_ev[k & 1], st), "poll event record");
+                if (k < 2) continue;
+                HIP_TRY(hipEventSynchronize(p->poll_ev[(k - 1) & 1]), "poll event synchronize");
+                if (__atomic_load_n(p->stop_host, __ATOMIC_ACQUIRE) == p->call_seq) {
+                    last = i;
+                    break;
+                }
+            }
             HIP_TRY(timed(p, "sir_tail",
-                          [&] { return launch_sir_tail(sp, t0 + n_steps - 1, false, tu, st); }),
+                          [&] { return launch_sir_tail(sp, t0 + n_steps - 1, last, false, tu, st); }),
                     "sir tail kernel");
             HIP_TRY(timed(p, "sir_clear",
                           [&] { return launch_sir_clear(sp, 1u << ((n_steps - 1) % 3), st); }),
@@ -919,6 +956,7 @@ amber_status_t run_batch(amber_pop *const *pops, uint32_t n, uint32_t n_steps)
                 b.run[j] = sir_params(p);
                 sir_fill(b.run[j]);
                 b.t0[j] = (uint32_t)p->step;
+                b.run[j].t_last = b.t0[j] + n_steps - 1;
                 // gather mode: one more workgroup per run for the demand-binning bookkeeping
                 blocks += blocks_for(p->r.n) + (mode == 1 ? 1u : 0u);
                 b.block_end[j] = blocks;
@@ -1035,6 +1073,15 @@ amber_status_t amber_init_population(const amber_run_desc_t *desc, const amber_b
                                       (rr.off_dmap[0] - rr.off_nsi) / 4, p->stream);
             if (e == hipSuccess)
                 p->persist_g = sir_persistent_groups_per_thread(rr.n, 8, &p->persist_blocks);
+            if (e == hipSuccess)
+                e = hipHostMalloc((void **)&p->stop_host, 64,
+                                  hipHostMallocMapped | hipHostMallocCoherent);
+            if (e == hipSuccess) {
+                *p->stop_host = 0;
+                e = hipHostGetDevicePointer((void **)&p->stop_dev, p->stop_host, 0);
+            }
+            for (int k = 0; k < 2 && e == hipSuccess; ++k)
+                e = hipEventCreateWithFlags(&p->poll_ev[k], hipEventDisableTiming);
             if (e == hipSuccess)
                 e = hipMemcpyAsync(ws_ptr(p, rr.off_table), rr.t_inf.data(),
                                    rr.t_inf.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
@@ -1187,7 +1234,9 @@ amber_status_t amber_set_tuning(amber_pop_t *pop, const amber_tuning_t *t)
     if (t->wealth_form > 2) return fail(AMBER_E_INVALID, "wealth_form must be 0, 1 or 2");
     if (t->sir_tile != 0 && t->sir_tile != 32 && t->sir_tile != 64)
         return fail(AMBER_E_INVALID, "sir_tile must be 0, 32 or 64");
+    if (t->sir_poll > 1) return fail(AMBER_E_INVALID, "sir_poll must be 0 or 1");
     pop->tuning.sir_tile = t->sir_tile;
+    pop->tuning.sir_poll = t->sir_poll;
     pop->tuning.wealth_form = t->wealth_form;
     pop->tuning.block = t->block;
     pop->tuning.sir_form = t->sir_form;
@@ -1207,6 +1256,7 @@ amber_status_t amber_get_tuning(const amber_pop_t *pop, amber_tuning_t *t)
     t->sir_count = pop->tuning.sir_count;
     t->wealth_form = pop->tuning.wealth_form;
     t->sir_tile = pop->tuning.sir_tile;
+    t->sir_poll = pop->tuning.sir_poll;
     return AMBER_OK;
 }
 

@@ -50,6 +50,11 @@ struct SirParams {
     uint32_t quads;            // ceil(L*L / 4), filled by the launcher
     uint32_t dquads;           // ceil(L*L / 16): 16-byte words of a demand map
     uint32_t t_base;           // first step of the current call (grid rotation origin)
+    uint32_t t_last;           // last step of the current call (gather mode), set per call
+    // gather mode: when non-null, the launch that runs the call's remaining
+    // steps stores stop_seq here (pinned host memory, system scope)
+    uint32_t *stop_word;
+    uint32_t stop_seq;
     // demand-driven binning (gather mode, see sir_body_demand): dmap[g] marks
     // the cells some susceptible agent may read; nsi holds per-step S and I
     // counts and the targeted-binning flags
@@ -92,6 +97,7 @@ struct Tuning {
                                // 4 = tiled (tile-sorted working copy, counts in LDS)
     uint32_t wealth_form = 0;  // 0 = automatic, 1 = atomic scatter, 2 = partition exchange
     uint32_t sir_tile = 0;     // tiled mode: tile side 32 or 64 (0 = automatic)
+    uint32_t sir_poll = 0;     // gather mode: 0 = poll for the early stop, 1 = never
 };
 
 hipError_t launch_init_wealth(int32_t *w, int32_t *inc0, int32_t *inc1, uint32_t n,
@@ -138,7 +144,9 @@ hipError_t launch_wealth_exchange(const WealthXParams &x, uint32_t t, uint32_t p
 // clear(1 << ((n-1) & 1) | 4).  sir_fill() runs inside every launcher.
 hipError_t launch_sir_head(SirParams p, uint32_t t, bool box, const Tuning &tu, hipStream_t st);
 hipError_t launch_sir_body(SirParams p, uint32_t t, bool box, const Tuning &tu, hipStream_t st);
-hipError_t launch_sir_tail(SirParams p, uint32_t t, bool box, const Tuning &tu, hipStream_t st);
+// i_last: call-relative index of the last body launch enqueued (gather mode)
+hipError_t launch_sir_tail(SirParams p, uint32_t t, uint32_t i_last, bool box, const Tuning &tu,
+                           hipStream_t st);
 hipError_t launch_sir_box(SirParams p, uint32_t t, hipStream_t st);
 hipError_t launch_sir_clear(SirParams p, uint32_t mask, hipStream_t st);
 // Exchange count mode: xbody(t0, no transition), then xcount, and for each

@@ -1,10 +1,11 @@
 """GPU parity of the gather mode's demand-driven binning: once susceptible
 agents are few next to many infected ones (32 S <= I and 10 I >= N, three
-steps back), infected
-agents are binned only on cells a susceptible agent may read.  Every count
-that is read must still be exact, so results equal the oracle bit for bit.
-Each case checks with the oracle's own per-step counts that the targeted
-path is taken inside at least one call."""
+steps back), infected agents are binned only on cells a susceptible agent
+may read, and once none is left (S = 0, three steps back) nothing is binned
+or counted at all.  Every count that is read must still be exact, so
+results equal the oracle bit for bit.  Each case checks with the oracle's
+own per-step counts that one of the two paths is taken inside a call, and
+the cases together take both."""
 import numpy as np
 import pytest
 
@@ -33,20 +34,22 @@ def say(*a):
 
 def targeted_steps(O, n, L, seed, stream, beta, gamma, chunks):
     """Call-relative steps j >= 3 whose binning is targeted under the rule,
-    from the oracle's S and I counts after every step."""
+    and those with no susceptible agent left, from the oracle's S and I
+    counts after every step."""
     ref = O.OracleRun(O.SIR, n, L, seed=seed, stream=stream, beta=beta, gamma=gamma)
     counts = []
     for _ in range(sum(chunks)):
         inv = ref.invariants()
         counts.append((inv["n_s"], inv["n_i"]))
         ref.step(1)
-    hits, t0 = 0, 0
+    targeted, none_left, t0 = 0, 0, 0
     for c in chunks:
         for j in range(3, c):
             s, i = counts[t0 + j - 3]     # states at the start of call-relative step j-3
-            hits += 32 * s <= i and 10 * i >= n
+            targeted += s > 0 and 32 * s <= i and 10 * i >= n
+            none_left += s == 0
         t0 += c
-    return hits, ref
+    return targeted, none_left, ref
 
 
 # (n, L, beta, gamma, chunks)
@@ -60,11 +63,19 @@ CASES = [
 ]
 
 
+def test_cases_take_both_paths(O):
+    paths = [targeted_steps(O, n, L, 11, 3, b, g, c)[:2] for n, L, b, g, c in CASES]
+    assert any(t > 0 for t, _ in paths) and any(z > 0 for _, z in paths)
+    # a case that takes both (the 80-step case does so within one call)
+    assert any(t > 0 and z > 0 for t, z in paths)
+
+
 @pytest.mark.parametrize("n,L,beta,gamma,chunks", CASES)
 def test_demand_binning_matches_oracle(A, O, n, L, beta, gamma, chunks):
     say(f"case demand binning n={n} L={L} beta={beta} chunks={chunks}")
-    hits, ref = targeted_steps(O, n, L, 11, 3, beta, gamma, chunks)
-    assert hits > 0, "the workload never reaches the targeted path"
+    targeted, none_left, ref = targeted_steps(O, n, L, 11, 3, beta, gamma, chunks)
+    say(f"  targeted steps {targeted}, steps without susceptible agents {none_left}")
+    assert targeted + none_left > 0, "the workload never leaves the full binning"
     pop = A.Population(A.SIR, n, L=L, seed=11, stream_id=3, beta=beta, gamma=gamma)
     pop.tune(sir_form=A.SIR_PIPELINED, sir_count=A.COUNT_GATHER)
     for c in chunks:
@@ -114,3 +125,38 @@ def test_demand_binning_in_batches(A, O):
             assert np.array_equal(g, r), (n, L)
         assert inv["digest"] == ref.digest()
         p.release()
+
+
+@pytest.mark.parametrize("poll", [0, 1])
+def test_early_stop_of_a_long_call(A, O, poll):
+    """One 200-step call that runs out of susceptible agents near step 40.
+    With polling on, the host stops enqueueing body launches at most 32
+    launches after the one that runs the remaining steps; with it off, every
+    launch is enqueued.  Both equal the oracle."""
+    n, L, beta, gamma, steps = 40000, 200, (1, 3), (1, 80), 200
+    say(f"case early stop poll={poll}")
+    ref = O.OracleRun(O.SIR, n, L, seed=11, stream=3, beta=beta, gamma=gamma)
+    first_none = None
+    for t in range(steps):
+        if ref.invariants()["n_s"] == 0:
+            first_none = t
+            break
+        ref.step(1)
+    assert first_none is not None and first_none + 3 + 2 * 16 < steps - 1
+    ref.step(steps - first_none)
+    pop = A.Population(A.SIR, n, L=L, seed=11, stream_id=3, beta=beta, gamma=gamma)
+    pop.tune(sir_form=A.SIR_PIPELINED, sir_count=A.COUNT_GATHER, sir_poll=poll)
+    pop.profile(True)
+    pop.step(steps)
+    body = pop.kernel_times()["sir_body"][0]
+    got, inv = pop.read(), pop.invariants()
+    pop.release()
+    if poll == 0:
+        # the launch running the remaining steps is first_none + 3; polls come
+        # every 16 launches, waiting for the launch 16 back
+        assert body <= first_none + 3 + 2 * 16, body
+    else:
+        assert body == steps - 1
+    for g, r in zip(got, ref.columns()):
+        assert np.array_equal(g, r)
+    assert inv["digest"] == ref.digest()
