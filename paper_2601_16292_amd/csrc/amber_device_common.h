@@ -764,14 +764,15 @@ __device__ __forceinline__ void sir_tail_group(const SirParams &p, uint32_t q, u
 
 // ------------------------------------------------------------------ SIR, demand-driven binning
 // The gather mode bins an infected agent into the count grid only where some
-// susceptible agent will read the count.  Susceptible agents never come back
-// and move one cell per step, so the 5 x 5 block around a susceptible
-// agent's post-move cell of step i covers its whole 3 x 3 block of step i+1.
-// Launch i of a call (call-relative) may therefore mark, in demand map
-// (i+1) % 3, the 5 x 5 blocks of its susceptible agents, so that launch i+1
-// bins only the infected agents whose cell is marked.  Marking costs 25 byte
-// stores per susceptible agent and saves one global atomic per infected
-// agent off the marked cells.
+// susceptible agent will read the count.  Susceptible agents never come
+// back, and an agent's move of step t+1 is a function of its id and t+1
+// only, so launch i of a call (call-relative, step t) can draw the move of
+// step t+1 of each of its susceptible agents and mark, in demand map
+// (i+1) % 3, the 3 x 3 block that agent reads at step t+1.  Launch i+1 then
+// bins only the infected agents whose cell is marked.  Marking costs one
+// extra move draw per group of four agents holding a susceptible one and 9
+// byte stores per susceptible agent; it saves one global atomic per
+// infected agent off the marked cells.
 //
 // Flag F_j of step j is decided by launch j-2 from the complete S and I
 // counts of step j-3: 1 = targeted binning (sir_targeted), 2 = no
@@ -793,7 +794,7 @@ __device__ __forceinline__ void sir_tail_group(const SirParams &p, uint32_t q, u
 // a tenth of the agents infected) and the susceptible agents few.
 __device__ __forceinline__ bool sir_targeted(uint32_t ns, uint32_t ni, uint32_t n)
 {
-    return 32ull * ns <= (uint64_t)ni && 10ull * ni >= (uint64_t)n;
+    return 12ull * ns <= (uint64_t)ni && 10ull * ni >= (uint64_t)n;
 }
 
 // Counts of call-relative step j: slot k of S at [k * NSI_STRIDE], of I at
@@ -894,33 +895,128 @@ __device__ __forceinline__ void sir_count_states(const SirParams &p, uint32_t i,
     }
 }
 
+// Marks the wrapped 3 x 3 block around (x, y): the cells a susceptible agent
+// at (x, y) reads.
 __device__ __forceinline__ void mark_demand(uint8_t *__restrict__ d, int32_t L, int32_t x, int32_t y)
 {
     if (!on_grid(x, y, L)) return;
-    for (int32_t dy = -2; dy <= 2; ++dy) {
-        const int32_t yy = (y + dy + 2 * L) % L;
-        uint8_t *row = d + (size_t)yy * (uint32_t)L;
-        for (int32_t dx = -2; dx <= 2; ++dx) row[(x + dx + 2 * L) % L] = 1;
+    for (int32_t dy = -1; dy <= 1; ++dy) {
+        uint8_t *row = d + (size_t)wrap_step(y, dy, L) * (uint32_t)L;
+        for (int32_t dx = -1; dx <= 1; ++dx) row[wrap_step(x, dx, L)] = 1;
     }
 }
 
 // Binning (all infected agents, or only those on marked cells) and marking
-// of one group after its transition and move.
+// of one group after its transition and move of step t.
 __device__ __forceinline__ void sir_bin_mark4(const SirParams &p, uint32_t *__restrict__ count,
-                                              uint32_t q, uint32_t S, const int4 &X, const int4 &Y,
-                                              uint32_t mode, const uint8_t *__restrict__ dcur,
+                                              uint32_t q, uint32_t t, uint32_t S, const int4 &X,
+                                              const int4 &Y, uint32_t mode,
+                                              const uint8_t *__restrict__ dcur,
                                               uint8_t *__restrict__ dnext)
 {
     const uint32_t a = 4 * q;
     const int32_t xs[4] = {X.x, X.y, X.z, X.w}, ys[4] = {Y.x, Y.y, Y.z, Y.w};
+    bool mark = false;
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k)
+        mark |= (mode & 1u) && a + k < p.n && ((S >> (8 * k)) & 0xffu) == ST_S;
+    uint4 r = make_uint4(0, 0, 0, 0);
+    if (mark) r = philox(q, t + 1, P_MOVE, p.k0, p.k1);     // the moves of step t+1
+    const uint32_t u[4] = {r.x, r.y, r.z, r.w};
 #pragma unroll
     for (uint32_t k = 0; k < 4; ++k) {
         const uint32_t st = (S >> (8 * k)) & 0xffu;
         if (a + k >= p.n || !on_grid(xs[k], ys[k], p.L)) continue;
         const uint32_t c = (uint32_t)ys[k] * (uint32_t)p.L + (uint32_t)xs[k];
         if (st == ST_I && (!(mode & 2u) || dcur[c])) atomicAdd(&count[c], 1u);
-        if (st == ST_S && (mode & 1u)) mark_demand(dnext, p.L, xs[k], ys[k]);
+        if (st == ST_S && (mode & 1u)) {
+            int32_t x2 = xs[k], y2 = ys[k];
+            moore_move(u[k], p.L, x2, y2);
+            mark_demand(dnext, p.L, x2, y2);
+        }
     }
+}
+
+// Recoveries of steps u0 .. u1 of the group's infected agents (bit j of inf
+// = agent 4q+j), with no susceptible agent left: an infected agent recovers
+// at the first of its draws below t_rec, and nothing else reads the draws.
+// The lanes of a wavefront share the draws.  Each round, the na groups that
+// still hold infected agents and steps get m = floor(64 / na) lanes each,
+// one lane per consecutive step, and each agent takes the first of its m
+// draws that hits.  A group then needs a draw only while it holds an
+// infected agent, and the wavefront runs about as many rounds as the sum of
+// those draws over 64.  Returns the bits of the agents still infected.
+// Every lane of the wavefront must call it.
+__device__ __forceinline__ uint32_t sir_recover_wave(const SirParams &p, uint32_t q, uint32_t inf,
+                                                     uint32_t u0, uint32_t u1)
+{
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t below = (1ull << lane) - 1;
+    uint32_t left = u1 - u0 + 1;                   // draws this group may still take
+    for (;;) {
+        const bool active = inf != 0 && left != 0;
+        const uint64_t A = __ballot(active);
+        if (A == 0) break;
+        const uint32_t na = (uint32_t)__popcll(A);
+        const uint32_t m = 64u / na;                            // lanes per group
+        // rank of the active lanes 0 .. na-1 in lane order (the inactive ones
+        // after them), and lane_of[r] = the lane of rank r
+        const uint32_t rank = active ? (uint32_t)__popcll(A & below)
+                                     : na + (uint32_t)__popcll(~A & below);
+        const uint32_t lane_of = (uint32_t)__builtin_amdgcn_ds_permute((int)(rank * 4), (int)lane);
+        const uint32_t slot = lane / m, off = lane - slot * m;
+        const uint32_t owner = (uint32_t)__builtin_amdgcn_ds_bpermute(
+            (int)((slot < na ? slot : 0u) * 4), (int)lane_of);
+        const uint32_t oq = __shfl(q, (int)owner);
+        const uint32_t oinf = __shfl(inf, (int)owner);
+        const uint32_t oleft = __shfl(left, (int)owner);
+        uint32_t hit = 0;
+        if (slot < na && off < oleft) {
+            const uint4 r = philox(oq, u1 + 1 - oleft + off, P_EPI, p.k0, p.k1);
+            hit = (r.x < p.t_rec ? 1u : 0u) | (r.y < p.t_rec ? 2u : 0u) |
+                  (r.z < p.t_rec ? 4u : 0u) | (r.w < p.t_rec ? 8u : 0u);
+            hit &= oinf;
+        }
+        const uint64_t seg = m == 64 ? ~0ull : ((1ull << m) - 1);
+#pragma unroll
+        for (uint32_t j = 0; j < 4; ++j) {
+            const uint64_t B = __ballot((hit >> j) & 1u);
+            if (active && ((B >> (rank * m)) & seg)) inf &= ~(1u << j);
+        }
+        if (active) left = left > m ? left - m : 0u;
+    }
+    return inf;
+}
+
+// The launch that finishes a call with no susceptible agent left: for the
+// group of this thread (valid = it holds agents), the moves of steps
+// t .. t_last and the recoveries of steps t-1 .. t_last, in registers.
+// Moves and recoveries are independent then.  Every lane of the wavefront
+// must call it.
+__device__ __forceinline__ void sir_finish_group(const SirParams &p, uint32_t q, bool valid,
+                                                 uint32_t t)
+{
+    int4 X = make_int4(0, 0, 0, 0), Y = make_int4(0, 0, 0, 0);
+    uint32_t S0 = 0, inf0 = 0;
+    if (valid) {
+        X = load_nt4(p.x, q);
+        Y = load_nt4(p.y, q);
+        S0 = load_nt1(p.s, q);
+#pragma unroll
+        for (uint32_t j = 0; j < 4; ++j)
+            if (4 * q + j < p.n && ((S0 >> (8 * j)) & 0xffu) == ST_I) inf0 |= 1u << j;
+        const uint32_t steps = p.t_last - t + 1;
+        for (uint32_t k = 0; k < steps; ++k) sir_move4(p, q, t + k, X, Y);
+    }
+    const uint32_t inf = sir_recover_wave(p, q, inf0, t - 1, p.t_last);
+    if (!valid) return;
+    uint32_t S = S0;
+#pragma unroll
+    for (uint32_t j = 0; j < 4; ++j)
+        if ((inf0 & ~inf) & (1u << j)) S = (S & ~(0xffu << (8 * j))) | ((uint32_t)ST_R << (8 * j));
+    store_nt4(p.x, q, X);
+    store_nt4(p.y, q, Y);
+    if (S != S0) store_nt1(p.s, q, S);
 }
 
 // Gather-mode head (launch 0 of a call) and body (launch i >= 1) for the
@@ -941,7 +1037,7 @@ __device__ __forceinline__ void sir_head_demand(const SirParams &p, uint32_t q, 
         sir_move4(p, q, t, X, Y);
         store_nt4(p.x, q, X);
         store_nt4(p.y, q, Y);
-        sir_bin_mark4(p, grid_of(p, t), q, S, X, Y, 0u, nullptr, nullptr);
+        sir_bin_mark4(p, grid_of(p, t), q, t, S, X, Y, 0u, nullptr, nullptr);
     }
     sir_count_states(p, 0, q, S, q < p.groups, s_wc, block);
 }
@@ -952,24 +1048,12 @@ __device__ __forceinline__ void sir_body_demand(const SirParams &p, uint32_t q, 
 {
     const uint32_t mode = sir_demand_modes(p, i);
     if (mode & 4u) {                               // the same in every workgroup
-        if ((mode & 8u) || q >= p.groups) return;
+        if (mode & 8u) return;
         // steps t .. t_last, then the tail's transition(t_last); no grid is read
         if (q == 0 && p.stop_word)                 // the host may stop enqueueing launches
             __hip_atomic_store(p.stop_word, p.stop_seq, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_SYSTEM);
-        int4 X = load_nt4(p.x, q);
-        int4 Y = load_nt4(p.y, q);
-        const uint32_t S0 = load_nt1(p.s, q);
-        uint32_t S = S0;
-        const uint32_t steps = p.t_last - t + 1;
-        for (uint32_t k = 0; k < steps; ++k) {
-            S = sir_transition4<false>(p, grid_of(p, t + k - 1), q, t + k - 1, S, X, Y);
-            sir_move4(p, q, t + k, X, Y);
-        }
-        S = sir_transition4<false>(p, grid_of(p, p.t_last), q, p.t_last, S, X, Y);
-        store_nt4(p.x, q, X);
-        store_nt4(p.y, q, Y);
-        if (S != S0) store_nt1(p.s, q, S);
+        sir_finish_group(p, q, q < p.groups, t);
         return;
     }
     zero_quads(grid_of(p, t + 1), p.quads, q, threads);
@@ -984,7 +1068,8 @@ __device__ __forceinline__ void sir_body_demand(const SirParams &p, uint32_t q, 
         store_nt4(p.x, q, X);
         store_nt4(p.y, q, Y);
         if (S2 != S) store_nt1(p.s, q, S2);
-        sir_bin_mark4(p, grid_of(p, t), q, S2, X, Y, mode, p.dmap[i % 3], p.dmap[(i + 1) % 3]);
+        sir_bin_mark4(p, grid_of(p, t), q, t, S2, X, Y, mode, p.dmap[i % 3],
+                      p.dmap[(i + 1) % 3]);
     }
     sir_count_states(p, i, q, S2, q < p.groups, s_wc, block);
 }

@@ -1,5 +1,5 @@
 """GPU parity of the gather mode's demand-driven binning: once susceptible
-agents are few next to many infected ones (32 S <= I and 10 I >= N, three
+agents are few next to many infected ones (12 S <= I and 10 I >= N, three
 steps back), infected agents are binned only on cells a susceptible agent
 may read, and once none is left (S = 0, three steps back) nothing is binned
 or counted at all.  Every count that is read must still be exact, so
@@ -46,7 +46,7 @@ def targeted_steps(O, n, L, seed, stream, beta, gamma, chunks):
     for c in chunks:
         for j in range(3, c):
             s, i = counts[t0 + j - 3]     # states at the start of call-relative step j-3
-            targeted += s > 0 and 32 * s <= i and 10 * i >= n
+            targeted += s > 0 and 12 * s <= i and 10 * i >= n
             none_left += s == 0
         t0 += c
     return targeted, none_left, ref
@@ -60,6 +60,10 @@ CASES = [
     (3000, 1, (1, 4), (1, 40), [20, 10]),
     (7000, 3, (1, 3), (1, 60), [40]),
     (100003, 316, (2, 5), (1, 100), [60, 20]),
+    # tiny grids: the marked 3 x 3 blocks wrap onto themselves
+    (200, 2, (1, 300), (1, 400), [60]),
+    (200, 4, (1, 300), (1, 400), [60]),
+    (200, 5, (1, 300), (1, 400), [60]),
 ]
 
 
