@@ -165,7 +165,13 @@ def roofline_for(times, bytes_per_kernel_total, traffic):
            "avg_launch_us": round(avg_s * 1e6, 3),
            "algorithmic_bytes_per_launch": int(bytes_per_launch)}
     if traffic and traffic.get("kernel") == name:
-        out["traffic"] = traffic.get("bytes_per_launch")
+        # the number of launches of a call can vary (the host stops enqueueing
+        # once one launch has run the call's remaining steps): bytes of the
+        # whole call over this run's launches
+        if "bytes_per_call" in traffic:
+            out["traffic"] = int(traffic["bytes_per_call"] / launches)
+        else:
+            out["traffic"] = traffic.get("bytes_per_launch")
     return out
 
 

@@ -238,9 +238,12 @@ typedef struct {
                                   call's remaining steps; amber_step then waits
                                   on the host every 16 launches until at most 32
                                   of the call's launches are queued, and stops
-                                  enqueueing once that launch has started.
-                                  1 = off: amber_step never waits and enqueues
-                                  one launch per step.                            */
+                                  enqueueing once that launch has started.  In
+                                  amber_step_batch a chunk of up to 16 SIR runs
+                                  stops once all of them have (on when every run
+                                  of the chunk has 0).  Never while the stream
+                                  is being captured into a graph.
+                                  1 = off: never waits; one launch per step.      */
     uint32_t reserved;
 } amber_tuning_t;
 

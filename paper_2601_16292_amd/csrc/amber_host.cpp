@@ -409,6 +409,42 @@ struct amber_pop {
 
 constexpr uint32_t SIR_POLL = 16;      // body launches between early-stop polls
 
+// Whether work enqueued on st is being captured into a graph (then the host
+// cannot wait for it, and nothing is polled).
+bool stream_capturing(hipStream_t st)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess) {
+        (void)hipGetLastError();
+        return true;
+    }
+    return cs != hipStreamCaptureStatusNone;
+}
+
+// Early-stop poll of a batched gather-mode chunk: every SIR_POLL body
+// launches, wait until at most 2 x SIR_POLL are queued, then stop once every
+// run's pinned word holds its call number.
+struct SirBatchPollState {
+    hipStream_t st;
+    hipEvent_t *ev;                      // two events
+    amber_pop *const *runs;
+    const uint32_t *seq;
+    uint32_t nruns;
+};
+
+int sir_batch_poll(void *ctx, uint32_t i)
+{
+    const SirBatchPollState &s = *(const SirBatchPollState *)ctx;
+    if (i % SIR_POLL != 0) return 0;
+    const uint32_t k = i / SIR_POLL;
+    if (hipEventRecord(s.ev[k & 1], s.st) != hipSuccess) return -1;
+    if (k < 2) return 0;
+    if (hipEventSynchronize(s.ev[(k - 1) & 1]) != hipSuccess) return -1;
+    for (uint32_t j = 0; j < s.nruns; ++j)
+        if (__atomic_load_n(s.runs[j]->stop_host, __ATOMIC_ACQUIRE) != s.seq[j]) return 0;
+    return 1;
+}
+
 namespace {
 std::mutex g_live_mu;
 std::unordered_set<const amber_pop *> g_live;
@@ -778,7 +814,8 @@ amber_status_t enqueue_steps(amber_pop *p, uint32_t n_steps)
             // launches the host waits until at most 2 x SIR_POLL launches are
             // queued and stops enqueueing once the word holds this call's
             // number.  Results do not depend on where it stops.
-            const bool poll = tu.sir_poll == 0 && p->stop_host && n_steps > 2 * SIR_POLL;
+            const bool poll = tu.sir_poll == 0 && p->stop_host && n_steps > 2 * SIR_POLL &&
+                              !stream_capturing(st);
             if (poll) {
                 if (++p->call_seq == 0) ++p->call_seq;
                 sp.stop_word = p->stop_dev;
@@ -967,8 +1004,25 @@ amber_status_t run_batch(amber_pop *const *pops, uint32_t n, uint32_t n_steps)
                 bands += b.run[j].xP;
                 b.band_end[j] = bands;
             }
+            // gather mode: early stop once every run of the chunk has run its
+            // remaining steps (each run's pinned word holds its call number)
+            bool poll = mode == 1 && n_steps > 2 * SIR_POLL && !stream_capturing(st);
+            uint32_t seq[BATCH_RUNS] = {};
+            for (uint32_t j = 0; j < b.nruns && poll; ++j)
+                poll = runs[c + j]->stop_host && runs[c + j]->tuning.sir_poll == 0;
+            for (uint32_t j = 0; j < b.nruns && poll; ++j) {
+                amber_pop *p = runs[c + j];
+                if (++p->call_seq == 0) ++p->call_seq;
+                seq[j] = p->call_seq;
+                b.run[j].stop_word = p->stop_dev;
+                b.run[j].stop_seq = seq[j];
+            }
+            SirBatchPollState ps{st, runs[c]->poll_ev, &runs[c], seq, b.nruns};
             HIP_TRY(timed(lead, "sir_batch",
-                          [&] { return launch_sir_batch(b, n_steps, mode, block, st); }),
+                          [&] {
+                              return launch_sir_batch(b, n_steps, mode, block, st,
+                                                      poll ? sir_batch_poll : nullptr, &ps);
+                          }),
                     "sir batch kernels");
         }
     }

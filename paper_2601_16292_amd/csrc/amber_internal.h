@@ -270,8 +270,12 @@ hipError_t launch_wealth_batch(const WealthBatch &b, uint32_t n_steps, uint32_t 
                                hipStream_t st);
 // SIR, pipelined: head, n_steps-1 bodies and a tail, each one launch for the chunk.
 // mode: 1 gather, 2 box, 3 exchange (every run of the chunk in that mode).
+// poll (gather mode, may be null): called after body launch i; returns 1 to
+// stop enqueueing body launches (every run has run its remaining steps), 0
+// to go on, -1 on a HIP error (returned as hipErrorUnknown)
+typedef int (*SirBatchPoll)(void *ctx, uint32_t i);
 hipError_t launch_sir_batch(const SirBatch &b, uint32_t n_steps, uint32_t mode, uint32_t block,
-                            hipStream_t st);
+                            hipStream_t st, SirBatchPoll poll = nullptr, void *poll_ctx = nullptr);
 void sir_fill(SirParams &p);
 
 // Two-stage reduction: per-workgroup partials, then one workgroup folds them

@@ -164,3 +164,60 @@ def test_early_stop_of_a_long_call(A, O, poll):
     for g, r in zip(got, ref.columns()):
         assert np.array_equal(g, r)
     assert inv["digest"] == ref.digest()
+
+
+def test_early_stop_in_batches(A, O):
+    """Runs that reach the end of their susceptible agents at different steps,
+    stepped together in 90-step calls (polling on; a chunk stops once every
+    run has run its remaining steps): every run equals the oracle."""
+    say("case early stop batched")
+    specs = [(40000, 200, (1, 3), (1, 80)), (20000, 141, (1, 2), (1, 50)),
+             (200, 5, (1, 300), (1, 400)), (30000, 173, (1, 2), (1, 40))]
+    pops = []
+    for k, (n, L, beta, gamma) in enumerate(specs):
+        p = A.Population(A.SIR, n, L=L, seed=7, stream_id=20 + k, beta=beta, gamma=gamma)
+        p.tune(sir_form=A.SIR_PIPELINED, sir_count=A.COUNT_GATHER)
+        pops.append(p)
+    A.step_batch(pops, 90)
+    A.step_batch(pops, 40)
+    for k, (p, (n, L, beta, gamma)) in enumerate(zip(pops, specs)):
+        ref = O.OracleRun(O.SIR, n, L, seed=7, stream=20 + k, beta=beta, gamma=gamma).step(130)
+        got, inv = p.read(), p.invariants()
+        for g, r in zip(got, ref.columns()):
+            assert np.array_equal(g, r), (n, L)
+        assert inv["digest"] == ref.digest()
+        p.release()
+
+
+def test_captured_long_call_matches_eager(A):
+    """A 70-step gather-mode call captured into a graph (no polling while
+    capturing; the launch that finishes the call still runs) and replayed on a
+    fresh state equals the eager call."""
+    import torch
+    n, L, beta, gamma = 40000, 200, (1, 3), (1, 80)
+    say("case captured long call")
+    eager = A.Population(A.SIR, n, L=L, seed=3, stream_id=5, beta=beta, gamma=gamma)
+    eager.tune(sir_form=A.SIR_PIPELINED, sir_count=A.COUNT_GATHER)
+    eager.step(70)
+    want = eager.invariants()["digest"]
+    eager.release()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        pop = A.Population(A.SIR, n, L=L, seed=3, stream_id=5, beta=beta, gamma=gamma,
+                           stream=side)
+        pop.tune(sir_form=A.SIR_PIPELINED, sir_count=A.COUNT_GATHER)
+    side.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        pop.step(70)
+    for rep in range(2):
+        fresh = A.Population(A.SIR, n, L=L, seed=3, stream_id=5, beta=beta, gamma=gamma,
+                             stream=side, buffers=dict(pop.cols, workspace=pop.workspace))
+        side.synchronize()
+        with torch.cuda.stream(side):
+            g.replay()
+        torch.cuda.synchronize()
+        assert pop.invariants()["digest"] == want, rep     # reads the replayed buffers
+        fresh.release()
+    pop.release()
