@@ -789,12 +789,15 @@ __device__ __forceinline__ void sir_tail_group(const SirParams &p, uint32_t q, u
 // They bin, mark, count and clear nothing; the tail clears all three count
 // grids for the next call (sir_demand_dirty).
 
-// Targeted binning pays a dependent byte load per infected agent in place
-// of a fire-and-forget atomic: worth it while the atomics are many (at least
-// a tenth of the agents infected) and the susceptible agents few.
-__device__ __forceinline__ bool sir_targeted(uint32_t ns, uint32_t ni, uint32_t n)
+// Targeted binning pays a dependent byte load per infected agent, and the
+// marking a move draw and 9 byte stores per susceptible agent, for the
+// atomics it saves off the marked cells (about a fraction exp(-9 S / L^2)
+// of them).  Measured at N = L^2 = 1e6, it pays once the atomics are many
+// (at least a tenth of the agents infected) and 3 S <= L^2, i.e. while up
+// to about 95 % of the cells are marked.
+__device__ __forceinline__ bool sir_targeted(uint32_t ns, uint32_t ni, uint32_t n, int32_t L)
 {
-    return 12ull * ns <= (uint64_t)ni && 10ull * ni >= (uint64_t)n;
+    return 3ull * ns <= (uint64_t)L * (uint64_t)L && 10ull * ni >= (uint64_t)n;
 }
 
 // Counts of call-relative step j: slot k of S at [k * NSI_STRIDE], of I at
@@ -819,7 +822,7 @@ __device__ __forceinline__ void sir_demand_book(const SirParams &p, uint32_t i)
                 a += __shfl_xor(a, off, 64);
                 b += __shfl_xor(b, off, 64);
             }
-            flag = a == 0 ? 2u : sir_targeted(a, b, p.n) ? 1u : 0u;
+            flag = a == 0 ? 2u : sir_targeted(a, b, p.n, p.L) ? 1u : 0u;
         }
         if (threadIdx.x == 0) p.nsi[NSI_FLAGS + ((i + 2) & 3u)] = flag;
     }

@@ -1,7 +1,7 @@
 """GPU parity of the gather mode's demand-driven binning: once susceptible
-agents are few next to many infected ones (12 S <= I and 10 I >= N, three
-steps back), infected agents are binned only on cells a susceptible agent
-may read, and once none is left (S = 0, three steps back) nothing is binned
+agents are few enough (3 S <= L^2) and infected ones many (10 I >= N),
+three steps back, infected agents are binned only on cells a susceptible
+agent may read, and once none is left (S = 0, three steps back) nothing is binned
 or counted at all.  Every count that is read must still be exact, so
 results equal the oracle bit for bit.  Each case checks with the oracle's
 own per-step counts that one of the two paths is taken inside a call, and
@@ -46,7 +46,7 @@ def targeted_steps(O, n, L, seed, stream, beta, gamma, chunks):
     for c in chunks:
         for j in range(3, c):
             s, i = counts[t0 + j - 3]     # states at the start of call-relative step j-3
-            targeted += s > 0 and 12 * s <= i and 10 * i >= n
+            targeted += s > 0 and 3 * s <= L * L and 10 * i >= n
             none_left += s == 0
         t0 += c
     return targeted, none_left, ref
