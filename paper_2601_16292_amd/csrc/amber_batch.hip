@@ -73,12 +73,10 @@ __global__ __launch_bounds__(NT) void k_wealth_x_batch(WealthXBatch b, uint32_t 
     __shared__ int32_t hist[1u << XB];
     __shared__ uint32_t pcount[PMAX];
     __shared__ uint32_t poff[PMAX];
-    __shared__ uint32_t praw[PMAX];
     uint32_t lb, nb;
     const uint32_t r = batch_run(b.block_end, b.nruns, lb, nb);
     wealth_exchange_partition<XB, PMAX, NT>(b.run[r], lb, b.t0[r] + i, parity_in,
-                                            (mode & 1u) != 0, (mode & 2u) != 0, hist, pcount, poff,
-                                            praw);
+                                            (mode & 1u) != 0, (mode & 2u) != 0, hist, pcount, poff);
 }
 
 // ------------------------------------------------------------------ SIR (pipelined)

@@ -215,38 +215,35 @@ __device__ __forceinline__ void wealth_exchange_partition(const WealthXParams &x
                                                           uint32_t t, uint32_t parity_in,
                                                           bool consume, bool produce,
                                                           int32_t *hist, uint32_t *pcount,
-                                                          uint32_t *poff, uint32_t *praw)
+                                                          uint32_t *poff)
 {
     constexpr uint32_t XR = 1u << XB;
     constexpr uint32_t G = XR / (4 * NT);      // 4-agent groups per thread
     const uint32_t tid = threadIdx.x;
     const uint32_t P = x.P;
     const uint32_t groups = groups_of(x.n);
+    static_assert(PMAX <= NT, "one source per thread in the fold");
+    // Fold: thread s (< P) reads source s's table entry, then its few records
+    // for this partition, four loads in flight before their LDS adds.  The
+    // table entry is loaded before the barrier that orders the histogram
+    // clear.
+    const uint32_t *tab = x.tab[parity_in];
+    const uint32_t e = consume && tid < P ? tab[(size_t)tid * P + p] : 0u;
     for (uint32_t i = tid; i < XR; i += NT) hist[i] = 0;
-    if (consume) {
-        // Load-balanced fold: prefix-sum the per-source counts, then every
-        // thread takes a flat record index and finds its source by binary
-        // search, so the records are read in parallel and coalesced.
-        const uint32_t *tab = x.tab[parity_in];
-        const uint32_t *rec = x.rec[parity_in];
-        for (uint32_t s = tid; s < P; s += NT) {
-            const uint32_t e = tab[(size_t)s * P + p];
-            praw[s] = e;
-            pcount[s] = e & 0xffffu;
+    __syncthreads();
+    if (consume && tid < P) {
+        const uint32_t cnt = e & 0xffffu;
+        const uint32_t *src = x.rec[parity_in] + (size_t)tid * XR + (e >> 16);
+        int32_t *const h = hist - (size_t)p * XR;
+        uint32_t k = 0;
+        for (; k + 4 <= cnt; k += 4) {
+            const uint32_t r0 = src[k], r1 = src[k + 1], r2 = src[k + 2], r3 = src[k + 3];
+            atomicAdd(&h[r0], 1);
+            atomicAdd(&h[r1], 1);
+            atomicAdd(&h[r2], 1);
+            atomicAdd(&h[r3], 1);
         }
-        __syncthreads();
-        block_exclusive_scan<NT, (PMAX + NT - 1) / NT>(pcount, poff, P);
-        const uint32_t total = poff[P - 1] + (praw[P - 1] & 0xffffu);
-        for (uint32_t i = tid; i < total; i += NT) {
-            uint32_t lo = 0, hi = P;               // last source with poff[s] <= i
-            while (hi - lo > 1) {
-                const uint32_t mid = (lo + hi) >> 1;
-                if (poff[mid] <= i) lo = mid;
-                else hi = mid;
-            }
-            const uint32_t r = rec[(size_t)lo * XR + (praw[lo] >> 16) + (i - poff[lo])];
-            atomicAdd(&hist[r - p * XR], 1);
-        }
+        for (; k < cnt; ++k) atomicAdd(&h[src[k]], 1);
     }
     for (uint32_t i = tid; i < P; i += NT) pcount[i] = 0;
     __syncthreads();
