@@ -188,12 +188,6 @@ __device__ __forceinline__ void block_exclusive_scan(const uint32_t *in, uint32_
     __syncthreads();
 }
 
-__device__ __forceinline__ void block_exclusive_scan_1024(const uint32_t *in, uint32_t *out,
-                                                          uint32_t n)
-{
-    block_exclusive_scan<1024, 4>(in, out, n);
-}
-
 // ------------------------------------------------------------------ wealth, partition exchange
 // The population is cut into partitions of XR = 2^XB consecutive agents and
 // one workgroup of NT threads (512 or 1024) owns each partition.  The kernel of step t
@@ -210,6 +204,21 @@ __device__ __forceinline__ void block_exclusive_scan_1024(const uint32_t *in, ui
 // with a fold-only launch, so the column holds the state at every call
 // boundary.
 
+// Adds the cnt records at src (agent ids; h is the histogram shifted by the
+// partition's first id) to the fold histogram: rounds of 8 loads in flight
+// before their LDS adds.
+__device__ __forceinline__ void wealth_fold_source(int32_t *h, const uint32_t *src, uint32_t cnt)
+{
+    for (uint32_t k = 0; k < cnt; k += 8) {
+        uint32_t r[8];
+#pragma unroll
+        for (uint32_t j = 0; j < 8; ++j) r[j] = k + j < cnt ? src[k + j] : 0xffffffffu;
+#pragma unroll
+        for (uint32_t j = 0; j < 8; ++j)
+            if (r[j] != 0xffffffffu) atomicAdd(&h[r[j]], 1);
+    }
+}
+
 template <int XB, int PMAX, int NT>
 __device__ __forceinline__ void wealth_exchange_partition(const WealthXParams &x, uint32_t p,
                                                           uint32_t t, uint32_t parity_in,
@@ -224,9 +233,8 @@ __device__ __forceinline__ void wealth_exchange_partition(const WealthXParams &x
     const uint32_t groups = groups_of(x.n);
     static_assert(PMAX <= NT, "one source per thread in the fold");
     // Fold: thread s (< P) reads source s's table entry, then its few records
-    // for this partition, four loads in flight before their LDS adds.  The
-    // table entry is loaded before the barrier that orders the histogram
-    // clear.
+    // for this partition.  The table entry is loaded before the barrier that
+    // orders the histogram clear.
     const uint32_t *tab = x.tab[parity_in];
     const uint32_t e = consume && tid < P ? tab[(size_t)tid * P + p] : 0u;
     for (uint32_t i = tid; i < XR; i += NT) hist[i] = 0;
@@ -235,15 +243,7 @@ __device__ __forceinline__ void wealth_exchange_partition(const WealthXParams &x
         const uint32_t cnt = e & 0xffffu;
         const uint32_t *src = x.rec[parity_in] + (size_t)tid * XR + (e >> 16);
         int32_t *const h = hist - (size_t)p * XR;
-        uint32_t k = 0;
-        for (; k + 4 <= cnt; k += 4) {
-            const uint32_t r0 = src[k], r1 = src[k + 1], r2 = src[k + 2], r3 = src[k + 3];
-            atomicAdd(&h[r0], 1);
-            atomicAdd(&h[r1], 1);
-            atomicAdd(&h[r2], 1);
-            atomicAdd(&h[r3], 1);
-        }
-        for (; k < cnt; ++k) atomicAdd(&h[src[k]], 1);
+        wealth_fold_source(h, src, cnt);
     }
     for (uint32_t i = tid; i < P; i += NT) pcount[i] = 0;
     __syncthreads();
@@ -302,10 +302,9 @@ __device__ __forceinline__ void wealth_exchange_partition(const WealthXParams &x
 }
 
 // Partitions of 2^15 agents (populations above 2^24, up to 2^27 agents in
-// 4096 partitions).  The histogram takes 128 KB of LDS, so the fold reads
-// the sources' table entries 1024 at a time, and the producer scans its
-// per-destination counts in place (one array of P + 1 words).  buf holds
-// at least WX15_BUF words.
+// 4096 partitions).  The histogram takes 128 KB of LDS; a thread folds up to
+// four sources, and the producer scans its per-destination counts in place
+// (one array of P + 1 words).  buf holds at least WX15_BUF words.
 constexpr uint32_t WX15_PMAX = 4096;
 constexpr uint32_t WX15_BUF = 5120;
 __device__ __forceinline__ void wealth_exchange_partition15(const WealthXParams &x, uint32_t p,
@@ -318,30 +317,24 @@ __device__ __forceinline__ void wealth_exchange_partition15(const WealthXParams 
     const uint32_t P = x.P;
     const uint32_t groups = groups_of(x.n);
     for (uint32_t i = tid; i < XR; i += 1024) hist[i] = 0;
+    __syncthreads();
     if (consume) {
+        // Fold: thread tid takes sources tid, tid + 1024, ... (up to 4): their
+        // table entries first, then each source's few records.
         const uint32_t *tab = x.tab[parity_in];
         const uint32_t *rec = x.rec[parity_in];
-        uint32_t *cnt = buf, *pre = buf + 1024, *raw = buf + 2048;
-        for (uint32_t c0 = 0; c0 < P; c0 += 1024) {
-            __syncthreads();                      // the previous chunk is folded
-            const uint32_t s = c0 + tid;
-            const uint32_t e = s < P ? tab[(size_t)s * P + p] : 0u;
-            raw[tid] = e;
-            cnt[tid] = e & 0xffffu;
-            __syncthreads();
-            block_exclusive_scan_1024(cnt, pre, 1024);
-            const uint32_t total = pre[1023] + cnt[1023];
-            const uint32_t ns = P - c0 < 1024 ? P - c0 : 1024u;
-            for (uint32_t i = tid; i < total; i += 1024) {
-                uint32_t lo = 0, hi = ns;             // last source with pre[s] <= i
-                while (hi - lo > 1) {
-                    const uint32_t mid = (lo + hi) >> 1;
-                    if (pre[mid] <= i) lo = mid;
-                    else hi = mid;
-                }
-                const uint32_t r = rec[(size_t)(c0 + lo) * XR + (raw[lo] >> 16) + (i - pre[lo])];
-                atomicAdd(&hist[r - p * XR], 1);
-            }
+        int32_t *const h = hist - (size_t)p * XR;
+        uint32_t e[WX15_PMAX / 1024];
+#pragma unroll
+        for (uint32_t c = 0; c < WX15_PMAX / 1024; ++c) {
+            const uint32_t s = c * 1024 + tid;
+            e[c] = s < P ? tab[(size_t)s * P + p] : 0u;
+        }
+#pragma unroll
+        for (uint32_t c = 0; c < WX15_PMAX / 1024; ++c) {
+            const uint32_t cnt = e[c] & 0xffffu;
+            const uint32_t *src = rec + (size_t)(c * 1024 + tid) * XR + (e[c] >> 16);
+            wealth_fold_source(h, src, cnt);
         }
     }
     __syncthreads();
