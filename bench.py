@@ -452,6 +452,11 @@ def main():
     roof = roofline_for(times, priced, load_traffic())
     if roof is not None:
         roof["timed_region_GBs"] = round(region_bytes / secs / 1e9, 1)
+        if roof["kernel"] == "sir_body":
+            roof["limits"] = ("by phase: global atomics while every infected agent is binned; "
+                              "dependent byte loads with demand-driven binning; Philox VALU "
+                              "work in the launch that finishes the call "
+                              "(profiles/sir_1m_phase_counters.md)")
     kernels = {k: {"launches": v[0], "avg_us": round(v[1] / max(1, v[0]) * 1e3, 3)}
                for k, v in times.items()}
 
