@@ -122,9 +122,9 @@ __global__ void k_sir_body_batch(SirBatch b, uint32_t i)
     sir_body_demand(p, q, (nb - 1) * blockDim.x, t, i, lb, s_wc);
 }
 
-// i_last: index of the last body launch enqueued (gather mode)
+// gather mode: the dirty check reads the flag of the run's last body launch
 template <bool BOX>
-__global__ void k_sir_tail_batch(SirBatch b, uint32_t i, uint32_t i_last)
+__global__ void k_sir_tail_batch(SirBatch b, uint32_t i)
 {
     uint32_t lb, nb;
     const uint32_t r = batch_run(b.block_end, b.nruns, lb, nb);
@@ -133,7 +133,7 @@ __global__ void k_sir_tail_batch(SirBatch b, uint32_t i, uint32_t i_last)
     const uint32_t q = lb * blockDim.x + threadIdx.x;
     if (!BOX) {
         zero_quads(grid_of(p, t + 2), p.quads, q, nb * blockDim.x);
-        if (sir_demand_dirty(p, i_last)) {          // a body launch ran transition(t)
+        if (sir_demand_dirty(p, b.i_last[r])) {     // a body launch ran transition(t)
             zero_quads(grid_of(p, t), p.quads, q, nb * blockDim.x);
             zero_quads(grid_of(p, t + 1), p.quads, q, nb * blockDim.x);
             return;
@@ -248,7 +248,7 @@ hipError_t launch_wealth_exchange_batch(const WealthXBatch &b, uint32_t n_steps,
 }
 
 hipError_t launch_sir_batch(const SirBatch &b, uint32_t n_steps, uint32_t mode, uint32_t block,
-                            hipStream_t st, SirBatchPoll poll, void *poll_ctx)
+                            hipStream_t st)
 {
     const uint32_t blocks = b.block_end[b.nruns - 1];
     const uint32_t cblocks = b.cell_block_end[b.nruns - 1];
@@ -267,8 +267,7 @@ hipError_t launch_sir_batch(const SirBatch &b, uint32_t n_steps, uint32_t mode, 
             AMBER_LAUNCH(k_sir_xbody_batch<true>, dim3(xblocks), dim3(256), 0, st, b, i);
             AMBER_LAUNCH(k_sir_xcount_batch, dim3(bands), dim3(256), 0, st, b);
         }
-        AMBER_LAUNCH(k_sir_tail_batch<true>, dim3(blocks), dim3(block), 0, st, b, n_steps - 1,
-                     n_steps - 1);
+        AMBER_LAUNCH(k_sir_tail_batch<true>, dim3(blocks), dim3(block), 0, st, b, n_steps - 1);
         AMBER_LAUNCH(k_sir_clear_batch, dim3(cblocks), dim3(256), 0, st, b, 4u);
     } else if (mode == 2) {
         AMBER_LAUNCH(k_sir_head_batch<true>, dim3(blocks), dim3(block), 0, st, b);
@@ -277,30 +276,32 @@ hipError_t launch_sir_batch(const SirBatch &b, uint32_t n_steps, uint32_t mode, 
             AMBER_LAUNCH(k_sir_body_batch<true>, dim3(blocks), dim3(block), 0, st, b, i);
             AMBER_LAUNCH(k_sir_box_batch, dim3(cblocks), dim3(256), 0, st, b, i);
         }
-        AMBER_LAUNCH(k_sir_tail_batch<true>, dim3(blocks), dim3(block), 0, st, b, n_steps - 1,
-                     n_steps - 1);
+        AMBER_LAUNCH(k_sir_tail_batch<true>, dim3(blocks), dim3(block), 0, st, b, n_steps - 1);
         AMBER_LAUNCH(k_sir_clear_batch, dim3(cblocks), dim3(256), 0, st, b,
                      (1u << ((n_steps - 1) & 1)) | 4u);
     } else {
-        AMBER_LAUNCH(k_sir_head_batch<false>, dim3(blocks), dim3(block), 0, st, b);
-        uint32_t last = n_steps - 1;
-        for (uint32_t i = 1; i < n_steps; ++i) {
-            AMBER_LAUNCH(k_sir_body_batch<false>, dim3(blocks), dim3(block), 0, st, b, i);
-            if (!poll) continue;
-            const int stop = poll(poll_ctx, i);
-            if (stop < 0) return hipErrorUnknown;
-            if (stop) {
-                last = i;
-                break;
-            }
-        }
-        AMBER_LAUNCH(k_sir_tail_batch<false>, dim3(blocks), dim3(block), 0, st, b, n_steps - 1,
-                     last);
-        AMBER_LAUNCH(k_sir_clear_batch, dim3(cblocks), dim3(256), 0, st, b,
-                     1u << ((n_steps - 1) % 3));
+        return hipErrorInvalidValue;           // gather mode: launch_sir_gather_batch
     }
 #undef AMBER_LAUNCH
     return hipSuccess;
+}
+
+hipError_t launch_sir_gather_batch(const SirBatch &b, uint32_t phase, uint32_t i, uint32_t n_steps,
+                                   uint32_t block, hipStream_t st)
+{
+    const uint32_t blocks = b.block_end[b.nruns - 1];
+    const uint32_t cblocks = b.cell_block_end[b.nruns - 1];
+    if (phase == 0)
+        hipLaunchKernelGGL(k_sir_head_batch<false>, dim3(blocks), dim3(block), 0, st, b);
+    else if (phase == 1)
+        hipLaunchKernelGGL(k_sir_body_batch<false>, dim3(blocks), dim3(block), 0, st, b, i);
+    else if (phase == 2)
+        hipLaunchKernelGGL(k_sir_tail_batch<false>, dim3(blocks), dim3(block), 0, st, b,
+                           n_steps - 1);
+    else
+        hipLaunchKernelGGL(k_sir_clear_batch, dim3(cblocks), dim3(256), 0, st, b,
+                           1u << ((n_steps - 1) % 3));
+    return hipGetLastError();
 }
 
 }  // namespace amber

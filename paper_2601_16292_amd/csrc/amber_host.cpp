@@ -11,6 +11,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
 #include <string>
@@ -152,7 +153,7 @@ uint32_t scaled_quotient(const Limbs &num, const Limbs &den)
 }
 
 // Builds the table; returns AMBER_OK, AMBER_E_INVALID or AMBER_E_UNSUPPORTED.
-amber_status_t build_infection_table(uint32_t num, uint32_t den, std::vector<uint32_t> &out)
+amber_status_t build_infection_table_exact(uint32_t num, uint32_t den, std::vector<uint32_t> &out)
 {
     out.clear();
     if (den == 0 || num >= den)
@@ -174,6 +175,32 @@ amber_status_t build_infection_table(uint32_t num, uint32_t den, std::vector<uin
                         "beta %u/%u needs more than %u threshold entries", num, den,
                         AMBER_MAX_TABLE);
     }
+}
+
+// The exact tables of the betas seen so far (a pure function of beta; long
+// tables take milliseconds of big-integer arithmetic, and sweeps repeat a
+// few betas over many runs).  At most 256 are kept.
+amber_status_t build_infection_table(uint32_t num, uint32_t den, std::vector<uint32_t> &out)
+{
+    static std::mutex mu;
+    static std::map<std::pair<uint32_t, uint32_t>, std::vector<uint32_t>> *cache =
+        new std::map<std::pair<uint32_t, uint32_t>, std::vector<uint32_t>>;   // never destroyed
+    const std::pair<uint32_t, uint32_t> key(num, den);
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        const auto it = cache->find(key);
+        if (it != cache->end()) {
+            out = it->second;
+            return AMBER_OK;
+        }
+    }
+    const amber_status_t st = build_infection_table_exact(num, den, out);
+    if (st == AMBER_OK) {
+        std::lock_guard<std::mutex> lk(mu);
+        if (cache->size() >= 256) cache->clear();
+        (*cache)[key] = out;
+    }
+    return st;
 }
 
 uint32_t bernoulli_threshold(uint32_t num, uint32_t den)
@@ -395,17 +422,71 @@ struct amber_pop {
     KernelTimer timer;
     uint32_t persist_g = 0, persist_blocks = 0;   // SIR persistent form fit (0 = none)
     // SIR gather-mode early stop: pinned word written by the device (host and
-    // device addresses), the number of the last polled call, two poll events
+    // device addresses, a slot of the process-wide pool), the number of the
+    // last polled call, two poll events (created on first use)
     uint32_t *stop_host = nullptr, *stop_dev = nullptr;
     uint32_t call_seq = 0;
     hipEvent_t poll_ev[2] = {nullptr, nullptr};
-    ~amber_pop()
+    ~amber_pop();
+};
+
+namespace {
+// Pinned, device-mapped host words for the early stop, handed out from 4 KB
+// pages of 64 slots (one 64-byte line each).  Pages are kept until the
+// process ends; a released handle's slot is reused (its stream has drained).
+struct StopWordPool {
+    std::mutex mu;
+    std::vector<std::pair<uint32_t *, uint32_t *>> free_slots;   // (host, device)
+    hipError_t take(uint32_t **host, uint32_t **dev)
     {
-        for (hipEvent_t e : poll_ev)
-            if (e) (void)hipEventDestroy(e);
-        if (stop_host) (void)hipHostFree(stop_host);
+        std::lock_guard<std::mutex> lk(mu);
+        if (free_slots.empty()) {
+            void *page = nullptr, *dpage = nullptr;
+            hipError_t e = hipHostMalloc(&page, 4096, hipHostMallocMapped | hipHostMallocCoherent |
+                                                          hipHostMallocPortable);
+            if (e == hipSuccess) e = hipHostGetDevicePointer(&dpage, page, 0);
+            if (e != hipSuccess) return e;
+            for (uint32_t k = 0; k < 64; ++k)
+                free_slots.emplace_back((uint32_t *)((char *)page + 64 * k),
+                                        (uint32_t *)((char *)dpage + 64 * k));
+        }
+        *host = free_slots.back().first;
+        *dev = free_slots.back().second;
+        free_slots.pop_back();
+        __atomic_store_n(*host, 0u, __ATOMIC_RELEASE);
+        return hipSuccess;
+    }
+    void give(uint32_t *host, uint32_t *dev)
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        free_slots.emplace_back(host, dev);
     }
 };
+// never destroyed: handles may be released during process teardown
+StopWordPool &stop_words()
+{
+    static StopWordPool *pool = new StopWordPool;
+    return *pool;
+}
+}  // namespace
+
+amber_pop::~amber_pop()
+{
+    for (hipEvent_t e : poll_ev)
+        if (e) (void)hipEventDestroy(e);
+    if (stop_host) stop_words().give(stop_host, stop_dev);
+}
+
+// The two poll events of a handle, created on its first polled call.
+hipError_t poll_events(amber_pop *p)
+{
+    for (int k = 0; k < 2; ++k)
+        if (!p->poll_ev[k]) {
+            const hipError_t e = hipEventCreateWithFlags(&p->poll_ev[k], hipEventDisableTiming);
+            if (e != hipSuccess) return e;
+        }
+    return hipSuccess;
+}
 
 constexpr uint32_t SIR_POLL = 16;      // body launches between early-stop polls
 
@@ -421,29 +502,6 @@ bool stream_capturing(hipStream_t st)
     return cs != hipStreamCaptureStatusNone;
 }
 
-// Early-stop poll of a batched gather-mode chunk: every SIR_POLL body
-// launches, wait until at most 2 x SIR_POLL are queued, then stop once every
-// run's pinned word holds its call number.
-struct SirBatchPollState {
-    hipStream_t st;
-    hipEvent_t *ev;                      // two events
-    amber_pop *const *runs;
-    const uint32_t *seq;
-    uint32_t nruns;
-};
-
-int sir_batch_poll(void *ctx, uint32_t i)
-{
-    const SirBatchPollState &s = *(const SirBatchPollState *)ctx;
-    if (i % SIR_POLL != 0) return 0;
-    const uint32_t k = i / SIR_POLL;
-    if (hipEventRecord(s.ev[k & 1], s.st) != hipSuccess) return -1;
-    if (k < 2) return 0;
-    if (hipEventSynchronize(s.ev[(k - 1) & 1]) != hipSuccess) return -1;
-    for (uint32_t j = 0; j < s.nruns; ++j)
-        if (__atomic_load_n(s.runs[j]->stop_host, __ATOMIC_ACQUIRE) != s.seq[j]) return 0;
-    return 1;
-}
 
 namespace {
 std::mutex g_live_mu;
@@ -817,6 +875,7 @@ amber_status_t enqueue_steps(amber_pop *p, uint32_t n_steps)
             const bool poll = tu.sir_poll == 0 && p->stop_host && n_steps > 2 * SIR_POLL &&
                               !stream_capturing(st);
             if (poll) {
+                HIP_TRY(poll_events(p), "poll events");
                 if (++p->call_seq == 0) ++p->call_seq;
                 sp.stop_word = p->stop_dev;
                 sp.stop_seq = p->call_seq;
@@ -867,6 +926,97 @@ amber_status_t join_streams(amber_pop *const *pops, uint32_t n, bool before)
         (void)hipEventDestroy(ev);
         if (e != hipSuccess) return hip_fail(e, "stream join");
     }
+    return AMBER_OK;
+}
+
+// SIR gather-mode runs of a batch, enqueued step by step: each step is one
+// body launch per pack of at most BATCH_RUNS active runs.  With polling,
+// every SIR_POLL steps the host waits until at most 2 x SIR_POLL steps are
+// queued, and a run whose launch running its remaining steps has started
+// (its pinned word holds its call number) leaves the later launches: the
+// active runs are packed again.  Each run's tail checks the flag of the last
+// body launch that held it.  Results do not depend on when a run leaves.
+amber_status_t run_sir_gather_batch(amber_pop *lead, const std::vector<amber_pop *> &runs,
+                                    uint32_t n_steps, uint32_t block, hipStream_t st)
+{
+    const uint32_t R = (uint32_t)runs.size();
+    std::vector<SirParams> prm(R);
+    std::vector<uint32_t> t0(R), seq(R, 0), i_last(R, n_steps - 1);
+    bool poll = n_steps > 2 * SIR_POLL && !stream_capturing(st);
+    for (amber_pop *p : runs) poll = poll && p->stop_host && p->tuning.sir_poll == 0;
+    for (uint32_t r = 0; r < R; ++r) {
+        amber_pop *p = runs[r];
+        prm[r] = sir_params(p);
+        sir_fill(prm[r]);
+        t0[r] = (uint32_t)p->step;
+        prm[r].t_last = t0[r] + n_steps - 1;
+        if (poll) {
+            if (++p->call_seq == 0) ++p->call_seq;
+            seq[r] = p->call_seq;
+            prm[r].stop_word = p->stop_dev;
+            prm[r].stop_seq = seq[r];
+        }
+    }
+    // packs of at most BATCH_RUNS runs (one more workgroup per run for the
+    // demand-binning bookkeeping)
+    auto make_packs = [&](const std::vector<uint32_t> &idx) {
+        std::vector<SirBatch> packs;
+        for (size_t c = 0; c < idx.size(); c += BATCH_RUNS) {
+            SirBatch b{};
+            uint32_t blocks = 0, cblocks = 0;
+            for (size_t k = c; k < idx.size() && k < c + BATCH_RUNS; ++k) {
+                const uint32_t r = idx[k], j = b.nruns++;
+                b.run[j] = prm[r];
+                b.t0[j] = t0[r];
+                b.i_last[j] = i_last[r];
+                blocks += (groups_of_host(runs[r]->r.n) + block - 1) / block + 1;
+                b.block_end[j] = blocks;
+                cblocks += (prm[r].quads + 255) / 256;
+                b.cell_block_end[j] = cblocks;
+            }
+            packs.push_back(b);
+        }
+        return packs;
+    };
+    std::vector<uint32_t> all(R), active;
+    for (uint32_t r = 0; r < R; ++r) all[r] = r;
+    active = all;
+    auto launch_packs = [&](const std::vector<SirBatch> &packs, uint32_t phase, uint32_t i) {
+        for (const SirBatch &b : packs) {
+            hipError_t e = launch_sir_gather_batch(b, phase, i, n_steps, block, st);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    if (poll) {
+        const hipError_t e = poll_events(runs[0]);
+        if (e != hipSuccess) return hip_fail(e, "poll events");
+    }
+    hipEvent_t *ev = runs[0]->poll_ev;
+    auto steps = [&]() -> hipError_t {
+        hipError_t e = launch_packs(make_packs(all), 0, 0);
+        std::vector<SirBatch> packs = make_packs(active);
+        for (uint32_t i = 1; i < n_steps && e == hipSuccess && !active.empty(); ++i) {
+            e = launch_packs(packs, 1, i);
+            if (e != hipSuccess || !poll || i % SIR_POLL != 0) continue;
+            const uint32_t k = i / SIR_POLL;
+            if ((e = hipEventRecord(ev[k & 1], st)) != hipSuccess || k < 2) continue;
+            if ((e = hipEventSynchronize(ev[(k - 1) & 1])) != hipSuccess) break;
+            std::vector<uint32_t> still;
+            for (uint32_t r : active) {
+                if (__atomic_load_n(runs[r]->stop_host, __ATOMIC_ACQUIRE) == seq[r]) i_last[r] = i;
+                else still.push_back(r);
+            }
+            if (still.size() != active.size()) {
+                active.swap(still);
+                packs = make_packs(active);
+            }
+        }
+        if (e == hipSuccess) e = launch_packs(make_packs(all), 2, 0);   // with the runs' i_last
+        if (e == hipSuccess) e = launch_packs(make_packs(all), 3, 0);
+        return e;
+    };
+    HIP_TRY(timed(lead, "sir_batch", steps), "sir batch kernels");
     return AMBER_OK;
 }
 
@@ -978,8 +1128,18 @@ amber_status_t run_batch(amber_pop *const *pops, uint32_t n, uint32_t n_steps)
                       [&] { return launch_wealth_batch(b, n_steps, block, st); }),
                 "wealth batch kernels");
     }
-    // SIR runs go in chunks of one count mode each
-    for (uint32_t mode = 1; mode <= 3; ++mode) {
+    // SIR runs of the gather mode go step by step; box and exchange runs in
+    // chunks of one count mode each
+    {
+        std::vector<amber_pop *> runs;
+        for (amber_pop *p : sir)
+            if (sir_batch_count_mode(p) == 1) runs.push_back(p);
+        if (!runs.empty()) {
+            rc = run_sir_gather_batch(lead, runs, n_steps, block, st);
+            if (rc != AMBER_OK) return rc;
+        }
+    }
+    for (uint32_t mode = 2; mode <= 3; ++mode) {
         std::vector<amber_pop *> runs;
         for (amber_pop *p : sir) {
             if (sir_batch_count_mode(p) == mode) runs.push_back(p);
@@ -994,8 +1154,8 @@ amber_status_t run_batch(amber_pop *const *pops, uint32_t n, uint32_t n_steps)
                 sir_fill(b.run[j]);
                 b.t0[j] = (uint32_t)p->step;
                 b.run[j].t_last = b.t0[j] + n_steps - 1;
-                // gather mode: one more workgroup per run for the demand-binning bookkeeping
-                blocks += blocks_for(p->r.n) + (mode == 1 ? 1u : 0u);
+                b.i_last[j] = n_steps - 1;
+                blocks += blocks_for(p->r.n);
                 b.block_end[j] = blocks;
                 cblocks += (b.run[j].quads + 255) / 256;
                 b.cell_block_end[j] = cblocks;
@@ -1004,25 +1164,8 @@ amber_status_t run_batch(amber_pop *const *pops, uint32_t n, uint32_t n_steps)
                 bands += b.run[j].xP;
                 b.band_end[j] = bands;
             }
-            // gather mode: early stop once every run of the chunk has run its
-            // remaining steps (each run's pinned word holds its call number)
-            bool poll = mode == 1 && n_steps > 2 * SIR_POLL && !stream_capturing(st);
-            uint32_t seq[BATCH_RUNS] = {};
-            for (uint32_t j = 0; j < b.nruns && poll; ++j)
-                poll = runs[c + j]->stop_host && runs[c + j]->tuning.sir_poll == 0;
-            for (uint32_t j = 0; j < b.nruns && poll; ++j) {
-                amber_pop *p = runs[c + j];
-                if (++p->call_seq == 0) ++p->call_seq;
-                seq[j] = p->call_seq;
-                b.run[j].stop_word = p->stop_dev;
-                b.run[j].stop_seq = seq[j];
-            }
-            SirBatchPollState ps{st, runs[c]->poll_ev, &runs[c], seq, b.nruns};
             HIP_TRY(timed(lead, "sir_batch",
-                          [&] {
-                              return launch_sir_batch(b, n_steps, mode, block, st,
-                                                      poll ? sir_batch_poll : nullptr, &ps);
-                          }),
+                          [&] { return launch_sir_batch(b, n_steps, mode, block, st); }),
                     "sir batch kernels");
         }
     }
@@ -1127,15 +1270,7 @@ amber_status_t amber_init_population(const amber_run_desc_t *desc, const amber_b
                                       (rr.off_dmap[0] - rr.off_nsi) / 4, p->stream);
             if (e == hipSuccess)
                 p->persist_g = sir_persistent_groups_per_thread(rr.n, 8, &p->persist_blocks);
-            if (e == hipSuccess)
-                e = hipHostMalloc((void **)&p->stop_host, 64,
-                                  hipHostMallocMapped | hipHostMallocCoherent);
-            if (e == hipSuccess) {
-                *p->stop_host = 0;
-                e = hipHostGetDevicePointer((void **)&p->stop_dev, p->stop_host, 0);
-            }
-            for (int k = 0; k < 2 && e == hipSuccess; ++k)
-                e = hipEventCreateWithFlags(&p->poll_ev[k], hipEventDisableTiming);
+            if (e == hipSuccess) e = stop_words().take(&p->stop_host, &p->stop_dev);
             if (e == hipSuccess)
                 e = hipMemcpyAsync(ws_ptr(p, rr.off_table), rr.t_inf.data(),
                                    rr.t_inf.size() * sizeof(uint32_t), hipMemcpyHostToDevice,

@@ -258,6 +258,7 @@ struct SirBatch {
     uint32_t cell_block_end[BATCH_RUNS];  // over grid quads (256 threads each)
     uint32_t xblock_end[BATCH_RUNS];      // exchange mode: producer workgroups (xW each)
     uint32_t band_end[BATCH_RUNS];        // exchange mode: count workgroups (xP each)
+    uint32_t i_last[BATCH_RUNS];          // gather mode: last body launch that held the run
     uint32_t nruns;
 };
 
@@ -268,14 +269,17 @@ hipError_t launch_wealth_small_batch(const WealthSmallBatch &b, uint32_t n_steps
 // Wealth, larger runs: one launch per step for the chunk, then one fold.
 hipError_t launch_wealth_batch(const WealthBatch &b, uint32_t n_steps, uint32_t block,
                                hipStream_t st);
-// SIR, pipelined: head, n_steps-1 bodies and a tail, each one launch for the chunk.
-// mode: 1 gather, 2 box, 3 exchange (every run of the chunk in that mode).
-// poll (gather mode, may be null): called after body launch i; returns 1 to
-// stop enqueueing body launches (every run has run its remaining steps), 0
-// to go on, -1 on a HIP error (returned as hipErrorUnknown)
-typedef int (*SirBatchPoll)(void *ctx, uint32_t i);
+// SIR, pipelined, box (mode 2) or exchange (mode 3) count mode: head,
+// n_steps-1 bodies and a tail, each one launch for the chunk.
 hipError_t launch_sir_batch(const SirBatch &b, uint32_t n_steps, uint32_t mode, uint32_t block,
-                            hipStream_t st, SirBatchPoll poll = nullptr, void *poll_ctx = nullptr);
+                            hipStream_t st);
+// SIR, pipelined, gather mode: one phase for the runs of b (the host
+// enqueues the steps of all runs step by step, so that runs that have run
+// their remaining steps can leave the later launches).  phase 0 = head,
+// 1 = body of call-relative step i, 2 = tail (dirty check on b.i_last),
+// 3 = clear of count grid (n_steps - 1) % 3 given as i.
+hipError_t launch_sir_gather_batch(const SirBatch &b, uint32_t phase, uint32_t i, uint32_t n_steps,
+                                   uint32_t block, hipStream_t st);
 void sir_fill(SirParams &p);
 
 // Two-stage reduction: per-workgroup partials, then one workgroup folds them
