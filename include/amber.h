@@ -210,7 +210,10 @@ typedef struct {
     uint32_t max_groups_per_thread; /* persistent form: largest number of 4-agent
                                   groups a thread may hold (1, 2, 4, 8; 0 = 8)    */
     uint32_t sir_count;        /* SIR neighbour counts in the pipelined form:
-                                  0 = automatic, 1 = sum the 3x3 block of the
+                                  0 = automatic (1 for calls of 128 steps or
+                                  more or grids of at most 16M cells, else 4
+                                  in plain calls and 2 in batches),
+                                  1 = sum the 3x3 block of the
                                   count grid per agent, 2 = box-sum the grid once
                                   per step (one stencil kernel) and read one
                                   cell per agent, 3 = exchange: infected cells are

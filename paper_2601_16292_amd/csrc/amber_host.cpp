@@ -630,8 +630,15 @@ SirParams sir_params(amber_pop *p)
 // gathers.  Beyond it every gathered cell and every binning atomic costs its
 // own memory line: the box mode then (one read per agent instead of nine),
 // and inside a plain call the tiled mode ahead of both (no random access).
-uint32_t sir_auto_count_mode(const amber_pop *p)
+// A call of SIR_AUTO_LONG_CALL steps or more keeps the gather mode at any
+// size: over a long call its demand-driven binning and the launch that runs
+// the steps left once no susceptible agent remains outweigh the slower
+// early steps (a 500-step run at 2^27 agents: 0.57 s against 1.10 s tiled).
+constexpr uint32_t SIR_AUTO_LONG_CALL = 128;
+
+uint32_t sir_auto_count_mode(const amber_pop *p, uint32_t n_steps)
 {
+    if (n_steps >= SIR_AUTO_LONG_CALL) return 1u;
     return (uint64_t)p->r.L * p->r.L > (16ull << 20) ? 2u : 1u;
 }
 
@@ -651,22 +658,22 @@ uint32_t sir_tile_side(const amber_pop *p)
     return want;
 }
 
-uint32_t sir_count_mode(const amber_pop *p)
+uint32_t sir_count_mode(const amber_pop *p, uint32_t n_steps)
 {
     const uint32_t want = p->tuning.sir_count;
     if (want == 3) return p->r.sx_P ? 3u : 0u;    // 0: unavailable, caller reports it
     if (want == 4) return sir_tile_side(p) ? 4u : 0u;
     if (want == 1 || want == 2) return want;
-    const uint32_t m = sir_auto_count_mode(p);
+    const uint32_t m = sir_auto_count_mode(p, n_steps);
     return m == 2 && sir_tile_side(p) ? 4u : m;
 }
 
 // Count mode of a run inside amber_step_batch (the batched kernels have the
 // gather, box and exchange modes).
-uint32_t sir_batch_count_mode(const amber_pop *p)
+uint32_t sir_batch_count_mode(const amber_pop *p, uint32_t n_steps)
 {
-    const uint32_t m = sir_count_mode(p);
-    if (m == 4) return sir_auto_count_mode(p);
+    const uint32_t m = sir_count_mode(p, n_steps);
+    if (m == 4) return sir_auto_count_mode(p, n_steps);
     return m == 0 ? 1u : m;     // exchange requested but unavailable: gather
 }
 
@@ -715,7 +722,7 @@ uint32_t tile_block(const amber_pop *p, const TileParams &tp)
 
 // The exchange mode (no global atomics) runs on request or when the
 // autotuner measures it faster.
-bool sir_box_mode(const amber_pop *p) { return sir_count_mode(p) == 2; }
+bool sir_box_mode(const amber_pop *p, uint32_t n_steps) { return sir_count_mode(p, n_steps) == 2; }
 
 amber_status_t enqueue_steps(amber_pop *p, uint32_t n_steps)
 {
@@ -812,7 +819,7 @@ amber_status_t enqueue_steps(amber_pop *p, uint32_t n_steps)
             return fail(AMBER_E_UNSUPPORTED, "the tiled count mode needs a grid side of at least "
                                              "2 x tile + 2 (grid side %u, tile %u)",
                         r.L, tu.sir_tile ? tu.sir_tile : TILE_MIN);
-        } else if (sir_count_mode(p) == 4) {
+        } else if (sir_count_mode(p, n_steps) == 4) {
             const TileParams tp = tile_params(p, sir_tile_side(p));
             const uint32_t blk = tile_block(p, tp);
             HIP_TRY(timed(p, "sir_tile_sort", [&] { return launch_sir_tile_sort(tp, st); }),
@@ -829,7 +836,7 @@ amber_status_t enqueue_steps(amber_pop *p, uint32_t n_steps)
             HIP_TRY(timed(p, "sir_clear",
                           [&] { return launch_zero_words(tp.C[0], words, st); }),
                     "sir clear kernel");
-        } else if (sir_count_mode(p) == 3) {
+        } else if (sir_count_mode(p, n_steps) == 3) {
             HIP_TRY(timed(p, "sir_xbody", [&] { return launch_sir_xbody(sp, t0, false, st); }),
                     "sir exchange body kernel");
             HIP_TRY(timed(p, "sir_xcount", [&] { return launch_sir_xcount(sp, st); }),
@@ -847,7 +854,7 @@ amber_status_t enqueue_steps(amber_pop *p, uint32_t n_steps)
             HIP_TRY(timed(p, "sir_clear",
                           [&] { return launch_sir_clear(sp, 4u, st); }),
                     "sir clear kernel");
-        } else if (sir_box_mode(p)) {
+        } else if (sir_box_mode(p, n_steps)) {
             HIP_TRY(timed(p, "sir_head", [&] { return launch_sir_head(sp, t0, true, tu, st); }),
                     "sir head kernel");
             HIP_TRY(timed(p, "sir_box", [&] { return launch_sir_box(sp, t0, st); }),
@@ -1133,7 +1140,7 @@ amber_status_t run_batch(amber_pop *const *pops, uint32_t n, uint32_t n_steps)
     {
         std::vector<amber_pop *> runs;
         for (amber_pop *p : sir)
-            if (sir_batch_count_mode(p) == 1) runs.push_back(p);
+            if (sir_batch_count_mode(p, n_steps) == 1) runs.push_back(p);
         if (!runs.empty()) {
             rc = run_sir_gather_batch(lead, runs, n_steps, block, st);
             if (rc != AMBER_OK) return rc;
@@ -1142,7 +1149,7 @@ amber_status_t run_batch(amber_pop *const *pops, uint32_t n, uint32_t n_steps)
     for (uint32_t mode = 2; mode <= 3; ++mode) {
         std::vector<amber_pop *> runs;
         for (amber_pop *p : sir) {
-            if (sir_batch_count_mode(p) == mode) runs.push_back(p);
+            if (sir_batch_count_mode(p, n_steps) == mode) runs.push_back(p);
         }
         for (size_t c = 0; c < runs.size(); c += BATCH_RUNS) {
             SirBatch b{};
