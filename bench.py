@@ -338,6 +338,23 @@ def roofline_big(torch, A, log2n):
         res[f"sir_body_tiled{tile}"] = entry
         pop.release()
         torch.cuda.empty_cache()
+
+    # a whole SIR run at this size: 499 steps in one call after one step,
+    # in the automatic mode (gather for long calls) and in the tiled mode
+    runs = {}
+    for label, tu in (("auto", {}), ("tiled32", dict(sir_form=1, sir_count=4, sir_tile=32))):
+        pop = A.Population(A.SIR, n, L=0, beta=(1, 20), gamma=(1, 100))
+        if tu:
+            pop.tune(**tu)
+        pop.step(1)
+        secs = timed_steps(torch, pop, 499, 0)
+        inv = pop.invariants()
+        runs[label] = {"seconds": round(secs, 4), "agent_steps_per_s": round(n * 499 / secs, 1),
+                       "digest": inv["digest"]}
+        pop.release()
+        torch.cuda.empty_cache()
+    runs["identical_outputs"] = runs["auto"]["digest"] == runs["tiled32"]["digest"]
+    res["sir_whole_run_499_steps"] = runs
     return res
 
 
