@@ -125,6 +125,21 @@ def test_host_threshold_table_equals_exact_fractions(beta):
     assert got_k == k_sat and got == want
 
 
+def test_host_threshold_tables_repeat_exactly():
+    """The host keeps the tables of the betas it has built: asking again, in
+    any order, returns the same exact table."""
+    from oracle import thresholds as TH
+    betas = [(15, 1500), (1, 20), (34, 1500), (1, 20), (15, 1500), (7, 9), (34, 1500)]
+    for beta in betas:
+        want, k_sat = TH.infection_table(*beta)
+        st, got, got_k = A.amber_infection_table(*beta)
+        assert st == A.OK and got_k == k_sat and got == want, beta
+    # an unsupported beta is reported every time, not remembered as a table
+    for _ in range(2):
+        st, _, _ = A.amber_infection_table(1, 100000)
+        assert st == A.E_UNSUPPORTED
+
+
 def test_host_threshold_table_limits():
     st, _, _ = A.amber_infection_table(1, 100000)     # k_sat ~ 2.2e6 entries
     assert st == A.E_UNSUPPORTED
