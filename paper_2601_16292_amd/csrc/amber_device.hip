@@ -108,8 +108,9 @@ __global__ __launch_bounds__(NT) void k_wealth_x(WealthXParams x, uint32_t t, ui
     __shared__ int32_t hist[1u << XB];
     __shared__ uint32_t pcount[PMAX];
     __shared__ uint32_t poff[PMAX];
-    wealth_exchange_partition<XB, PMAX, NT>(x, blockIdx.x, t, parity_in, (mode & 1u) != 0,
-                                            (mode & 2u) != 0, hist, pcount, poff);
+    wealth_exchange_partition<XB, PMAX, NT>(x, xcd_partition(blockIdx.x, gridDim.x), t,
+                                            parity_in, (mode & 1u) != 0, (mode & 2u) != 0,
+                                            hist, pcount, poff);
 }
 
 __global__ __launch_bounds__(1024) void k_wealth_x15(WealthXParams x, uint32_t t, uint32_t parity_in,
@@ -117,8 +118,8 @@ __global__ __launch_bounds__(1024) void k_wealth_x15(WealthXParams x, uint32_t t
 {
     __shared__ int32_t hist[1u << 15];
     __shared__ uint32_t buf[WX15_BUF];
-    wealth_exchange_partition15(x, blockIdx.x, t, parity_in, (mode & 1u) != 0, (mode & 2u) != 0,
-                                hist, buf);
+    wealth_exchange_partition15(x, xcd_partition(blockIdx.x, gridDim.x), t, parity_in,
+                                (mode & 1u) != 0, (mode & 2u) != 0, hist, buf);
 }
 
 // head: move + bin(t).  The gather-mode head also clears demand map 2 and

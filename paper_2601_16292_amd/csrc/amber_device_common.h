@@ -188,6 +188,21 @@ __device__ __forceinline__ void block_exclusive_scan(const uint32_t *in, uint32_
     __syncthreads();
 }
 
+// ------------------------------------------------------------------ XCD-aware work mapping
+// Item of workgroup b out of P items: workgroups are dealt to the 8 XCDs in
+// turn (b mod 8), so this gives each XCD a run of consecutive items.
+// Neighbouring items that read each other's data (wealth owners reading
+// neighbouring table words and record pieces, tiles reading their
+// neighbours' records and rings) then share that XCD's L2.  A bijection on
+// [0, P) for any P; only speed depends on the dealing order.
+__device__ __forceinline__ uint32_t xcd_partition(uint32_t b, uint32_t P)
+{
+    const uint32_t xcd = b & 7u, j = b >> 3;
+    uint32_t start = 0;
+    for (uint32_t y = 0; y < xcd; ++y) start += (P - y + 7) >> 3;   // items dealt to XCD y
+    return start + j;
+}
+
 // ------------------------------------------------------------------ wealth, partition exchange
 // The population is cut into partitions of XR = 2^XB consecutive agents and
 // one workgroup of NT threads (512 or 1024) owns each partition.  The kernel of step t

@@ -235,7 +235,7 @@ __global__ void __launch_bounds__(1024) k_tile_step(TileParams p, StepIO io, uin
     const uint32_t tid = threadIdx.x, NT = blockDim.x;
     const uint32_t lane = tid & 63u, nw = NT >> 6;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wavefront-uniform
-    const uint32_t nT = p.nT, tile = blockIdx.x;
+    const uint32_t nT = p.nT, tile = xcd_partition(blockIdx.x, gridDim.x);
     const uint32_t tj = tile / nT, ti = tile - tj * nT;
     const uint32_t last = (uint32_t)p.L - (nT - 1) * T;
     const uint32_t li = ti ? ti - 1 : nT - 1, ri = ti + 1 < nT ? ti + 1 : 0u;
