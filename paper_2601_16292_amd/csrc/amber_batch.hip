@@ -75,8 +75,11 @@ __global__ __launch_bounds__(NT) void k_wealth_x_batch(WealthXBatch b, uint32_t 
     __shared__ uint32_t poff[PMAX];
     uint32_t lb, nb;
     const uint32_t r = batch_run(b.block_end, b.nruns, lb, nb);
-    wealth_exchange_partition<XB, PMAX, NT>(b.run[r], lb, b.t0[r] + i, parity_in,
-                                            (mode & 1u) != 0, (mode & 2u) != 0, hist, pcount, poff);
+    // blocks lb and lb + 8 of a run sit on one XCD whatever the run's first
+    // block: the run's partitions are dealt as in the single-run kernel
+    wealth_exchange_partition<XB, PMAX, NT>(b.run[r], xcd_partition(lb, nb), b.t0[r] + i,
+                                            parity_in, (mode & 1u) != 0, (mode & 2u) != 0, hist,
+                                            pcount, poff);
 }
 
 // ------------------------------------------------------------------ SIR (pipelined)
