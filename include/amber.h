@@ -168,7 +168,12 @@ AMBER_API amber_status_t amber_infection_table(uint32_t beta_num, uint32_t beta_
  * wealth to wealth_init; RANDOM_WALK and SIR draw x and y uniformly on the
  * grid (INIT_POS words); SIR marks agents 0..I0-1 infected, the rest
  * susceptible.  Enqueues on hip_stream (a hipStream_t; NULL = default
- * stream) and returns a handle at step 0.  Does not synchronise. */
+ * stream) and returns a handle at step 0.  Does not synchronise.
+ * AMBER_E_INVALID for a bad descriptor, or for a buffer that is NULL,
+ * misaligned, not device memory of the current device, or (where the runtime
+ * reports the extent of its allocation) shorter than the run needs;
+ * AMBER_E_NOMEM when workspace_bytes is below amber_workspace_bytes(desc).
+ * Nothing is enqueued when it fails. */
 AMBER_API amber_status_t amber_init_population(const amber_run_desc_t *desc,
                                      const amber_buffers_t *bufs,
                                      void *hip_stream, amber_pop_t **out);

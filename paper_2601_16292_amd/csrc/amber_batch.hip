@@ -70,7 +70,7 @@ template <int XB, int PMAX, int NT>
 __global__ __launch_bounds__(NT) void k_wealth_x_batch(WealthXBatch b, uint32_t i,
                                                        uint32_t parity_in, uint32_t mode)
 {
-    __shared__ int32_t hist[1u << XB];
+    __shared__ __align__(16) int32_t hist[1u << XB];
     __shared__ uint32_t pcount[PMAX];
     __shared__ uint32_t poff[PMAX];
     uint32_t lb, nb;

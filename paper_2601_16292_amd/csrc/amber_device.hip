@@ -105,7 +105,7 @@ template <int XB, int PMAX, int NT>
 __global__ __launch_bounds__(NT) void k_wealth_x(WealthXParams x, uint32_t t, uint32_t parity_in,
                                                  uint32_t mode)
 {
-    __shared__ int32_t hist[1u << XB];
+    __shared__ __align__(16) int32_t hist[1u << XB];
     __shared__ uint32_t pcount[PMAX];
     __shared__ uint32_t poff[PMAX];
     wealth_exchange_partition<XB, PMAX, NT>(x, xcd_partition(blockIdx.x, gridDim.x), t,
@@ -116,7 +116,7 @@ __global__ __launch_bounds__(NT) void k_wealth_x(WealthXParams x, uint32_t t, ui
 __global__ __launch_bounds__(1024) void k_wealth_x15(WealthXParams x, uint32_t t, uint32_t parity_in,
                                                      uint32_t mode)
 {
-    __shared__ int32_t hist[1u << 15];
+    __shared__ __align__(16) int32_t hist[1u << 15];
     __shared__ uint32_t buf[WX15_BUF];
     wealth_exchange_partition15(x, xcd_partition(blockIdx.x, gridDim.x), t, parity_in,
                                 (mode & 1u) != 0, (mode & 2u) != 0, hist, buf);

@@ -212,8 +212,8 @@ __device__ __forceinline__ uint32_t xcd_partition(uint32_t b, uint32_t P)
 //   (2) decides its donors on the resulting snapshot, takes their unit, and
 //       draws their recipients;
 //   (3) counting-sorts those recipient ids by destination partition in LDS
-//       and writes them to its own output segment with plain stores, plus one
-//       (offset, count) word per destination.
+//       and writes them to its own output segment with contiguous stores,
+//       plus one (offset, count) word per destination.
 // No global atomics are used, and the column is read and written once per
 // step.  Records and tables are double-buffered by step parity; a call ends
 // with a fold-only launch, so the column holds the state at every call
@@ -231,6 +231,32 @@ __device__ __forceinline__ void wealth_fold_source(int32_t *h, const uint32_t *s
 #pragma unroll
         for (uint32_t j = 0; j < 8; ++j)
             if (r[j] != 0xffffffffu) atomicAdd(&h[r[j]], 1);
+    }
+}
+
+// Writes the producer's recipient ids to its output segment, grouped by
+// destination: record (g, j) goes to position off[dest] + rank.  The ids are
+// first placed in LDS (stage, at least `total` words, free at this point),
+// then copied out with contiguous 16-byte stores, so that every memory line
+// of the segment is written whole by one wavefront.
+template <int G, int XB, int NT>
+__device__ __forceinline__ void wealth_write_records(uint32_t *rec_out, uint32_t *stage,
+                                                     const uint32_t (&rcp)[G][4],
+                                                     const uint32_t (&rank)[G][4],
+                                                     const uint32_t *off, uint32_t total)
+{
+#pragma unroll
+    for (uint32_t g = 0; g < G; ++g)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (rcp[g][j] != 0xffffffffu) stage[off[rcp[g][j] >> XB] + rank[g][j]] = rcp[g][j];
+    __syncthreads();
+    for (uint32_t i = 4 * threadIdx.x; i < total; i += 4 * NT) {
+        if (i + 4 <= total) {
+            *(uint4 *)(rec_out + i) = *(const uint4 *)(stage + i);
+        } else {
+            for (uint32_t k = i; k < total; ++k) rec_out[k] = stage[k];
+        }
     }
 }
 
@@ -305,13 +331,9 @@ __device__ __forceinline__ void wealth_exchange_partition(const WealthXParams &x
     if (!produce) return;
     __syncthreads();
     block_exclusive_scan<NT, (PMAX + NT - 1) / NT>(pcount, poff, P);
-    uint32_t *rec_out = x.rec[parity_in ^ 1u] + (size_t)p * XR;
-#pragma unroll
-    for (uint32_t g = 0; g < G; ++g)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-            if (rcp[g][j] != 0xffffffffu)
-                rec_out[poff[rcp[g][j] >> XB] + rank[g][j]] = rcp[g][j];
+    // the fold histogram (XR words) is dead: it stages the at most XR records
+    wealth_write_records<G, XB, NT>(x.rec[parity_in ^ 1u] + (size_t)p * XR, (uint32_t *)hist,
+                                    rcp, rank, poff, poff[P - 1] + pcount[P - 1]);
     uint32_t *tab_out = x.tab[parity_in ^ 1u] + (size_t)p * P;
     for (uint32_t d = tid; d < P; d += NT) tab_out[d] = (poff[d] << 16) | pcount[d];
 }
@@ -398,13 +420,8 @@ __device__ __forceinline__ void wealth_exchange_partition15(const WealthXParams 
     if (!produce) return;
     __syncthreads();
     block_exclusive_scan<1024, 5>(pcount, pcount, P + 1);      // counts -> offsets, total last
-    uint32_t *rec_out = x.rec[parity_in ^ 1u] + (size_t)p * XR;
-#pragma unroll
-    for (uint32_t g = 0; g < G; ++g)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-            if (rcp[g][j] != 0xffffffffu)
-                rec_out[pcount[rcp[g][j] >> XB] + rank[g][j]] = rcp[g][j];
+    wealth_write_records<G, XB, 1024>(x.rec[parity_in ^ 1u] + (size_t)p * XR, (uint32_t *)hist,
+                                      rcp, rank, pcount, pcount[P]);
     uint32_t *tab_out = x.tab[parity_in ^ 1u] + (size_t)p * P;
     for (uint32_t d = tid; d < P; d += 1024)
         tab_out[d] = (pcount[d] << 16) | (pcount[d + 1] - pcount[d]);

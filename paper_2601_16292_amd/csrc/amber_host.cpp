@@ -527,7 +527,21 @@ amber_status_t check_device_ptr(const void *p, int device, const char *what, siz
     if (attr.device != device)
         return fail(AMBER_E_INVALID, "%s lives on device %d, current device is %d", what,
                     attr.device, device);
-    (void)need;
+    // The need bytes from p must lie inside the allocation that holds p (the
+    // runtime may not know the extent of every kind of allocation: then only
+    // the caller's declared sizes stand).
+    hipDeviceptr_t base = nullptr;
+    size_t extent = 0;
+    if (hipMemGetAddressRange(&base, &extent, const_cast<void *>(p)) != hipSuccess) {
+        (void)hipGetLastError();
+        return AMBER_OK;
+    }
+    const uint64_t off = (uint64_t)((uintptr_t)p - (uintptr_t)base);
+    if ((uintptr_t)p < (uintptr_t)base || off > extent || extent - off < need)
+        return fail(AMBER_E_INVALID,
+                    "%s has %llu bytes left in its allocation, the run needs %llu", what,
+                    (unsigned long long)((uintptr_t)p < (uintptr_t)base || off > extent ? 0 : extent - off),
+                    (unsigned long long)need);
     return AMBER_OK;
 }
 
@@ -720,8 +734,7 @@ uint32_t tile_block(const amber_pop *p, const TileParams &tp)
     return std::max(b, p->tuning.block);
 }
 
-// The exchange mode (no global atomics) runs on request or when the
-// autotuner measures it faster.
+// The box mode: one read of a per-cell 3x3 sum per susceptible agent.
 bool sir_box_mode(const amber_pop *p, uint32_t n_steps) { return sir_count_mode(p, n_steps) == 2; }
 
 amber_status_t enqueue_steps(amber_pop *p, uint32_t n_steps)

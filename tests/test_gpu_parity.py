@@ -231,6 +231,55 @@ def test_device_validation(A):
     assert A.amber_step(h, 1) == A.E_STATE
 
 
+def _allocation_range(ptr):
+    """(base, size) of the HIP allocation holding device address ptr, or None."""
+    import ctypes
+    try:
+        hip = ctypes.CDLL("libamdhip64.so")
+    except OSError:
+        return None
+    base, size = ctypes.c_void_p(), ctypes.c_size_t()
+    if hip.hipMemGetAddressRange(ctypes.byref(base), ctypes.byref(size), ctypes.c_void_p(ptr)) != 0:
+        return None
+    return base.value, size.value
+
+
+def test_buffers_shorter_than_their_allocation_allows(A):
+    """A buffer that starts too close to the end of its allocation is refused.
+    Each case also carries a later fault (a host workspace, a workspace off the
+    256-byte grid), so that nothing is enqueued even if the extent check were
+    missing: only the error message tells which check fired."""
+    import torch
+    say("case buffer extent")
+    d = A.make_desc(A.RANDOM_WALK, 1000, 10)
+    need = A.amber_column_bytes(d, A.COL_X)
+    x = torch.empty(need // 4, dtype=torch.int32, device="cuda")
+    y = torch.empty_like(x)
+    ws = torch.empty(A.amber_workspace_bytes(d) + 512, dtype=torch.uint8, device="cuda")
+    rng = _allocation_range(y.data_ptr())
+    if rng is None:
+        pytest.skip("the runtime does not report allocation extents")
+    base, size = rng
+    assert base <= y.data_ptr() and y.data_ptr() + need <= base + size
+    host_ws = np.zeros(64, dtype=np.uint8)
+    b = A.Buffers()
+    b.col[A.COL_X], b.col[A.COL_Y] = x.data_ptr(), (base + size - 256) & ~15
+    b.workspace, b.workspace_bytes = host_ws.ctypes.data, A.amber_workspace_bytes(d)
+    st, h = A.amber_init_population(d, b, 0)
+    assert st == A.E_INVALID and "y column" in A.amber_last_error() \
+        and "allocation" in A.amber_last_error(), A.amber_last_error()
+    b.col[A.COL_Y] = y.data_ptr()
+    wbase, wsize = _allocation_range(ws.data_ptr())
+    b.workspace = ((wbase + wsize - A.amber_workspace_bytes(d) // 2) & ~255) + 16
+    st, h = A.amber_init_population(d, b, 0)
+    assert st == A.E_INVALID and "workspace" in A.amber_last_error() \
+        and "allocation" in A.amber_last_error(), A.amber_last_error()
+    b.workspace = ws.data_ptr()
+    st, h = A.amber_init_population(d, b, 0)
+    assert st == A.OK, A.amber_last_error()
+    assert A.amber_release(h) == A.OK
+
+
 # ------------------------------------------------------------------ launch shapes
 
 def _sir_tuned(A, n, L, steps, chunks, tunings, seed=2, stream=6, beta=(1, 10), gamma=(1, 30)):
