@@ -219,18 +219,24 @@ __device__ __forceinline__ uint32_t xcd_partition(uint32_t b, uint32_t P)
 // with a fold-only launch, so the column holds the state at every call
 // boundary.
 
-// Adds the cnt records at src (agent ids; h is the histogram shifted by the
-// partition's first id) to the fold histogram: rounds of 8 loads in flight
-// before their LDS adds.
-__device__ __forceinline__ void wealth_fold_source(int32_t *h, const uint32_t *src, uint32_t cnt)
+// Adds records [off, off + cnt) of a source's segment seg (agent ids; h is
+// the histogram shifted by the partition's first id) to the fold histogram.
+// The records are read with aligned 16-byte loads, two per round: a piece of
+// a few records then costs one or two loads, whatever its offset.  seg is
+// 16-byte aligned and off + cnt never passes the segment's end (a multiple
+// of 4 words), so every load stays inside the segment; words outside the
+// piece are read and ignored.
+__device__ __forceinline__ void wealth_fold_source(int32_t *h, const uint32_t *seg, uint32_t off,
+                                                   uint32_t cnt)
 {
-    for (uint32_t k = 0; k < cnt; k += 8) {
-        uint32_t r[8];
-#pragma unroll
-        for (uint32_t j = 0; j < 8; ++j) r[j] = k + j < cnt ? src[k + j] : 0xffffffffu;
+    const uint32_t end = off + cnt;
+    for (uint32_t k = off & ~3u; k < end; k += 8) {
+        const uint4 u0 = *(const uint4 *)(seg + k);
+        const uint4 u1 = k + 4 < end ? *(const uint4 *)(seg + k + 4) : make_uint4(0, 0, 0, 0);
+        const uint32_t v[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
 #pragma unroll
         for (uint32_t j = 0; j < 8; ++j)
-            if (r[j] != 0xffffffffu) atomicAdd(&h[r[j]], 1);
+            if (k + j >= off && k + j < end) atomicAdd(&h[v[j]], 1);
     }
 }
 
@@ -280,12 +286,9 @@ __device__ __forceinline__ void wealth_exchange_partition(const WealthXParams &x
     const uint32_t e = consume && tid < P ? tab[(size_t)tid * P + p] : 0u;
     for (uint32_t i = tid; i < XR; i += NT) hist[i] = 0;
     __syncthreads();
-    if (consume && tid < P) {
-        const uint32_t cnt = e & 0xffffu;
-        const uint32_t *src = x.rec[parity_in] + (size_t)tid * XR + (e >> 16);
-        int32_t *const h = hist - (size_t)p * XR;
-        wealth_fold_source(h, src, cnt);
-    }
+    if (consume && tid < P)
+        wealth_fold_source(hist - (size_t)p * XR, x.rec[parity_in] + (size_t)tid * XR, e >> 16,
+                           e & 0xffffu);
     for (uint32_t i = tid; i < P; i += NT) pcount[i] = 0;
     __syncthreads();
     int4 V[G];
@@ -353,26 +356,24 @@ __device__ __forceinline__ void wealth_exchange_partition15(const WealthXParams 
     const uint32_t tid = threadIdx.x;
     const uint32_t P = x.P;
     const uint32_t groups = groups_of(x.n);
+    // Fold: thread tid takes sources tid, tid + 1024, ... (up to 4).  Their
+    // table entries are loaded before the barrier that orders the histogram
+    // clear, then each source's few records are counted.
+    const uint32_t *tab = x.tab[parity_in];
+    uint32_t e[WX15_PMAX / 1024];
+#pragma unroll
+    for (uint32_t c = 0; c < WX15_PMAX / 1024; ++c) {
+        const uint32_t s = c * 1024 + tid;
+        e[c] = consume && s < P ? tab[(size_t)s * P + p] : 0u;
+    }
     for (uint32_t i = tid; i < XR; i += 1024) hist[i] = 0;
     __syncthreads();
     if (consume) {
-        // Fold: thread tid takes sources tid, tid + 1024, ... (up to 4): their
-        // table entries first, then each source's few records.
-        const uint32_t *tab = x.tab[parity_in];
         const uint32_t *rec = x.rec[parity_in];
         int32_t *const h = hist - (size_t)p * XR;
-        uint32_t e[WX15_PMAX / 1024];
 #pragma unroll
-        for (uint32_t c = 0; c < WX15_PMAX / 1024; ++c) {
-            const uint32_t s = c * 1024 + tid;
-            e[c] = s < P ? tab[(size_t)s * P + p] : 0u;
-        }
-#pragma unroll
-        for (uint32_t c = 0; c < WX15_PMAX / 1024; ++c) {
-            const uint32_t cnt = e[c] & 0xffffu;
-            const uint32_t *src = rec + (size_t)(c * 1024 + tid) * XR + (e[c] >> 16);
-            wealth_fold_source(h, src, cnt);
-        }
+        for (uint32_t c = 0; c < WX15_PMAX / 1024; ++c)
+            wealth_fold_source(h, rec + (size_t)(c * 1024 + tid) * XR, e[c] >> 16, e[c] & 0xffffu);
     }
     __syncthreads();
     uint32_t *pcount = buf;                       // P counts, then P + 1 offsets
