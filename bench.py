@@ -339,10 +339,12 @@ def roofline_big(torch, A, log2n):
         pop.release()
         torch.cuda.empty_cache()
 
-    # a whole SIR run at this size: 499 steps in one call after one step,
-    # in the automatic mode (gather for long calls) and in the tiled mode
+    # a whole SIR run at this size: 499 steps in one call after one step, in
+    # the automatic mode (tiled, then gather once few susceptible agents are
+    # left), all in the gather mode, and all in the tiled mode
     runs = {}
-    for label, tu in (("auto", {}), ("tiled32", dict(sir_form=1, sir_count=4, sir_tile=32))):
+    for label, tu in (("auto", {}), ("gather", dict(sir_form=1, sir_count=1)),
+                      ("tiled32", dict(sir_form=1, sir_count=4, sir_tile=32))):
         pop = A.Population(A.SIR, n, L=0, beta=(1, 20), gamma=(1, 100))
         if tu:
             pop.tune(**tu)
@@ -353,7 +355,8 @@ def roofline_big(torch, A, log2n):
                        "digest": inv["digest"]}
         pop.release()
         torch.cuda.empty_cache()
-    runs["identical_outputs"] = runs["auto"]["digest"] == runs["tiled32"]["digest"]
+    runs["identical_outputs"] = (runs["auto"]["digest"] == runs["gather"]["digest"]
+                                 == runs["tiled32"]["digest"])
     res["sir_whole_run_499_steps"] = runs
     return res
 

@@ -215,9 +215,10 @@ typedef struct {
     uint32_t max_groups_per_thread; /* persistent form: largest number of 4-agent
                                   groups a thread may hold (1, 2, 4, 8; 0 = 8)    */
     uint32_t sir_count;        /* SIR neighbour counts in the pipelined form:
-                                  0 = automatic (1 for calls of 128 steps or
-                                  more or grids of at most 16M cells, else 4
-                                  in plain calls and 2 in batches),
+                                  0 = automatic: 1 on grids of at most 16M
+                                  cells; on larger grids 5 for calls of 128
+                                  steps or more, else 4 (in batches: 1 for
+                                  such long calls, else 2),
                                   1 = sum the 3x3 block of the
                                   count grid per agent, 2 = box-sum the grid once
                                   per step (one stencil kernel) and read one
@@ -232,7 +233,15 @@ typedef struct {
                                   tile bins and sums the counts in LDS (needs a
                                   grid side of at least 2 x tile + 2, else
                                   AMBER_E_UNSUPPORTED; inside amber_step_batch
-                                  such runs use the automatic mode)              */
+                                  such runs use the automatic mode),
+                                  5 = tiled, then gather: as 4, and every 16
+                                  steps of calls over 32 steps the host reads a
+                                  device count of susceptible agents from the
+                                  previous poll; once 20 S <= N it ends the
+                                  tiled part (records back to the columns) and
+                                  runs the rest of the call as mode 1 (same
+                                  condition and fallback as 4; with sir_poll 1
+                                  or under graph capture it stays tiled)        */
     uint32_t wealth_form;      /* WEALTH above 8192 agents: 0 = automatic,
                                   1 = global atomic scatter-add, 2 = partition
                                   exchange (recipient ids counting-sorted by
@@ -247,10 +256,12 @@ typedef struct {
                                   on the host every 16 launches until at most 32
                                   of the call's launches are queued, and stops
                                   enqueueing once that launch has started.  In
-                                  amber_step_batch a chunk of up to 16 SIR runs
-                                  stops once all of them have (on when every run
-                                  of the chunk has 0).  Never while the stream
-                                  is being captured into a graph.
+                                  amber_step_batch a run leaves the later
+                                  launches once its own such launch has started
+                                  (on when every gather-mode run of the batch
+                                  has 0).  Never while the stream is being
+                                  captured into a graph.  Mode 5 polls its
+                                  susceptible count the same way.
                                   1 = off: never waits; one launch per step.      */
     uint32_t reserved;
 } amber_tuning_t;

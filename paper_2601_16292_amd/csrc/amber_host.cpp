@@ -240,7 +240,7 @@ struct Resolved {
     uint32_t tile_tiles = 0;                        // tiles of the smallest side the buffers fit
     uint64_t tile_rec = 0;                          // record slots per generation
     uint64_t off_trec[2] = {0, 0}, off_thdr[2] = {0, 0}, off_tring[2] = {0, 0};
-    uint64_t off_tcur = 0, off_tctr = 0;
+    uint64_t off_tcur = 0, off_tctr = 0, off_tscnt = 0;
     uint64_t ws_bytes = 0;
 };
 
@@ -344,6 +344,8 @@ amber_status_t resolve(const amber_run_desc_t *d, Resolved &r, bool want_table)
                 ws += align_up((uint64_t)r.tile_tiles * 4, 256);
                 r.off_tctr = ws;
                 ws += 512;
+                r.off_tscnt = ws;               // susceptible agents per tile
+                ws += align_up((uint64_t)r.tile_tiles * 4, 256);
             }
         }
     }
@@ -609,7 +611,7 @@ hipError_t timer_cut(amber_pop *p)
 int32_t *col_i32(amber_pop *p, amber_col_t c) { return (int32_t *)p->b.col[c]; }
 uint8_t *ws_ptr(amber_pop *p, uint64_t off) { return (uint8_t *)p->b.workspace + off; }
 
-SirParams sir_params(amber_pop *p)
+SirParams sir_params(amber_pop *p, uint32_t t_base)
 {
     const Resolved &r = p->r;
     SirParams sp{};
@@ -628,7 +630,7 @@ SirParams sir_params(amber_pop *p)
     sp.L = (int32_t)r.L;
     sp.k0 = r.seed;
     sp.k1 = r.stream;
-    sp.t_base = (uint32_t)p->step;
+    sp.t_base = t_base;
     if (r.sx_P) {
         sp.xrec = (uint32_t *)ws_ptr(p, r.off_sxrec);
         sp.xtab = (uint32_t *)ws_ptr(p, r.off_sxtab);
@@ -639,21 +641,25 @@ SirParams sir_params(amber_pop *p)
     return sp;
 }
 
-// SIR neighbour-count mode of the pipelined form: 1 gather, 2 box, 3 exchange.
+// SIR neighbour-count mode of the pipelined form: 1 gather, 2 box, 3 exchange,
+// 4 tiled, 5 tiled until few susceptible agents remain, then gather.
 // Automatic choice for grids that fit in the last-level cache: the 3x3
 // gathers.  Beyond it every gathered cell and every binning atomic costs its
 // own memory line: the box mode then (one read per agent instead of nine),
 // and inside a plain call the tiled mode ahead of both (no random access).
-// A call of SIR_AUTO_LONG_CALL steps or more keeps the gather mode at any
-// size: over a long call its demand-driven binning and the launch that runs
-// the steps left once no susceptible agent remains outweigh the slower
-// early steps (a 500-step run at 2^27 agents: 0.57 s against 1.10 s tiled).
+// A call of SIR_AUTO_LONG_CALL steps or more on such a grid starts tiled and
+// moves to the gather mode once few susceptible agents are left: from then
+// on the demand-driven binning and the launch that runs the steps left once
+// none remains make the gather steps the cheaper ones (a 500-step run at
+// 2^27 agents: 0.57 s all gather, 1.10 s all tiled).  On smaller grids a
+// long call keeps the gather mode.
 constexpr uint32_t SIR_AUTO_LONG_CALL = 128;
 
 uint32_t sir_auto_count_mode(const amber_pop *p, uint32_t n_steps)
 {
-    if (n_steps >= SIR_AUTO_LONG_CALL) return 1u;
-    return (uint64_t)p->r.L * p->r.L > (16ull << 20) ? 2u : 1u;
+    const bool big = (uint64_t)p->r.L * p->r.L > (16ull << 20);
+    if (!big) return 1u;
+    return n_steps >= SIR_AUTO_LONG_CALL ? 5u : 2u;
 }
 
 uint32_t sir_tile_side(const amber_pop *p);
@@ -676,18 +682,21 @@ uint32_t sir_count_mode(const amber_pop *p, uint32_t n_steps)
 {
     const uint32_t want = p->tuning.sir_count;
     if (want == 3) return p->r.sx_P ? 3u : 0u;    // 0: unavailable, caller reports it
-    if (want == 4) return sir_tile_side(p) ? 4u : 0u;
+    if (want == 4 || want == 5) return sir_tile_side(p) ? want : 0u;
     if (want == 1 || want == 2) return want;
     const uint32_t m = sir_auto_count_mode(p, n_steps);
-    return m == 2 && sir_tile_side(p) ? 4u : m;
+    if (m == 2) return sir_tile_side(p) ? 4u : 2u;
+    if (m == 5) return sir_tile_side(p) ? 5u : 1u;
+    return m;
 }
 
 // Count mode of a run inside amber_step_batch (the batched kernels have the
-// gather, box and exchange modes).
+// gather, box and exchange modes): the tiled modes become box for short
+// calls on big grids and gather otherwise.
 uint32_t sir_batch_count_mode(const amber_pop *p, uint32_t n_steps)
 {
     const uint32_t m = sir_count_mode(p, n_steps);
-    if (m == 4) return sir_auto_count_mode(p, n_steps);
+    if (m == 4 || m == 5) return sir_auto_count_mode(p, n_steps) == 2 ? 2u : 1u;
     return m == 0 ? 1u : m;     // exchange requested but unavailable: gather
 }
 
@@ -734,8 +743,209 @@ uint32_t tile_block(const amber_pop *p, const TileParams &tp)
     return std::max(b, p->tuning.block);
 }
 
-// The box mode: one read of a per-cell 3x3 sum per susceptible agent.
-bool sir_box_mode(const amber_pop *p, uint32_t n_steps) { return sir_count_mode(p, n_steps) == 2; }
+// SIR steps t0 .. t0 + n_steps - 1 of the pipelined form in the gather mode.
+amber_status_t enqueue_sir_gather(amber_pop *p, uint32_t t0, uint32_t n_steps)
+{
+    const Tuning &tu = p->tuning;
+    hipStream_t st = p->stream;
+    SirParams sp = sir_params(p, t0);
+    sp.t_last = t0 + n_steps - 1;
+    // Early stop: once no susceptible agent is left, one body launch
+    // runs the call's remaining steps and announces it in a pinned
+    // word; the later launches would do nothing.  Every SIR_POLL
+    // launches the host waits until at most 2 x SIR_POLL launches are
+    // queued and stops enqueueing once the word holds this call's
+    // number.  Results do not depend on where it stops.
+    const bool poll = tu.sir_poll == 0 && p->stop_host && n_steps > 2 * SIR_POLL &&
+                      !stream_capturing(st);
+    if (poll) {
+        HIP_TRY(poll_events(p), "poll events");
+        if (++p->call_seq == 0) ++p->call_seq;
+        sp.stop_word = p->stop_dev;
+        sp.stop_seq = p->call_seq;
+    }
+    HIP_TRY(timed(p, "sir_head", [&] { return launch_sir_head(sp, t0, false, tu, st); }),
+            "sir head kernel");
+    uint32_t last = n_steps - 1;
+    for (uint32_t i = 1; i < n_steps; ++i) {
+        HIP_TRY(timed(p, "sir_body",
+                      [&] { return launch_sir_body(sp, t0 + i, false, tu, st); }),
+                "sir body kernel");
+        if (!poll || i % SIR_POLL != 0) continue;
+        const uint32_t k = i / SIR_POLL;
+        HIP_TRY(hipEventRecord(p->poll_ev[k & 1], st), "poll event record");
+        if (k < 2) continue;
+        HIP_TRY(hipEventSynchronize(p->poll_ev[(k - 1) & 1]), "poll event synchronize");
+        if (__atomic_load_n(p->stop_host, __ATOMIC_ACQUIRE) == p->call_seq) {
+            last = i;
+            break;
+        }
+    }
+    HIP_TRY(timed(p, "sir_tail",
+                  [&] { return launch_sir_tail(sp, t0 + n_steps - 1, last, false, tu, st); }),
+            "sir tail kernel");
+    HIP_TRY(timed(p, "sir_clear",
+                  [&] { return launch_sir_clear(sp, 1u << ((n_steps - 1) % 3), st); }),
+            "sir clear kernel");
+    return AMBER_OK;
+}
+
+// Fraction of susceptible agents at or below which a tiled-then-gather call
+// moves to the gather mode: S * SIR_SWITCH_DIV <= N.  With the host's poll
+// lag (one to two polls) the switch lands near S = N / 50, about where a
+// gather-mode step (nine gathers per susceptible agent, demand-driven
+// binning) becomes cheaper than a tiled step (every agent sorted).
+constexpr uint32_t SIR_SWITCH_DIV = 20;
+
+// SIR steps t0 .. t0 + n_steps - 1 in the tiled mode: sort, head, bodies,
+// tail, then the two count grids back to zero.  With may_switch the bodies
+// also count the susceptible agents per tile; every SIR_POLL body launches
+// a one-workgroup kernel sums them into the handle's pinned words, and the
+// host reads the sum of the previous poll.  Once S * SIR_SWITCH_DIV <= N it
+// ends the tiled segment there (the tail writes the columns back) and
+// reports in *done how many steps the segment covered; the caller runs the
+// rest in the gather mode.  Results do not depend on where it switches.
+amber_status_t enqueue_sir_tiled(amber_pop *p, uint32_t t0, uint32_t n_steps, bool may_switch,
+                                 uint32_t *done)
+{
+    const Resolved &r = p->r;
+    hipStream_t st = p->stream;
+    const bool poll = may_switch && p->tuning.sir_poll == 0 && p->stop_host &&
+                      n_steps > 2 * SIR_POLL && !stream_capturing(st);
+    TileParams tp = tile_params(p, sir_tile_side(p));
+    if (poll) {
+        HIP_TRY(poll_events(p), "poll events");
+        tp.scnt = (uint32_t *)ws_ptr(p, r.off_tscnt);
+    }
+    const uint32_t blk = tile_block(p, tp);
+    HIP_TRY(timed(p, "sir_tile_sort", [&] { return launch_sir_tile_sort(tp, st); }),
+            "sir tile sort kernels");
+    HIP_TRY(timed(p, "sir_tile_head", [&] { return launch_sir_tile_step(tp, t0, 0, n_steps, blk, st); }),
+            "sir tile step kernel");
+    uint32_t k = n_steps;                        // steps of the tiled segment
+    for (uint32_t i = 1; i < n_steps; ++i) {
+        HIP_TRY(timed(p, "sir_tile_body",
+                      [&] { return launch_sir_tile_step(tp, t0, i, n_steps, blk, st); }),
+                "sir tile step kernel");
+        if (!poll || i % SIR_POLL != 0 || i + 1 >= n_steps) continue;
+        const uint32_t q = i / SIR_POLL;
+        uint32_t *sum_dev = p->stop_dev + 1 + (q & 1);       // words 1 and 2 of the slot
+        HIP_TRY(timed(p, "sir_tile_count",
+                      [&] { return launch_sum_words(tp.scnt, tp.nT * tp.nT, sum_dev, st); }),
+                "sir tile count kernel");
+        HIP_TRY(hipEventRecord(p->poll_ev[q & 1], st), "poll event record");
+        if (q < 2) continue;
+        HIP_TRY(hipEventSynchronize(p->poll_ev[(q - 1) & 1]), "poll event synchronize");
+        const uint32_t sus = __atomic_load_n(p->stop_host + 1 + ((q - 1) & 1), __ATOMIC_ACQUIRE);
+        if ((uint64_t)sus * SIR_SWITCH_DIV <= r.n) {
+            k = i + 1;
+            break;
+        }
+    }
+    HIP_TRY(timed(p, "sir_tile_tail", [&] { return launch_sir_tile_step(tp, t0, k, k, blk, st); }),
+            "sir tile step kernel");
+    // the two count grids it used go back to zero, as the other modes expect
+    const uint64_t words = (r.off_count[2] - r.off_count[0]) / 4;
+    HIP_TRY(timed(p, "sir_clear", [&] { return launch_zero_words(tp.C[0], words, st); }),
+            "sir clear kernel");
+    *done = k;
+    return AMBER_OK;
+}
+
+// SIR steps t0 .. t0 + n_steps - 1 in the form and count mode the tuning
+// (or the automatic choice) selects.
+amber_status_t enqueue_sir(amber_pop *p, uint32_t t0, uint32_t n_steps)
+{
+    const Resolved &r = p->r;
+    hipStream_t st = p->stream;
+    const Tuning &tu = p->tuning;
+    const uint32_t mode = sir_count_mode(p, n_steps);
+    SirParams sp = sir_params(p, t0);
+    sp.t_last = t0 + n_steps - 1;
+    // Automatic choice: the pipelined form.  The persistent form keeps the
+    // state in registers but pays a device-wide barrier per step, which on
+    // gfx950 costs more than the launch it saves; it runs only on request.
+    uint32_t g = 0, blocks = 0;
+    if (tu.sir_form == 2) {
+        if (tu.max_g >= 8) {
+            g = p->persist_g;
+            blocks = p->persist_blocks;
+        } else {
+            g = sir_persistent_groups_per_thread(r.n, tu.max_g, &blocks);
+        }
+        if (g == 0)
+            return fail(AMBER_E_UNSUPPORTED,
+                        "the persistent SIR form does not fit %u agents on this device", r.n);
+    }
+    if (g) {
+        uint32_t *sync_words = (uint32_t *)ws_ptr(p, r.off_sync);
+        uint32_t *err = (uint32_t *)ws_ptr(p, ERR_FLAG_OFFSET);
+        HIP_TRY(timed(p, "sir_persistent",
+                      [&] {
+                          return launch_sir_persistent(sp, sync_words, err, t0, n_steps, g,
+                                                       blocks, st);
+                      }),
+                "sir persistent kernel");
+        HIP_TRY(timed(p, "sir_clear",
+                      [&] { return launch_sir_clear(sp, 1u << ((n_steps - 1) % 3), st); }),
+                "sir clear kernel");
+    } else if (tu.sir_count == 3 && !r.sx_P) {
+        return fail(AMBER_E_UNSUPPORTED, "the exchange count mode does not fit this run "
+                                         "(grid side %u, %u agents)", r.L, r.n);
+    } else if (tu.sir_count == 4 && !sir_tile_side(p)) {
+        return fail(AMBER_E_UNSUPPORTED, "the tiled count mode needs a grid side of at least "
+                                         "2 x tile + 2 (grid side %u, tile %u)",
+                    r.L, tu.sir_tile ? tu.sir_tile : TILE_MIN);
+    } else if (tu.sir_count == 5 && !sir_tile_side(p)) {
+        return fail(AMBER_E_UNSUPPORTED, "the tiled-then-gather count mode needs a grid side of "
+                                         "at least 2 x tile + 2 (grid side %u, tile %u)",
+                    r.L, tu.sir_tile ? tu.sir_tile : TILE_MIN);
+    } else if (mode == 4 || mode == 5) {
+        uint32_t done = 0;
+        const amber_status_t rc = enqueue_sir_tiled(p, t0, n_steps, mode == 5, &done);
+        if (rc != AMBER_OK || done == n_steps) return rc;
+        return enqueue_sir_gather(p, t0 + done, n_steps - done);
+    } else if (mode == 3) {
+        HIP_TRY(timed(p, "sir_xbody", [&] { return launch_sir_xbody(sp, t0, false, st); }),
+                "sir exchange body kernel");
+        HIP_TRY(timed(p, "sir_xcount", [&] { return launch_sir_xcount(sp, st); }),
+                "sir exchange count kernel");
+        for (uint32_t i = 1; i < n_steps; ++i) {
+            HIP_TRY(timed(p, "sir_xbody",
+                          [&] { return launch_sir_xbody(sp, t0 + i, true, st); }),
+                    "sir exchange body kernel");
+            HIP_TRY(timed(p, "sir_xcount", [&] { return launch_sir_xcount(sp, st); }),
+                    "sir exchange count kernel");
+        }
+        HIP_TRY(timed(p, "sir_tail_box",
+                      [&] { return launch_sir_tail(sp, t0 + n_steps - 1, n_steps - 1, true, tu, st); }),
+                "sir tail kernel");
+        HIP_TRY(timed(p, "sir_clear",
+                      [&] { return launch_sir_clear(sp, 4u, st); }),
+                "sir clear kernel");
+    } else if (mode == 2) {
+        HIP_TRY(timed(p, "sir_head", [&] { return launch_sir_head(sp, t0, true, tu, st); }),
+                "sir head kernel");
+        HIP_TRY(timed(p, "sir_box", [&] { return launch_sir_box(sp, t0, st); }),
+                "sir box kernel");
+        for (uint32_t i = 1; i < n_steps; ++i) {
+            HIP_TRY(timed(p, "sir_body_box",
+                          [&] { return launch_sir_body(sp, t0 + i, true, tu, st); }),
+                    "sir body kernel");
+            HIP_TRY(timed(p, "sir_box", [&] { return launch_sir_box(sp, t0 + i, st); }),
+                    "sir box kernel");
+        }
+        HIP_TRY(timed(p, "sir_tail_box",
+                      [&] { return launch_sir_tail(sp, t0 + n_steps - 1, n_steps - 1, true, tu, st); }),
+                "sir tail kernel");
+        HIP_TRY(timed(p, "sir_clear",
+                      [&] { return launch_sir_clear(sp, (1u << ((n_steps - 1) & 1)) | 4u, st); }),
+                "sir clear kernel");
+    } else {
+        return enqueue_sir_gather(p, t0, n_steps);
+    }
+    return AMBER_OK;
+}
 
 amber_status_t enqueue_steps(amber_pop *p, uint32_t n_steps)
 {
@@ -796,134 +1006,7 @@ amber_status_t enqueue_steps(amber_pop *p, uint32_t n_steps)
                     "wealth fold kernel");
         }
     } else {
-        SirParams sp = sir_params(p);
-        sp.t_last = t0 + n_steps - 1;
-        // Automatic choice: the pipelined form.  The persistent form keeps the
-        // state in registers but pays a device-wide barrier per step, which on
-        // gfx950 costs more than the launch it saves; it runs only on request.
-        uint32_t g = 0, blocks = 0;
-        if (tu.sir_form == 2) {
-            if (tu.max_g >= 8) {
-                g = p->persist_g;
-                blocks = p->persist_blocks;
-            } else {
-                g = sir_persistent_groups_per_thread(r.n, tu.max_g, &blocks);
-            }
-            if (g == 0)
-                return fail(AMBER_E_UNSUPPORTED,
-                            "the persistent SIR form does not fit %u agents on this device", r.n);
-        }
-        if (g) {
-            uint32_t *sync_words = (uint32_t *)ws_ptr(p, r.off_sync);
-            uint32_t *err = (uint32_t *)ws_ptr(p, ERR_FLAG_OFFSET);
-            HIP_TRY(timed(p, "sir_persistent",
-                          [&] {
-                              return launch_sir_persistent(sp, sync_words, err, t0, n_steps, g,
-                                                           blocks, st);
-                          }),
-                    "sir persistent kernel");
-            HIP_TRY(timed(p, "sir_clear",
-                          [&] { return launch_sir_clear(sp, 1u << ((n_steps - 1) % 3), st); }),
-                    "sir clear kernel");
-        } else if (tu.sir_count == 3 && !r.sx_P) {
-            return fail(AMBER_E_UNSUPPORTED, "the exchange count mode does not fit this run "
-                                             "(grid side %u, %u agents)", r.L, r.n);
-        } else if (tu.sir_count == 4 && !sir_tile_side(p)) {
-            return fail(AMBER_E_UNSUPPORTED, "the tiled count mode needs a grid side of at least "
-                                             "2 x tile + 2 (grid side %u, tile %u)",
-                        r.L, tu.sir_tile ? tu.sir_tile : TILE_MIN);
-        } else if (sir_count_mode(p, n_steps) == 4) {
-            const TileParams tp = tile_params(p, sir_tile_side(p));
-            const uint32_t blk = tile_block(p, tp);
-            HIP_TRY(timed(p, "sir_tile_sort", [&] { return launch_sir_tile_sort(tp, st); }),
-                    "sir tile sort kernels");
-            for (uint32_t i = 0; i <= n_steps; ++i) {
-                const char *name = i == 0 ? "sir_tile_head"
-                                          : (i == n_steps ? "sir_tile_tail" : "sir_tile_body");
-                HIP_TRY(timed(p, name,
-                              [&] { return launch_sir_tile_step(tp, t0, i, n_steps, blk, st); }),
-                        "sir tile step kernel");
-            }
-            // the two count grids it used go back to zero, as the other modes expect
-            const uint64_t words = (r.off_count[2] - r.off_count[0]) / 4;
-            HIP_TRY(timed(p, "sir_clear",
-                          [&] { return launch_zero_words(tp.C[0], words, st); }),
-                    "sir clear kernel");
-        } else if (sir_count_mode(p, n_steps) == 3) {
-            HIP_TRY(timed(p, "sir_xbody", [&] { return launch_sir_xbody(sp, t0, false, st); }),
-                    "sir exchange body kernel");
-            HIP_TRY(timed(p, "sir_xcount", [&] { return launch_sir_xcount(sp, st); }),
-                    "sir exchange count kernel");
-            for (uint32_t i = 1; i < n_steps; ++i) {
-                HIP_TRY(timed(p, "sir_xbody",
-                              [&] { return launch_sir_xbody(sp, t0 + i, true, st); }),
-                        "sir exchange body kernel");
-                HIP_TRY(timed(p, "sir_xcount", [&] { return launch_sir_xcount(sp, st); }),
-                        "sir exchange count kernel");
-            }
-            HIP_TRY(timed(p, "sir_tail_box",
-                          [&] { return launch_sir_tail(sp, t0 + n_steps - 1, n_steps - 1, true, tu, st); }),
-                    "sir tail kernel");
-            HIP_TRY(timed(p, "sir_clear",
-                          [&] { return launch_sir_clear(sp, 4u, st); }),
-                    "sir clear kernel");
-        } else if (sir_box_mode(p, n_steps)) {
-            HIP_TRY(timed(p, "sir_head", [&] { return launch_sir_head(sp, t0, true, tu, st); }),
-                    "sir head kernel");
-            HIP_TRY(timed(p, "sir_box", [&] { return launch_sir_box(sp, t0, st); }),
-                    "sir box kernel");
-            for (uint32_t i = 1; i < n_steps; ++i) {
-                HIP_TRY(timed(p, "sir_body_box",
-                              [&] { return launch_sir_body(sp, t0 + i, true, tu, st); }),
-                        "sir body kernel");
-                HIP_TRY(timed(p, "sir_box", [&] { return launch_sir_box(sp, t0 + i, st); }),
-                        "sir box kernel");
-            }
-            HIP_TRY(timed(p, "sir_tail_box",
-                          [&] { return launch_sir_tail(sp, t0 + n_steps - 1, n_steps - 1, true, tu, st); }),
-                    "sir tail kernel");
-            HIP_TRY(timed(p, "sir_clear",
-                          [&] { return launch_sir_clear(sp, (1u << ((n_steps - 1) & 1)) | 4u, st); }),
-                    "sir clear kernel");
-        } else {
-            // Early stop: once no susceptible agent is left, one body launch
-            // runs the call's remaining steps and announces it in a pinned
-            // word; the later launches would do nothing.  Every SIR_POLL
-            // launches the host waits until at most 2 x SIR_POLL launches are
-            // queued and stops enqueueing once the word holds this call's
-            // number.  Results do not depend on where it stops.
-            const bool poll = tu.sir_poll == 0 && p->stop_host && n_steps > 2 * SIR_POLL &&
-                              !stream_capturing(st);
-            if (poll) {
-                HIP_TRY(poll_events(p), "poll events");
-                if (++p->call_seq == 0) ++p->call_seq;
-                sp.stop_word = p->stop_dev;
-                sp.stop_seq = p->call_seq;
-            }
-            HIP_TRY(timed(p, "sir_head", [&] { return launch_sir_head(sp, t0, false, tu, st); }),
-                    "sir head kernel");
-            uint32_t last = n_steps - 1;
-            for (uint32_t i = 1; i < n_steps; ++i) {
-                HIP_TRY(timed(p, "sir_body",
-                              [&] { return launch_sir_body(sp, t0 + i, false, tu, st); }),
-                        "sir body kernel");
-                if (!poll || i % SIR_POLL != 0) continue;
-                const uint32_t k = i / SIR_POLL;
-                HIP_TRY(hipEventRecord(p->poll_ev[k & 1], st), "poll event record");
-                if (k < 2) continue;
-                HIP_TRY(hipEventSynchronize(p->poll_ev[(k - 1) & 1]), "poll event synchronize");
-                if (__atomic_load_n(p->stop_host, __ATOMIC_ACQUIRE) == p->call_seq) {
-                    last = i;
-                    break;
-                }
-            }
-            HIP_TRY(timed(p, "sir_tail",
-                          [&] { return launch_sir_tail(sp, t0 + n_steps - 1, last, false, tu, st); }),
-                    "sir tail kernel");
-            HIP_TRY(timed(p, "sir_clear",
-                          [&] { return launch_sir_clear(sp, 1u << ((n_steps - 1) % 3), st); }),
-                    "sir clear kernel");
-        }
+        return enqueue_sir(p, t0, n_steps);
     }
     return AMBER_OK;
 }
@@ -966,7 +1049,7 @@ amber_status_t run_sir_gather_batch(amber_pop *lead, const std::vector<amber_pop
     for (amber_pop *p : runs) poll = poll && p->stop_host && p->tuning.sir_poll == 0;
     for (uint32_t r = 0; r < R; ++r) {
         amber_pop *p = runs[r];
-        prm[r] = sir_params(p);
+        prm[r] = sir_params(p, (uint32_t)p->step);
         sir_fill(prm[r]);
         t0[r] = (uint32_t)p->step;
         prm[r].t_last = t0[r] + n_steps - 1;
@@ -1170,7 +1253,7 @@ amber_status_t run_batch(amber_pop *const *pops, uint32_t n, uint32_t n_steps)
             for (size_t k = c; k < runs.size() && k < c + BATCH_RUNS; ++k) {
                 amber_pop *p = runs[k];
                 const uint32_t j = b.nruns++;
-                b.run[j] = sir_params(p);
+                b.run[j] = sir_params(p, (uint32_t)p->step);
                 sir_fill(b.run[j]);
                 b.t0[j] = (uint32_t)p->step;
                 b.run[j].t_last = b.t0[j] + n_steps - 1;
@@ -1439,7 +1522,7 @@ amber_status_t amber_set_tuning(amber_pop_t *pop, const amber_tuning_t *t)
         t->max_groups_per_thread != 2 && t->max_groups_per_thread != 4 &&
         t->max_groups_per_thread != 8)
         return fail(AMBER_E_INVALID, "max_groups_per_thread must be 0, 1, 2, 4 or 8");
-    if (t->sir_count > 4) return fail(AMBER_E_INVALID, "sir_count must be 0, 1, 2, 3 or 4");
+    if (t->sir_count > 5) return fail(AMBER_E_INVALID, "sir_count must be in 0 .. 5");
     if (t->wealth_form > 2) return fail(AMBER_E_INVALID, "wealth_form must be 0, 1 or 2");
     if (t->sir_tile != 0 && t->sir_tile != 32 && t->sir_tile != 64)
         return fail(AMBER_E_INVALID, "sir_tile must be 0, 32 or 64");

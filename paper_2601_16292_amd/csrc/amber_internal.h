@@ -194,6 +194,8 @@ struct TileParams {
     uint32_t *cursor;          // one word per tile (initial sort)
     uint32_t *ctr;             // overflow allocators: ctr[0] and ctr[64]
     uint32_t *err;             // sticky device error word: bit ERR_TILE_LISTS
+    uint32_t *scnt;            // body launches: susceptible agents per tile after the
+                               // transition (NULL: not counted)
 };
 // Bits of the sticky device error word at ERR_FLAG_OFFSET.
 constexpr uint32_t ERR_BARRIER = 1u;      // a persistent-form barrier wait gave up
@@ -210,6 +212,8 @@ uint32_t sir_tile_cap(uint32_t n, uint32_t nt);
 hipError_t launch_sir_tile_sort(const TileParams &p, hipStream_t st);
 hipError_t launch_sir_tile_step(const TileParams &p, uint32_t t0, uint32_t i, uint32_t n,
                                 uint32_t block, hipStream_t st);
+// dst[0] = a[0] + ... + a[n-1] (one workgroup; dst may be mapped host memory).
+hipError_t launch_sum_words(const uint32_t *a, uint32_t n, uint32_t *dst, hipStream_t st);
 
 // ------------------------------------------------------------------ batches
 // Run tables of the batched launches, passed by value as kernel arguments.

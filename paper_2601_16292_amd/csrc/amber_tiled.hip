@@ -231,7 +231,7 @@ __global__ void __launch_bounds__(1024) k_tile_step(TileParams p, StepIO io, uin
     __shared__ uint32_t wcnt[MOVE ? MAXW * 9 : 1]; // per-wavefront group counts
     __shared__ uint32_t wbase[MOVE ? MAXW * 9 : 1];// per-wavefront group bases
     __shared__ uint32_t c_start[9], c_fix[9], c_ovf[9], c_cnt[9], gtot[9];
-    __shared__ uint32_t s_ovf, s_store;
+    __shared__ uint32_t s_ovf, s_store, s_sus;
     const uint32_t tid = threadIdx.x, NT = blockDim.x;
     const uint32_t lane = tid & 63u, nw = NT >> 6;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wavefront-uniform
@@ -442,6 +442,7 @@ __global__ void __launch_bounds__(1024) k_tile_step(TileParams p, StepIO io, uin
         uint32_t *H = io.hdr_out + (size_t)tile * TILE_HDR;
         H[0] = s_ovf;
         for (int g = 0; g < 9; ++g) H[1 + g] = gtot[g];
+        s_sus = 0;
     }
     __syncthreads();
 
@@ -453,6 +454,7 @@ __global__ void __launch_bounds__(1024) k_tile_step(TileParams p, StepIO io, uin
     const uint32_t hb = uj + 1 == nT ? last : T;   // height of the tile above
     uint32_t *mine = wbase + wave * 9;
     uint32_t stay_run = mine[STAY];
+    uint32_t wsus = 0;                              // susceptible records of this wavefront
     for (uint32_t r0 = 0; r0 < n_in; r0 += round_cap) {
         if (!one) {
             fetch(r0);
@@ -465,11 +467,13 @@ __global__ void __launch_bounds__(1024) k_tile_step(TileParams p, StepIO io, uin
             if (r0 + j * NT + wave * 64 >= n_in) break;
             const bool act = r0 + j * NT + tid < n_in;
             uint32_t g = STAY, pk = 0;
+            bool sus = false;
             if (act) {
                 uint32_t s = (rpk[j] >> 20) & 3u;
                 if (TRANS)
                     s = tile_transition<RW>(p, reg, rid[j], s, rpk[j] & 1023u,
                                             (rpk[j] >> 10) & 1023u, t - 1);
+                sus = s == ST_S;
                 const uint32_t m = rmv[j];
                 const uint32_t cx = m & 1023u, cy = (m >> 10) & 1023u;   // new local + 1
                 g = (m >> 20) & 15u;
@@ -494,9 +498,12 @@ __global__ void __launch_bounds__(1024) k_tile_step(TileParams p, StepIO io, uin
                 other &= ~same;
             }
             if (act && store) out[rec_slot(slot, p.cap, fix, ovf)] = make_uint2(rid[j], pk);
+            if (TRANS) wsus += (uint32_t)__popcll(__ballot(sus));
         }
     }
+    if (TRANS && p.scnt && lane == 0 && wsus) atomicAdd(&s_sus, wsus);
     __syncthreads();
+    if (TRANS && p.scnt && tid == 0) p.scnt[tile] = s_sus;
 
     // counts of step t: interior to the grid (rows by wavefront), ring to the
     // tile's ring array
@@ -691,6 +698,29 @@ hipError_t launch_sir_tile_sort(const TileParams &p, hipStream_t st)
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (nt <= TILE_LDS_BINS) hipLaunchKernelGGL(k_tile_scatter<true>, grid, thr, 0, st, p);
     else hipLaunchKernelGGL(k_tile_scatter<false>, grid, thr, 0, st, p);
+    return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(1024) k_sum_words(const uint32_t *__restrict__ a, uint32_t n,
+                                                   uint32_t *dst)
+{
+    __shared__ uint32_t part[16];
+    const uint32_t tid = threadIdx.x, lane = tid & 63u;
+    uint32_t v = 0;
+    for (uint32_t i = tid; i < n; i += 1024) v += a[i];
+    for (uint32_t off = 32; off; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) part[tid >> 6] = v;
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t s = 0;
+        for (uint32_t k = 0; k < 16; ++k) s += part[k];
+        __hip_atomic_store(dst, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
+
+hipError_t launch_sum_words(const uint32_t *a, uint32_t n, uint32_t *dst, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_sum_words, dim3(1), dim3(1024), 0, st, a, n, dst);
     return hipGetLastError();
 }
 

@@ -342,7 +342,7 @@ def test_block_size_invariance(A, O, model, n, block):
 def test_tuning_validation(A):
     pop = A.Population(A.RANDOM_WALK, 100, L=10)
     for bad in [dict(block=32), dict(block=1088), dict(block=100), dict(sir_form=3),
-                dict(max_groups_per_thread=3), dict(sir_count=5), dict(wealth_form=3),
+                dict(max_groups_per_thread=3), dict(sir_count=6), dict(wealth_form=3),
                 dict(sir_tile=16), dict(sir_tile=48), dict(sir_poll=2)]:
         with pytest.raises(A.AmberError):
             pop.tune(**bad)

@@ -164,3 +164,58 @@ def test_full_sir_1m_tiled(A, golden, tile):
         for k in ("digest", "n_s", "n_i", "n_r", "out_of_bounds"):
             assert inv[k] == want[k], (t, k, inv[k], want[k])
     pop.release()
+
+
+# ------------------------------------------------------------------ tiled, then gather
+# (n, L, beta, gamma, initial infected, chunks, sir_poll)
+SWITCH_CASES = [
+    (40000, 200, (1, 12), (1, 200), 0, [160], 0),          # switch while S > 0
+    (40000, 200, (1, 200), (1, 1000), 38900, [120], 0),     # S small from the start
+    (40000, 200, (1, 12), (1, 200), 0, [50, 110], 0),       # tiled call, then a switch
+    (40000, 200, (1, 12), (1, 200), 0, [160], 1),           # no polls: tiled throughout
+]
+
+
+def expected_tile_bodies(sus, n, chunks, poll):
+    """Tiled body launches and switches the host takes: after body i = 16 q
+    (q >= 2, i + 1 < steps of the call) it reads the susceptible count summed
+    at poll q - 1, which is S after t0 + 16 (q - 1) steps, and ends the tiled
+    part after step i once 20 S <= N."""
+    bodies = switches = t0 = 0
+    for c in chunks:
+        k = c
+        if poll == 0 and c > 32:
+            for q in range(2, c // 16 + 1):
+                if 16 * q + 1 >= c:
+                    break
+                if 20 * sus[t0 + 16 * (q - 1)] <= n:
+                    k = 16 * q + 1
+                    break
+        bodies += k - 1
+        switches += k < c
+        t0 += c
+    return bodies, switches
+
+
+@pytest.mark.parametrize("n,L,beta,gamma,i0,chunks,poll", SWITCH_CASES)
+def test_tiled_then_gather_matches_oracle(A, O, n, L, beta, gamma, i0, chunks, poll):
+    say(f"case tiled-then-gather n={n} L={L} beta={beta} i0={i0} chunks={chunks} poll={poll}")
+    ref = O.OracleRun(O.SIR, n, L, seed=4, stream=9, beta=beta, gamma=gamma, initial_infected=i0)
+    sus = [ref.invariants()["n_s"]]
+    for _ in range(sum(chunks)):
+        ref.step(1)
+        sus.append(ref.invariants()["n_s"])
+    bodies, switches = expected_tile_bodies(sus, n, chunks, poll)
+    if poll == 0:
+        assert switches >= 1
+    pop = A.Population(A.SIR, n, L=L, seed=4, stream_id=9, beta=beta, gamma=gamma,
+                       initial_infected=i0)
+    pop.tune(sir_count=A.COUNT_TILED_GATHER, sir_poll=poll)
+    pop.profile(True)
+    for c in chunks:
+        pop.step(c)
+    times = pop.kernel_times()
+    assert times["sir_tile_body"][0] == bodies, (times, bodies)
+    assert ("sir_body" in times and times["sir_body"][0] > 0) == (switches > 0), times
+    assert_same(pop, ref, sum(chunks))
+    pop.release()
