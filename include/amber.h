@@ -217,8 +217,8 @@ typedef struct {
     uint32_t sir_count;        /* SIR neighbour counts in the pipelined form:
                                   0 = automatic: 1 on grids of at most 16M
                                   cells; on larger grids 5 for calls of 128
-                                  steps or more, else 4 (in batches: 1 for
-                                  such long calls, else 2),
+                                  steps or more, 4 for 16 to 127 steps, else 2
+                                  (in batches: 1 for such long calls, else 2),
                                   1 = sum the 3x3 block of the
                                   count grid per agent, 2 = box-sum the grid once
                                   per step (one stencil kernel) and read one

@@ -654,6 +654,10 @@ SirParams sir_params(amber_pop *p, uint32_t t_base)
 // 2^27 agents: 0.57 s all gather, 1.10 s all tiled).  On smaller grids a
 // long call keeps the gather mode.
 constexpr uint32_t SIR_AUTO_LONG_CALL = 128;
+// A tiled call pays a sort of the columns into records and a scatter back
+// (about 27 ms at 2^27 agents, against 1.8 ms saved per step over the box
+// mode), so on big grids calls of fewer steps stay in the box mode.
+constexpr uint32_t SIR_AUTO_TILED_CALL = 16;
 
 uint32_t sir_auto_count_mode(const amber_pop *p, uint32_t n_steps)
 {
@@ -685,7 +689,7 @@ uint32_t sir_count_mode(const amber_pop *p, uint32_t n_steps)
     if (want == 4 || want == 5) return sir_tile_side(p) ? want : 0u;
     if (want == 1 || want == 2) return want;
     const uint32_t m = sir_auto_count_mode(p, n_steps);
-    if (m == 2) return sir_tile_side(p) ? 4u : 2u;
+    if (m == 2) return sir_tile_side(p) && n_steps >= SIR_AUTO_TILED_CALL ? 4u : 2u;
     if (m == 5) return sir_tile_side(p) ? 5u : 1u;
     return m;
 }

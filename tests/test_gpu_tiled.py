@@ -219,3 +219,24 @@ def test_tiled_then_gather_matches_oracle(A, O, n, L, beta, gamma, i0, chunks, p
     assert ("sir_body" in times and times["sir_body"][0] > 0) == (switches > 0), times
     assert_same(pop, ref, sum(chunks))
     pop.release()
+
+
+def test_automatic_modes_on_a_big_grid(A, O):
+    """Grids above 16M cells: the automatic choice takes the box mode for a
+    call of fewer than 16 steps, the tiled mode up to 127 steps and tiled
+    then gather from 128 steps on; every call must still match the oracle."""
+    n, L, beta, gamma = 30000, 4200, (1, 2), (1, 50)
+    say(f"case automatic big grid n={n} L={L}")
+    pop = A.Population(A.SIR, n, L=L, seed=8, stream_id=1, beta=beta, gamma=gamma)
+    pop.profile(True)
+    ref = O.OracleRun(O.SIR, n, L, seed=8, stream=1, beta=beta, gamma=gamma)
+    done = 0
+    for steps, kernel in ((10, "sir_box"), (40, "sir_tile_body"), (130, "sir_tile_count")):
+        pop.profile(True)                        # zeroes the per-kernel totals
+        pop.step(steps)
+        done += steps
+        times = pop.kernel_times()
+        assert times.get(kernel, (0, 0))[0] > 0, (steps, times)
+        ref.step(steps)
+        assert_same(pop, ref, done)
+    pop.release()
