@@ -85,7 +85,9 @@ def test_many_runs_chunked_into_launches(A, O, count):
                   beta=((15 + 19 * (i % 16)), 1500)) for i in range(53)]
     pops = [make(A, s) for s in specs]
     for i, p in enumerate(pops):
-        p.tune(sir_count=(1 + i % 3) if count == "mixed" else count)
+        # mixed: every count mode, the tiled ones (4, 5) mapped by the batch
+        # to the automatic mode where their tiles fit
+        p.tune(sir_count=(1 + i % 5) if count == "mixed" else count)
     A.step_batch(pops, 17)
     for p, s in zip(pops, specs):
         ref = oracle_run(O, s, 17)
