@@ -407,7 +407,12 @@ __global__ void __launch_bounds__(1024) k_tile_step(TileParams p, StepIO io, uin
     __syncthreads();
 
     if (!MOVE) {
-        // last launch of the call: transition, then back to the columns
+        // last launch of the call: transition, then one 8-byte word per agent,
+        // {x | y << 16, state}, into the free record generation at the agent's
+        // id; k_tile_unpack then splits it into the columns with streaming
+        // stores (three scattered stores per agent would each cost a partial
+        // memory line)
+        uint2 *const packed = io.rec_out;
         for (uint32_t r0 = 0; r0 < n_in; r0 += round_cap) {
             if (r0) fetch(r0);
 #pragma unroll
@@ -422,9 +427,9 @@ __global__ void __launch_bounds__(1024) k_tile_step(TileParams p, StepIO io, uin
                 }
                 uint32_t s = (rpk[j] >> 20) & 3u;
                 if (TRANS) s = tile_transition<RW>(p, reg, rid[j], s, lx, ly, t - 1);
-                p.x[rid[j]] = x0 + (int32_t)lx;
-                p.y[rid[j]] = y0 + (int32_t)ly;
-                p.s[rid[j]] = (uint8_t)s;
+                packed[rid[j]] = make_uint2((uint32_t)(x0 + (int32_t)lx) |
+                                                ((uint32_t)(y0 + (int32_t)ly) << 16),
+                                            s);
             }
         }
         return;
@@ -643,6 +648,34 @@ __global__ void __launch_bounds__(1024) k_tile_scatter(TileParams p)
     }
 }
 
+// Columns from the tail's packed words (agent order): one thread per 4
+// agents; a last partial group writes only its agents below n.  x and y fit
+// 16 bits since L*L < 2^31.
+__global__ void __launch_bounds__(256) k_tile_unpack(const uint2 *__restrict__ packed,
+                                                     int32_t *__restrict__ x,
+                                                     int32_t *__restrict__ y,
+                                                     uint8_t *__restrict__ s, uint32_t n)
+{
+    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t a = 4 * q;
+    if (a >= n) return;
+    if (a + 4 <= n) {
+        const uint4 u0 = ((const uint4 *)packed)[2 * q], u1 = ((const uint4 *)packed)[2 * q + 1];
+        ((int4 *)x)[q] = make_int4((int32_t)(u0.x & 0xffffu), (int32_t)(u0.z & 0xffffu),
+                                   (int32_t)(u1.x & 0xffffu), (int32_t)(u1.z & 0xffffu));
+        ((int4 *)y)[q] = make_int4((int32_t)(u0.x >> 16), (int32_t)(u0.z >> 16),
+                                   (int32_t)(u1.x >> 16), (int32_t)(u1.z >> 16));
+        ((uint32_t *)s)[q] = u0.y | (u0.w << 8) | (u1.y << 16) | (u1.w << 24);
+        return;
+    }
+    for (uint32_t j = 0; a + j < n; ++j) {
+        const uint2 u = packed[a + j];
+        x[a + j] = (int32_t)(u.x & 0xffffu);
+        y[a + j] = (int32_t)(u.x >> 16);
+        s[a + j] = (uint8_t)u.y;
+    }
+}
+
 template <uint32_t T>
 hipError_t step_launch(const TileParams &p, uint32_t t, uint32_t gen, uint32_t phase,
                        uint32_t block, hipStream_t st)
@@ -662,6 +695,11 @@ hipError_t step_launch(const TileParams &p, uint32_t t, uint32_t gen, uint32_t p
     if (phase == 0) hipLaunchKernelGGL((k_tile_step<T, false, true>), grid, thr, 0, st, p, io, t);
     else if (phase == 1) hipLaunchKernelGGL((k_tile_step<T, true, true>), grid, thr, 0, st, p, io, t);
     else hipLaunchKernelGGL((k_tile_step<T, true, false>), grid, thr, 0, st, p, io, t);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || phase != 2) return e;
+    const uint32_t groups = (p.n + 3) / 4;
+    hipLaunchKernelGGL(k_tile_unpack, dim3((groups + 255) / 256), dim3(256), 0, st, io.rec_out,
+                       p.x, p.y, p.s, p.n);
     return hipGetLastError();
 }
 
