@@ -168,8 +168,8 @@ def test_early_stop_of_a_long_call(A, O, poll):
 
 def test_early_stop_in_batches(A, O):
     """Runs that reach the end of their susceptible agents at different steps,
-    stepped together in 90-step calls (polling on; a chunk stops once every
-    run has run its remaining steps): every run equals the oracle."""
+    stepped together in 90-step calls (polling on; a run leaves the later
+    launches once its remaining steps have run): every run equals the oracle."""
     say("case early stop batched")
     specs = [(40000, 200, (1, 3), (1, 80)), (20000, 141, (1, 2), (1, 50)),
              (200, 5, (1, 300), (1, 400)), (30000, 173, (1, 2), (1, 40))]
@@ -189,15 +189,18 @@ def test_early_stop_in_batches(A, O):
         p.release()
 
 
-def test_captured_long_call_matches_eager(A):
-    """A 70-step gather-mode call captured into a graph (no polling while
-    capturing; the launch that finishes the call still runs) and replayed on a
-    fresh state equals the eager call."""
+@pytest.mark.parametrize("count", ["gather", "tiled_gather"])
+def test_captured_long_call_matches_eager(A, count):
+    """A 70-step call captured into a graph and replayed on a fresh state
+    equals the eager call.  No polling while capturing: in the gather mode
+    the launch that finishes the call still runs; the tiled-then-gather mode
+    stays tiled, while its eager call may move to the gather mode."""
     import torch
     n, L, beta, gamma = 40000, 200, (1, 3), (1, 80)
-    say("case captured long call")
+    mode = A.COUNT_GATHER if count == "gather" else A.COUNT_TILED_GATHER
+    say(f"case captured long call, {count}")
     eager = A.Population(A.SIR, n, L=L, seed=3, stream_id=5, beta=beta, gamma=gamma)
-    eager.tune(sir_form=A.SIR_PIPELINED, sir_count=A.COUNT_GATHER)
+    eager.tune(sir_form=A.SIR_PIPELINED, sir_count=mode)
     eager.step(70)
     want = eager.invariants()["digest"]
     eager.release()
@@ -206,7 +209,7 @@ def test_captured_long_call_matches_eager(A):
     with torch.cuda.stream(side):
         pop = A.Population(A.SIR, n, L=L, seed=3, stream_id=5, beta=beta, gamma=gamma,
                            stream=side)
-        pop.tune(sir_form=A.SIR_PIPELINED, sir_count=A.COUNT_GATHER)
+        pop.tune(sir_form=A.SIR_PIPELINED, sir_count=mode)
     side.synchronize()
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g, stream=side):
