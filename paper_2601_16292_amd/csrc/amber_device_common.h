@@ -921,6 +921,43 @@ __device__ __forceinline__ void sir_count_states(const SirParams &p, uint32_t i,
     }
 }
 
+// Coarse demand map that follows fine map m: one byte per 8 x 8 block of
+// cells, marked whenever a cell of the block is.  On grids larger than an
+// L2, an infected agent reads its block's byte (a small map that stays in
+// the L2) and its cell's byte only on a marked block: once few susceptible
+// agents are left, most of the random reads of the big fine map go.
+__device__ __forceinline__ uint8_t *coarse_of(const SirParams &p, const uint8_t *m)
+{
+    const size_t cells = (size_t)(uint32_t)p.L * (uint32_t)p.L;
+    return (uint8_t *)m + ((cells + 255) & ~(size_t)255);
+}
+
+__device__ __forceinline__ uint32_t coarse_quads(const SirParams &p)
+{
+    return (p.cside * p.cside + 15) / 16;
+}
+
+// Marks the coarse blocks of the wrapped 3 x 3 block around (x, y): the
+// blocks of the three columns and three rows (the middle one only when it
+// differs from both ends).
+__device__ __forceinline__ void mark_coarse(uint8_t *__restrict__ c, uint32_t cs, int32_t L,
+                                            int32_t x, int32_t y)
+{
+    if (!on_grid(x, y, L)) return;
+    const uint32_t bx[3] = {(uint32_t)wrap_step(x, -1, L) >> 3, (uint32_t)x >> 3,
+                            (uint32_t)wrap_step(x, 1, L) >> 3};
+    const uint32_t by[3] = {(uint32_t)wrap_step(y, -1, L) >> 3, (uint32_t)y >> 3,
+                            (uint32_t)wrap_step(y, 1, L) >> 3};
+    const bool midx = bx[1] != bx[0] && bx[1] != bx[2], midy = by[1] != by[0] && by[1] != by[2];
+    for (uint32_t j = 0; j < 3; ++j) {
+        if (j == 1 && !midy) continue;
+        for (uint32_t k = 0; k < 3; ++k) {
+            if (k == 1 && !midx) continue;
+            c[by[j] * cs + bx[k]] = 1;
+        }
+    }
+}
+
 // Marks the wrapped 3 x 3 block around (x, y): the cells a susceptible agent
 // at (x, y) reads.
 __device__ __forceinline__ void mark_demand(uint8_t *__restrict__ d, int32_t L, int32_t x, int32_t y)
@@ -949,16 +986,23 @@ __device__ __forceinline__ void sir_bin_mark4(const SirParams &p, uint32_t *__re
     uint4 r = make_uint4(0, 0, 0, 0);
     if (mark) r = philox(q, t + 1, P_MOVE, p.k0, p.k1);     // the moves of step t+1
     const uint32_t u[4] = {r.x, r.y, r.z, r.w};
+    const uint8_t *ccur = p.cside && (mode & 2u) ? coarse_of(p, dcur) : nullptr;
+    uint8_t *cnext = p.cside && (mode & 1u) ? coarse_of(p, dnext) : nullptr;
 #pragma unroll
     for (uint32_t k = 0; k < 4; ++k) {
         const uint32_t st = (S >> (8 * k)) & 0xffu;
         if (a + k >= p.n || !on_grid(xs[k], ys[k], p.L)) continue;
         const uint32_t c = (uint32_t)ys[k] * (uint32_t)p.L + (uint32_t)xs[k];
-        if (st == ST_I && (!(mode & 2u) || dcur[c])) atomicAdd(&count[c], 1u);
+        if (st == ST_I &&
+            (!(mode & 2u) ||
+             ((!ccur || ccur[((uint32_t)ys[k] >> 3) * p.cside + ((uint32_t)xs[k] >> 3)]) &&
+              dcur[c])))
+            atomicAdd(&count[c], 1u);
         if (st == ST_S && (mode & 1u)) {
             int32_t x2 = xs[k], y2 = ys[k];
             moore_move(u[k], p.L, x2, y2);
             mark_demand(dnext, p.L, x2, y2);
+            if (cnext) mark_coarse(cnext, p.cside, p.L, x2, y2);
         }
     }
 }
@@ -1055,6 +1099,7 @@ __device__ __forceinline__ void sir_head_demand(const SirParams &p, uint32_t q, 
                                                 uint32_t t, uint32_t block, uint32_t *s_wc)
 {
     zero_quads((uint32_t *)p.dmap[2], p.dquads, q, threads);
+    if (p.cside) zero_quads((uint32_t *)coarse_of(p, p.dmap[2]), coarse_quads(p), q, threads);
     uint32_t S = 0;
     if (q < p.groups) {
         int4 X = load_nt4(p.x, q);
@@ -1084,6 +1129,8 @@ __device__ __forceinline__ void sir_body_demand(const SirParams &p, uint32_t q, 
     }
     zero_quads(grid_of(p, t + 1), p.quads, q, threads);
     zero_quads((uint32_t *)p.dmap[(i + 2) % 3], p.dquads, q, threads);
+    if (p.cside)
+        zero_quads((uint32_t *)coarse_of(p, p.dmap[(i + 2) % 3]), coarse_quads(p), q, threads);
     uint32_t S2 = 0;
     if (q < p.groups) {
         int4 X = load_nt4(p.x, q);

@@ -232,6 +232,7 @@ struct Resolved {
     // workspace layout (byte offsets)
     uint64_t off_inc0 = 0, off_inc1 = 0, off_table = 0, off_count[3] = {0, 0, 0}, off_sync = 0;
     uint64_t off_nsi = 0, off_dmap[3] = {0, 0, 0};
+    uint32_t cside = 0;                             // coarse demand maps (0 = none)
     uint32_t xbits = 0, xparts = 0;                 // wealth partition exchange (0 = unavailable)
     uint32_t sx_h = 0, sx_P = 0, sx_W = 0;          // SIR exchange count mode (0 = unavailable)
     uint64_t off_sxrec = 0, off_sxtab = 0;
@@ -308,9 +309,12 @@ amber_status_t resolve(const amber_run_desc_t *d, Resolved &r, bool want_table)
             }
             r.off_nsi = ws;
             ws += align_up((uint64_t)NSI_WORDS * 4, 256);
+            // demand maps, each followed by its coarse map (one byte per 8 x 8
+            // cells) on grids larger than an XCD's L2
+            r.cside = (uint64_t)L * L > (4ull << 20) ? (L + 7) / 8 : 0u;
             for (int b = 0; b < 3; ++b) {
                 r.off_dmap[b] = ws;
-                ws += align_up((uint64_t)L * L, 256);
+                ws += align_up((uint64_t)L * L, 256) + align_up((uint64_t)r.cside * r.cside, 256);
             }
             r.off_sync = ws;
             ws += align_up((uint64_t)SYNC_WORDS * 4, 256);
@@ -622,6 +626,7 @@ SirParams sir_params(amber_pop *p, uint32_t t_base)
         sp.count[b] = (uint32_t *)ws_ptr(p, r.off_count[b]);
         sp.dmap[b] = ws_ptr(p, r.off_dmap[b]);
     }
+    sp.cside = r.cside;
     sp.nsi = (uint32_t *)ws_ptr(p, r.off_nsi);
     sp.t_inf = (const uint32_t *)ws_ptr(p, r.off_table);
     sp.table_len = (uint32_t)r.t_inf.size();

@@ -64,6 +64,9 @@ struct SirParams {
     uint32_t *xrec;            // xW segments of 3*1024 cell records
     uint32_t *xtab;            // xtab[w*xP + band] = offset << 16 | count
     uint32_t xh, xP, xW;       // rows per band, bands (>= 3), producer workgroups
+    // side of the coarse demand maps (one byte per 8 x 8 cells, stored after
+    // each fine map at its 256-byte-rounded end), 0 = none
+    uint32_t cside;
 };
 
 // Counts area of the demand-driven binning: for each call-relative step

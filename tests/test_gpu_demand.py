@@ -224,3 +224,29 @@ def test_captured_long_call_matches_eager(A, count):
         assert pop.invariants()["digest"] == want, rep     # reads the replayed buffers
         fresh.release()
     pop.release()
+
+
+@pytest.mark.parametrize("n,L,i0", [(200000, 2100, 100000), (150000, 2051, 90000)])
+def test_coarse_demand_maps_on_big_grids(A, O, n, L, i0):
+    """Grids above 4M cells also keep a coarse demand map (one byte per 8 x 8
+    cells; the last block of each axis is partial here) that an infected agent
+    reads before its cell's byte.  With half the agents infected from the
+    start, the binning is targeted from the fourth launch on; results must
+    still equal the oracle."""
+    beta, gamma, chunks = (1, 2), (1, 50), [40, 30]
+    say(f"case coarse demand maps n={n} L={L} i0={i0}")
+    ref = O.OracleRun(O.SIR, n, L, seed=6, stream=2, beta=beta, gamma=gamma, initial_infected=i0)
+    inv = ref.invariants()
+    assert 3 * inv["n_s"] <= L * L and 10 * inv["n_i"] >= n
+    ref.step(sum(chunks))
+    assert ref.invariants()["n_s"] < n - i0        # some agents were infected
+    pop = A.Population(A.SIR, n, L=L, seed=6, stream_id=2, beta=beta, gamma=gamma,
+                       initial_infected=i0)
+    pop.tune(sir_form=A.SIR_PIPELINED, sir_count=A.COUNT_GATHER)
+    for c in chunks:
+        pop.step(c)
+    got, inv = pop.read(), pop.invariants()
+    pop.release()
+    for g, r in zip(got, ref.columns()):
+        assert np.array_equal(g, r)
+    assert inv["digest"] == ref.digest()
