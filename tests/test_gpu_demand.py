@@ -226,7 +226,9 @@ def test_captured_long_call_matches_eager(A, count):
     pop.release()
 
 
-@pytest.mark.parametrize("n,L,i0", [(200000, 2100, 100000), (150000, 2051, 90000)])
+# L = 2049 = 8 * 256 + 1: the wrapped block of a cell in the last column
+# spans three coarse columns (the last one a single cell wide)
+@pytest.mark.parametrize("n,L,i0", [(200000, 2100, 100000), (150000, 2049, 90000)])
 def test_coarse_demand_maps_on_big_grids(A, O, n, L, i0):
     """Grids above 4M cells also keep a coarse demand map (one byte per 8 x 8
     cells; the last block of each axis is partial here) that an infected agent
