@@ -237,7 +237,7 @@ typedef struct {
                                   5 = tiled, then gather: as 4, and every 16
                                   steps of calls over 32 steps the host reads a
                                   device count of susceptible agents from the
-                                  previous poll; once 20 S <= N it ends the
+                                  previous poll; once 4 S <= N it ends the
                                   tiled part (records back to the columns) and
                                   runs the rest of the call as mode 1 (same
                                   condition and fallback as 4; with sir_poll 1

@@ -800,11 +800,12 @@ amber_status_t enqueue_sir_gather(amber_pop *p, uint32_t t0, uint32_t n_steps)
 }
 
 // Fraction of susceptible agents at or below which a tiled-then-gather call
-// moves to the gather mode: S * SIR_SWITCH_DIV <= N.  With the host's poll
-// lag (one to two polls) the switch lands near S = N / 50, about where a
-// gather-mode step (nine gathers per susceptible agent, demand-driven
-// binning) becomes cheaper than a tiled step (every agent sorted).
-constexpr uint32_t SIR_SWITCH_DIV = 20;
+// moves to the gather mode: S * SIR_SWITCH_DIV <= N, read one poll (16
+// steps) late.  At 2^27 agents the switch then lands where S is near N / 20,
+// about where a gather-mode step (nine gathers per susceptible agent,
+// demand-driven binning on coarse and fine maps) becomes cheaper than a
+// tiled step (every agent sorted).
+constexpr uint32_t SIR_SWITCH_DIV = 4;
 
 // SIR steps t0 .. t0 + n_steps - 1 in the tiled mode: sort, head, bodies,
 // tail, then the two count grids back to zero.  With may_switch the bodies

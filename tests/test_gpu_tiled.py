@@ -180,7 +180,7 @@ def expected_tile_bodies(sus, n, chunks, poll):
     """Tiled body launches and switches the host takes: after body i = 16 q
     (q >= 2, i + 1 < steps of the call) it reads the susceptible count summed
     at poll q - 1, which is S after t0 + 16 (q - 1) steps, and ends the tiled
-    part after step i once 20 S <= N."""
+    part after step i once 4 S <= N."""
     bodies = switches = t0 = 0
     for c in chunks:
         k = c
@@ -188,7 +188,7 @@ def expected_tile_bodies(sus, n, chunks, poll):
             for q in range(2, c // 16 + 1):
                 if 16 * q + 1 >= c:
                     break
-                if 20 * sus[t0 + 16 * (q - 1)] <= n:
+                if 4 * sus[t0 + 16 * (q - 1)] <= n:
                     k = 16 * q + 1
                     break
         bodies += k - 1
