@@ -215,10 +215,12 @@ typedef struct {
     uint32_t max_groups_per_thread; /* persistent form: largest number of 4-agent
                                   groups a thread may hold (1, 2, 4, 8; 0 = 8)    */
     uint32_t sir_count;        /* SIR neighbour counts in the pipelined form:
-                                  0 = automatic: 1 on grids of at most 16M
-                                  cells; on larger grids 5 for calls of 128
-                                  steps or more, 4 for 16 to 127 steps, else 2
-                                  (in batches: 1 for such long calls, else 2),
+                                  0 = automatic: for calls of 128 steps or
+                                  more, 5 on grids of more than 2M cells, else
+                                  1; for shorter calls, 1 on grids of at most
+                                  16M cells, else 4 for 16 to 127 steps and 2
+                                  below (in batches: 1 for long calls, else 1
+                                  or 2 by the same grid rule),
                                   1 = sum the 3x3 block of the
                                   count grid per agent, 2 = box-sum the grid once
                                   per step (one stencil kernel) and read one

@@ -652,23 +652,25 @@ SirParams sir_params(amber_pop *p, uint32_t t_base)
 // gathers.  Beyond it every gathered cell and every binning atomic costs its
 // own memory line: the box mode then (one read per agent instead of nine),
 // and inside a plain call the tiled mode ahead of both (no random access).
-// A call of SIR_AUTO_LONG_CALL steps or more on such a grid starts tiled and
-// moves to the gather mode once few susceptible agents are left: from then
-// on the demand-driven binning and the launch that runs the steps left once
-// none remains make the gather steps the cheaper ones (a 500-step run at
-// 2^27 agents: 0.57 s all gather, 1.10 s all tiled).  On smaller grids a
-// long call keeps the gather mode.
+// A call of SIR_AUTO_LONG_CALL steps or more on a grid of more than
+// SIR_AUTO_SWITCH_CELLS cells starts tiled and moves to the gather mode once
+// few susceptible agents are left: from then on the demand-driven binning
+// and the launch that runs the steps left once none remains make the gather
+// steps the cheaper ones.  500-step runs, all gather against tiled then
+// gather: 2.89 / 3.27 ms at 1e6 agents (L = 1000), 5.70 / 5.56 ms at 2e6,
+// 8.99 / 7.94 ms at 3e6, 53.9 / 38.8 ms at 1.6e7, 0.543 / 0.296 s at 2^27.
 constexpr uint32_t SIR_AUTO_LONG_CALL = 128;
+constexpr uint64_t SIR_AUTO_SWITCH_CELLS = 2ull << 20;
 // A tiled call pays a sort of the columns into records and a scatter back
-// (about 27 ms at 2^27 agents, against 1.8 ms saved per step over the box
+// (about 19 ms at 2^27 agents, against 1.8 ms saved per step over the box
 // mode), so on big grids calls of fewer steps stay in the box mode.
 constexpr uint32_t SIR_AUTO_TILED_CALL = 16;
 
 uint32_t sir_auto_count_mode(const amber_pop *p, uint32_t n_steps)
 {
-    const bool big = (uint64_t)p->r.L * p->r.L > (16ull << 20);
-    if (!big) return 1u;
-    return n_steps >= SIR_AUTO_LONG_CALL ? 5u : 2u;
+    const uint64_t cells = (uint64_t)p->r.L * p->r.L;
+    if (n_steps >= SIR_AUTO_LONG_CALL) return cells > SIR_AUTO_SWITCH_CELLS ? 5u : 1u;
+    return cells > (16ull << 20) ? 2u : 1u;
 }
 
 uint32_t sir_tile_side(const amber_pop *p);
