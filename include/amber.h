@@ -42,8 +42,10 @@
  * amber_last_error() returns a thread-local message for the last failure.
  *
  * Concurrency: calls on one handle are ordered on its stream; a handle must
- * not be used from two threads at once.  Only amber_read_columns and
- * amber_invariants synchronise with the host.
+ * not be used from two threads at once.  Only amber_read_columns,
+ * amber_invariants, amber_profile_* and amber_release synchronise with the
+ * host; amber_step and amber_step_batch wait for the device only when the
+ * caller opts in (sir_poll 2 in amber_tuning_t).
  */
 #ifndef AMBER_H
 #define AMBER_H
@@ -178,21 +180,42 @@ AMBER_API amber_status_t amber_init_population(const amber_run_desc_t *desc,
                                      const amber_buffers_t *bufs,
                                      void *hip_stream, amber_pop_t **out);
 
-/* Enqueue steps t .. t+n_steps-1 of the model on the handle's stream, where t
- * is the handle's step count; on return the step count is t+n_steps.  When
- * the enqueued work completes, the caller's columns hold the state after
- * those steps.  Any split of a run into calls gives bit-identical results. */
+/* One model step composed of full-population, filtered and id-indexed
+ * scatter updates over the columns (Sec. 3.1.1 listings and Sec. 3.3 view
+ * API), applied with synchronous snapshot semantics (Sec. 3.4): every rule
+ * of step t reads the state at the start of step t.  The per-model rules are
+ * those of the benchmark models (Sec. 5.1.2) in the torus-grid restatement
+ * at the top of this header.
+ * Enqueues steps t .. t+n_steps-1 on the handle's stream, where t is the
+ * handle's step count; on return the step count is t+n_steps.  When the
+ * enqueued work completes, the caller's columns hold the state after those
+ * steps.  Any split of a run into calls gives bit-identical results.  With
+ * the default tuning (sir_poll 0) it never waits for the device: it returns
+ * once everything is enqueued.  AMBER_E_STATE for a released handle,
+ * AMBER_E_INVALID when t+n_steps would exceed 2^32-1, AMBER_E_UNSUPPORTED
+ * for a tuning the run does not fit, AMBER_E_DEVICE when a launch fails. */
 AMBER_API amber_status_t amber_step(amber_pop_t *pop, uint32_t n_steps);
 
-/* Enqueue the same n_steps on each of n handles as fused batched launches
- * (one kernel per phase for all runs), ordered on the first handle's stream
- * (the other handles' streams are joined before and after).  Results are
- * bit-identical to calling amber_step on each handle alone.  Handles must be
- * distinct and on one device; models may be mixed. */
+/* Many runs stepped together: the replicates and parameter sweeps of an
+ * experiment (Sec. 4.2), each run still the plain run of its own descriptor
+ * and key.  Enqueues the same n_steps on each of n handles as fused batched
+ * launches (one kernel per phase for many runs), ordered on the first
+ * handle's stream (the other handles' streams are joined before and after).
+ * Results are bit-identical to calling amber_step on each handle alone.
+ * Handles must be distinct and on one device; models may be mixed.  Like
+ * amber_step it only enqueues unless every SIR run of the batch has
+ * sir_poll 2.  Errors as amber_step, and AMBER_E_INVALID for a repeated
+ * handle, AMBER_E_STATE for handles on different devices. */
 AMBER_API amber_status_t amber_step_batch(amber_pop_t *const *pops, uint32_t n, uint32_t n_steps);
 
-/* Copy the columns selected by col_mask (bit c = column c) to host memory:
- * host_dst[c] receives N elements of column c.  Synchronises the stream. */
+/* Read access to the agent-state columns (the column reads of the view API,
+ * Sec. 3.3).  Copies the columns selected by col_mask (bit c =
+ * column c) to host memory: host_dst[c] receives N elements of column c
+ * (int32, or uint8 for the state column), host memory owned by the caller.
+ * Synchronises the stream.  AMBER_E_INVALID for a column the model does not
+ * use, a NULL destination or unknown mask bits (nothing is copied);
+ * AMBER_E_DEVICE when a copy fails or a kernel raised the sticky device
+ * error word since the handle was created. */
 AMBER_API amber_status_t amber_read_columns(amber_pop_t *pop, uint32_t col_mask,
                                   void *const *host_dst);
 
@@ -216,8 +239,8 @@ typedef struct {
                                   groups a thread may hold (1, 2, 4, 8; 0 = 8)    */
     uint32_t sir_count;        /* SIR neighbour counts in the pipelined form:
                                   0 = automatic: for calls of 128 steps or
-                                  more, 5 on grids of more than 2M cells, else
-                                  1; for shorter calls, 1 on grids of at most
+                                  more, 5 on grids of more than 2M cells when
+                                  sir_poll is 2, else 1; for shorter calls, 1 on grids of at most
                                   16M cells, else 4 for 16 to 127 steps and 2
                                   below (in batches: 1 for long calls, else 1
                                   or 2 by the same grid rule),
@@ -243,7 +266,9 @@ typedef struct {
                                   tiled part (records back to the columns) and
                                   runs the rest of the call as mode 1 (same
                                   condition and fallback as 4; with sir_poll 1
-                                  or under graph capture it stays tiled)        */
+                                  or under graph capture it stays tiled, and
+                                  with sir_poll 0 it switches only if the count
+                                  is already there when the host looks)         */
     uint32_t wealth_form;      /* WEALTH above 8192 agents: 0 = automatic,
                                   1 = global atomic scatter-add, 2 = partition
                                   exchange (recipient ids counting-sorted by
@@ -251,20 +276,30 @@ typedef struct {
                                   AMBER_E_UNSUPPORTED above 2^27 agents)         */
     uint32_t sir_tile;         /* tiled count mode: tile side 32 or 64 cells
                                   (0 = automatic)                                 */
-    uint32_t sir_poll;         /* SIR gather mode (sir_count 1), calls of more
-                                  than 32 steps: 0 = early stop on.  Once no
-                                  susceptible agent is left, one launch runs the
-                                  call's remaining steps; amber_step then waits
-                                  on the host every 16 launches until at most 32
-                                  of the call's launches are queued, and stops
-                                  enqueueing once that launch has started.  In
-                                  amber_step_batch a run leaves the later
-                                  launches once its own such launch has started
-                                  (on when every gather-mode run of the batch
-                                  has 0).  Never while the stream is being
-                                  captured into a graph.  Mode 5 polls its
-                                  susceptible count the same way.
-                                  1 = off: never waits; one launch per step.      */
+    uint32_t sir_poll;         /* SIR calls of more than 32 steps in the gather
+                                  mode (sir_count 1) and the tiled-then-gather
+                                  mode (5).  In the gather mode, once no
+                                  susceptible agent is left, one launch runs
+                                  the call's remaining steps and stores the
+                                  call's number in a pinned host word; the
+                                  later launches do nothing.
+                                  0 = read without waiting (default): every 16
+                                  launches the host reads that word and stops
+                                  enqueueing once it is set; mode 5 reads the
+                                  susceptible count of the previous poll only
+                                  if the device has already written it.
+                                  amber_step never waits for the device.
+                                  1 = off: one launch per step, no reads.
+                                  2 = paced (opt-in; blocks): as 0, but every
+                                  16 launches the host first waits until at
+                                  most 32 of the call's launches are queued,
+                                  so the early stop and the switch of mode 5
+                                  take effect at once.  Only with 2 does the
+                                  automatic count mode choose 5.
+                                  In amber_step_batch the same per run (paced
+                                  only when every gather-mode run of the batch
+                                  has 2).  Nothing is read while the stream is
+                                  being captured into a graph.                   */
     uint32_t reserved;
 } amber_tuning_t;
 

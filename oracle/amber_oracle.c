@@ -245,6 +245,14 @@ static uint64_t fmix64(uint64_t z)
     return z ^ (z >> 31);
 }
 
+/* The finaliser alone, exported so that tests can pin it to SplitMix64's
+ * published outputs (the generator's k-th output is the finaliser applied
+ * to k times its increment 0x9E3779B97F4A7C15). */
+uint64_t orc_fmix64(uint64_t z)
+{
+    return fmix64(z);
+}
+
 /* Order-free digest of a population: sum over agents (mod 2^64) of
  * h_a, where h = fmix64(a) and then, for each column value v_j of the row
  * in column order, h = fmix64(h ^ ((j+1) << 32 | v_j)). */

@@ -47,6 +47,8 @@ def lib():
         L.orc_neighbour_infected.restype = ctypes.c_uint64
         L.orc_digest.argtypes = [_u32, _u32, _p, _p]
         L.orc_digest.restype = ctypes.c_uint64
+        L.orc_fmix64.argtypes = [ctypes.c_uint64]
+        L.orc_fmix64.restype = ctypes.c_uint64
         L.orc_invariants.argtypes = [_u32, _u32, _p, _p, _p, _p, _p]
         L.orc_run_wealth.argtypes = [_u32, _i32, _u32, _u32, _u32, _u32, _p, ctypes.c_int]
         L.orc_run_walk.argtypes = [_u32, _u32, _u32, _u32, _u32, _u32, _p, _p, ctypes.c_int]
@@ -118,6 +120,11 @@ def digest(cols):
     ptrs = (ctypes.c_void_p * len(cols))(*[c.ctypes.data for c in cols])
     widths = np.array([c.dtype.itemsize for c in cols], dtype=np.uint32)
     return int(lib().orc_digest(n, len(cols), ptrs, _ptr(widths)))
+
+
+def fmix64(z):
+    """SplitMix64's finaliser, as the digest uses it."""
+    return int(lib().orc_fmix64(z & 0xFFFFFFFFFFFFFFFF))
 
 
 class _Inv(ctypes.Structure):

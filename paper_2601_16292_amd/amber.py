@@ -9,8 +9,10 @@ handle; every step of the path runs in the library's HIP kernels.
 There is no CPU fallback: loading fails loudly when ``libamber.so`` is
 missing.
 """
+import atexit
 import ctypes
 import os
+import weakref
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libamber.so")
@@ -80,6 +82,7 @@ class Tuning(ctypes.Structure):
 SIR_AUTO, SIR_PIPELINED, SIR_PERSISTENT = 0, 1, 2
 COUNT_AUTO, COUNT_GATHER, COUNT_BOX, COUNT_EXCHANGE, COUNT_TILED, COUNT_TILED_GATHER = 0, 1, 2, 3, 4, 5
 WEALTH_AUTO, WEALTH_ATOMIC, WEALTH_EXCHANGE = 0, 1, 2
+POLL_NOWAIT, POLL_OFF, POLL_PACED = 0, 1, 2
 
 
 class KernelTime(ctypes.Structure):
@@ -267,6 +270,20 @@ def footprint_bytes(desc):
     return cols + ws if ws else 0
 
 
+_LIVE = weakref.WeakSet()
+
+
+@atexit.register
+def _release_all():
+    """Release every live handle while the interpreter, torch and the HIP
+    runtime are still whole, rather than from __del__ during teardown."""
+    for pop in list(_LIVE):
+        try:
+            pop.release()
+        except Exception:
+            pass
+
+
 class Population:
     """One run: device buffers (torch tensors on the current device) plus the
     library handle.  ``stream`` is a torch.cuda.Stream (default: current)."""
@@ -299,8 +316,11 @@ class Population:
         b.workspace = self.workspace.data_ptr()
         b.workspace_bytes = self.workspace.numel()
         self.bufs = b
-        st, self.handle = amber_init_population(self.desc, b, self.stream.cuda_stream)
+        self.handle = None
+        st, handle = amber_init_population(self.desc, b, self.stream.cuda_stream)
         check(st)
+        self.handle = handle
+        _LIVE.add(self)
 
     # --- steps
     def step(self, n_steps=1):
@@ -347,9 +367,10 @@ class Population:
         return t
 
     def release(self):
-        if self.handle is not None and self.handle.value:
-            check(amber_release(self.handle))
-        self.handle = None
+        h, self.handle = getattr(self, "handle", None), None
+        _LIVE.discard(self)
+        if h is not None and h.value:
+            check(amber_release(h))
 
     def __del__(self):
         try:

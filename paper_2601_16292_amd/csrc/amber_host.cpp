@@ -496,6 +496,16 @@ hipError_t poll_events(amber_pop *p)
 
 constexpr uint32_t SIR_POLL = 16;      // body launches between early-stop polls
 
+// sir_poll values: how a long SIR call learns what the device has reached.
+// NOWAIT reads the pinned words only when the device has already written
+// them (a plain host load of the early-stop word; hipEventQuery before the
+// susceptible count of the tiled-then-gather mode) and never waits, so
+// amber_step only enqueues.  PACED also waits, every SIR_POLL launches,
+// until at most 2 x SIR_POLL launches are queued, so the early stop and the
+// mode switch take effect at once; amber_step then blocks for most of the
+// call.  OFF reads nothing: one launch per step.
+constexpr uint32_t POLL_NOWAIT = 0, POLL_OFF = 1, POLL_PACED = 2;
+
 // Whether work enqueued on st is being captured into a graph (then the host
 // cannot wait for it, and nothing is polled).
 bool stream_capturing(hipStream_t st)
@@ -510,8 +520,11 @@ bool stream_capturing(hipStream_t st)
 
 
 namespace {
-std::mutex g_live_mu;
-std::unordered_set<const amber_pop *> g_live;
+// The set of live handles and its lock are never destroyed: a handle may be
+// released (or a call validated) from another library's teardown at process
+// exit, after this library's ordinary static objects would be gone.
+std::mutex &g_live_mu = *new std::mutex;
+std::unordered_set<const amber_pop *> &g_live = *new std::unordered_set<const amber_pop *>;
 
 bool is_live(const amber_pop *p)
 {
@@ -669,7 +682,12 @@ constexpr uint32_t SIR_AUTO_TILED_CALL = 16;
 uint32_t sir_auto_count_mode(const amber_pop *p, uint32_t n_steps)
 {
     const uint64_t cells = (uint64_t)p->r.L * p->r.L;
-    if (n_steps >= SIR_AUTO_LONG_CALL) return cells > SIR_AUTO_SWITCH_CELLS ? 5u : 1u;
+    // the switch needs the host to see the susceptible count while the call
+    // is still being enqueued, which only the paced poll guarantees: an
+    // unpaced call is enqueued long before its first poll has run, and
+    // would stay tiled
+    if (n_steps >= SIR_AUTO_LONG_CALL)
+        return cells > SIR_AUTO_SWITCH_CELLS && p->tuning.sir_poll == POLL_PACED ? 5u : 1u;
     return cells > (16ull << 20) ? 2u : 1u;
 }
 
@@ -764,13 +782,15 @@ amber_status_t enqueue_sir_gather(amber_pop *p, uint32_t t0, uint32_t n_steps)
     // Early stop: once no susceptible agent is left, one body launch
     // runs the call's remaining steps and announces it in a pinned
     // word; the later launches would do nothing.  Every SIR_POLL
-    // launches the host waits until at most 2 x SIR_POLL launches are
-    // queued and stops enqueueing once the word holds this call's
-    // number.  Results do not depend on where it stops.
-    const bool poll = tu.sir_poll == 0 && p->stop_host && n_steps > 2 * SIR_POLL &&
-                      !stream_capturing(st);
-    if (poll) {
-        HIP_TRY(poll_events(p), "poll events");
+    // launches the host reads the word (PACED: after waiting until at
+    // most 2 x SIR_POLL launches are queued) and stops enqueueing once
+    // it holds this call's number.  Results do not depend on where it
+    // stops.
+    const bool watch = tu.sir_poll != POLL_OFF && p->stop_host && n_steps > 2 * SIR_POLL &&
+                       !stream_capturing(st);
+    const bool paced = watch && tu.sir_poll == POLL_PACED;
+    if (watch) {
+        if (paced) HIP_TRY(poll_events(p), "poll events");
         if (++p->call_seq == 0) ++p->call_seq;
         sp.stop_word = p->stop_dev;
         sp.stop_seq = p->call_seq;
@@ -782,11 +802,13 @@ amber_status_t enqueue_sir_gather(amber_pop *p, uint32_t t0, uint32_t n_steps)
         HIP_TRY(timed(p, "sir_body",
                       [&] { return launch_sir_body(sp, t0 + i, false, tu, st); }),
                 "sir body kernel");
-        if (!poll || i % SIR_POLL != 0) continue;
-        const uint32_t k = i / SIR_POLL;
-        HIP_TRY(hipEventRecord(p->poll_ev[k & 1], st), "poll event record");
-        if (k < 2) continue;
-        HIP_TRY(hipEventSynchronize(p->poll_ev[(k - 1) & 1]), "poll event synchronize");
+        if (!watch || i % SIR_POLL != 0) continue;
+        if (paced) {
+            const uint32_t k = i / SIR_POLL;
+            HIP_TRY(hipEventRecord(p->poll_ev[k & 1], st), "poll event record");
+            if (k < 2) continue;
+            HIP_TRY(hipEventSynchronize(p->poll_ev[(k - 1) & 1]), "poll event synchronize");
+        }
         if (__atomic_load_n(p->stop_host, __ATOMIC_ACQUIRE) == p->call_seq) {
             last = i;
             break;
@@ -822,8 +844,9 @@ amber_status_t enqueue_sir_tiled(amber_pop *p, uint32_t t0, uint32_t n_steps, bo
 {
     const Resolved &r = p->r;
     hipStream_t st = p->stream;
-    const bool poll = may_switch && p->tuning.sir_poll == 0 && p->stop_host &&
+    const bool poll = may_switch && p->tuning.sir_poll != POLL_OFF && p->stop_host &&
                       n_steps > 2 * SIR_POLL && !stream_capturing(st);
+    const bool paced = p->tuning.sir_poll == POLL_PACED;
     TileParams tp = tile_params(p, sir_tile_side(p));
     if (poll) {
         HIP_TRY(poll_events(p), "poll events");
@@ -847,7 +870,17 @@ amber_status_t enqueue_sir_tiled(amber_pop *p, uint32_t t0, uint32_t n_steps, bo
                 "sir tile count kernel");
         HIP_TRY(hipEventRecord(p->poll_ev[q & 1], st), "poll event record");
         if (q < 2) continue;
-        HIP_TRY(hipEventSynchronize(p->poll_ev[(q - 1) & 1]), "poll event synchronize");
+        if (paced) {
+            HIP_TRY(hipEventSynchronize(p->poll_ev[(q - 1) & 1]), "poll event synchronize");
+        } else {
+            // the previous poll's sum only if the device has already written it
+            const hipError_t e = hipEventQuery(p->poll_ev[(q - 1) & 1]);
+            if (e == hipErrorNotReady) {
+                (void)hipGetLastError();
+                continue;
+            }
+            HIP_TRY(e, "poll event query");
+        }
         const uint32_t sus = __atomic_load_n(p->stop_host + 1 + ((q - 1) & 1), __ATOMIC_ACQUIRE);
         if ((uint64_t)sus * SIR_SWITCH_DIV <= r.n) {
             k = i + 1;
@@ -1058,7 +1091,11 @@ amber_status_t run_sir_gather_batch(amber_pop *lead, const std::vector<amber_pop
     std::vector<SirParams> prm(R);
     std::vector<uint32_t> t0(R), seq(R, 0), i_last(R, n_steps - 1);
     bool poll = n_steps > 2 * SIR_POLL && !stream_capturing(st);
-    for (amber_pop *p : runs) poll = poll && p->stop_host && p->tuning.sir_poll == 0;
+    bool paced = true;
+    for (amber_pop *p : runs) {
+        poll = poll && p->stop_host && p->tuning.sir_poll != POLL_OFF;
+        paced = paced && p->tuning.sir_poll == POLL_PACED;
+    }
     for (uint32_t r = 0; r < R; ++r) {
         amber_pop *p = runs[r];
         prm[r] = sir_params(p, (uint32_t)p->step);
@@ -1103,7 +1140,7 @@ amber_status_t run_sir_gather_batch(amber_pop *lead, const std::vector<amber_pop
         }
         return hipSuccess;
     };
-    if (poll) {
+    if (poll && paced) {
         const hipError_t e = poll_events(runs[0]);
         if (e != hipSuccess) return hip_fail(e, "poll events");
     }
@@ -1114,9 +1151,11 @@ amber_status_t run_sir_gather_batch(amber_pop *lead, const std::vector<amber_pop
         for (uint32_t i = 1; i < n_steps && e == hipSuccess && !active.empty(); ++i) {
             e = launch_packs(packs, 1, i);
             if (e != hipSuccess || !poll || i % SIR_POLL != 0) continue;
-            const uint32_t k = i / SIR_POLL;
-            if ((e = hipEventRecord(ev[k & 1], st)) != hipSuccess || k < 2) continue;
-            if ((e = hipEventSynchronize(ev[(k - 1) & 1])) != hipSuccess) break;
+            if (paced) {
+                const uint32_t k = i / SIR_POLL;
+                if ((e = hipEventRecord(ev[k & 1], st)) != hipSuccess || k < 2) continue;
+                if ((e = hipEventSynchronize(ev[(k - 1) & 1])) != hipSuccess) break;
+            }
             std::vector<uint32_t> still;
             for (uint32_t r : active) {
                 if (__atomic_load_n(runs[r]->stop_host, __ATOMIC_ACQUIRE) == seq[r]) i_last[r] = i;
@@ -1321,6 +1360,7 @@ amber_status_t amber_infection_table(uint32_t beta_num, uint32_t beta_den, uint3
     if (out) std::memcpy(out, t.data(), std::min<size_t>(cap, t.size()) * sizeof(uint32_t));
     return AMBER_OK;
 }
+
 
 amber_status_t amber_init_population(const amber_run_desc_t *desc, const amber_buffers_t *bufs,
                                      void *hip_stream, amber_pop_t **out)
@@ -1538,7 +1578,8 @@ amber_status_t amber_set_tuning(amber_pop_t *pop, const amber_tuning_t *t)
     if (t->wealth_form > 2) return fail(AMBER_E_INVALID, "wealth_form must be 0, 1 or 2");
     if (t->sir_tile != 0 && t->sir_tile != 32 && t->sir_tile != 64)
         return fail(AMBER_E_INVALID, "sir_tile must be 0, 32 or 64");
-    if (t->sir_poll > 1) return fail(AMBER_E_INVALID, "sir_poll must be 0 or 1");
+    if (t->sir_poll != POLL_NOWAIT && t->sir_poll != POLL_OFF && t->sir_poll != POLL_PACED)
+        return fail(AMBER_E_INVALID, "sir_poll must be 0, 1 or 2");
     pop->tuning.sir_tile = t->sir_tile;
     pop->tuning.sir_poll = t->sir_poll;
     pop->tuning.wealth_form = t->wealth_form;

@@ -11,7 +11,9 @@ Continuous batching at step-chunk granularity:
     with them on the device;
   * a run that has finished has its invariants and digest read back (its
     completion time), releases its slot and memory, and queued requests are
-    admitted on the next tick.
+    admitted on the next tick;
+  * a run alone on the device with no request waiting runs all its remaining
+    steps in one amber_step call paced by the host, as a plain run does.
 
 A run's arithmetic never depends on the batch it is in, its slot or its
 admission time: its random stream is keyed by (seed, request id) and every
@@ -97,10 +99,20 @@ def serve(requests, budget_bytes, chunk=50, max_slots=512, time_scale=1.0, torch
                 if wait > 0:
                     time.sleep(min(wait, 0.05))
             continue
-        # one tick: every resident run advances by min(chunk, what it has left)
-        by_len = {}
-        for run in resident:
-            by_len.setdefault(min(chunk, run.left), []).append(run)
+        # one tick: every resident run advances by min(chunk, what it has left);
+        # a run alone on the device with nothing queued behind it runs all its
+        # steps in one call, paced by the host (the early stop and, on big
+        # grids, the tiled-then-gather mode take effect as for a plain run)
+        if len(resident) == 1 and not queue and not (pending and pending[0]["arrival"] <= now()):
+            run = resident[0]
+            run.pop.tune(sir_poll=A.POLL_PACED)
+            run.pop.step(run.left)
+            run.left = 0
+            by_len = {}
+        else:
+            by_len = {}
+            for run in resident:
+                by_len.setdefault(min(chunk, run.left), []).append(run)
         for k, runs in by_len.items():
             A.step_batch([r.pop for r in runs], k)
             for r in runs:

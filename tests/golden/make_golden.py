@@ -9,9 +9,18 @@ GPU path.  Outputs (JSON, in this directory):
                 of agents), grid SIR N=1e6 on 1000x1000 x 500 steps (digest and
                 invariants at several steps);
   sweep.json    the 256-replicate SIR sweep, 300 steps: per-replicate digest
-                and S/I/R counts (slow: run with --sweep, uses a process pool).
+                and S/I/R counts (slow: run with --sweep, uses a process pool);
+  served_sample.json
+                a stratified sample of the 10,000-request served stream: for
+                each model, the first request of each N decile (log-spaced
+                over [1e4, 1e7]) plus the model's heaviest request (largest
+                N x steps); digest and invariants after all its steps
+                (--served, process pool);
+  sir_2p27.json grid SIR at N = 2^27 (L = round(sqrt N) = 11585), beta 1/20,
+                gamma 1/100, key (0, 0), 500 steps: digest and S/I/R at
+                checkpoints (--big; about half an hour on one core).
 
-Usage:  python tests/golden/make_golden.py [--sweep] [--jobs N]
+Usage:  python tests/golden/make_golden.py [--sweep | --served | --big] [--jobs N]
 """
 import argparse
 import json
@@ -91,15 +100,82 @@ def sweep(jobs):
     return dict(steps=runs[0]["steps"], runs=res)
 
 
+SERVED_DECILES = 10
+
+
+def served_sample():
+    """Indices of the stratified sample of the served stream (inputs only)."""
+    reqs = W.served_stream()
+    edges = np.logspace(4, 7, SERVED_DECILES + 1)
+    picked = []
+    for m in range(3):
+        mine = [r for r in reqs if r["model"] == m]
+        for d in range(SERVED_DECILES):
+            lo, hi = edges[d], edges[d + 1]
+            for r in mine:
+                if lo <= r["n"] < hi or (d == SERVED_DECILES - 1 and r["n"] == hi):
+                    picked.append(r["id"])
+                    break
+        heavy = max(mine, key=lambda r: (r["n"] * r["steps"], -r["id"]))
+        if heavy["id"] not in picked:
+            picked.append(heavy["id"])
+    return sorted(picked)
+
+
+def _served_one(req):
+    r = O.OracleRun(req["model"], req["n"], req["L"], seed=req["seed"], stream=req["stream"],
+                    wealth_init=req.get("wealth_init", 1), beta=tuple(req.get("beta", (1, 20))),
+                    gamma=tuple(req.get("gamma", (1, 100)))).step(req["steps"])
+    inv = _inv(r)
+    return dict(id=req["id"], model=req["model"], n=req["n"], steps=req["steps"], **inv)
+
+
+def served(jobs):
+    reqs = W.served_stream()
+    ids = served_sample()
+    todo = sorted((reqs[i] for i in ids), key=lambda r: -r["n"] * r["steps"])
+    with Pool(jobs) as pool:
+        res = pool.map(_served_one, todo, chunksize=1)
+    res.sort(key=lambda d: d["id"])
+    return dict(sample="per model: first request of each N decile (log-spaced over [1e4, 1e7]) "
+                       "and the heaviest request (largest N x steps)", runs=res)
+
+
+BIG_CHECKPOINTS = (0, 1, 10, 50, 100, 150, 200, 300, 400, 500)
+
+
+def big():
+    c = W.SIR_BIG
+    r = O.OracleRun(O.SIR, c["n"], c["L"], seed=c["seed"], stream=c["stream"], beta=c["beta"],
+                    gamma=c["gamma"])
+    marks = {}
+    for t in BIG_CHECKPOINTS:
+        r.step(t - r.t)
+        marks[str(t)] = _inv(r)
+        print("sir 2^27", t, marks[str(t)], flush=True)
+    cfg = {k: list(v) if isinstance(v, tuple) else v for k, v in c.items()}
+    cfg["L"] = r.L
+    cfg["steps"] = BIG_CHECKPOINTS[-1]
+    return dict(config=cfg, checkpoints=marks)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--sweep", action="store_true")
+    ap.add_argument("--served", action="store_true")
+    ap.add_argument("--big", action="store_true")
     ap.add_argument("--jobs", type=int, default=max(1, (os.cpu_count() or 2) - 1))
     args = ap.parse_args()
     t0 = time.time()
     if args.sweep:
         data = sweep(args.jobs)
         path = os.path.join(HERE, "sweep.json")
+    elif args.served:
+        data = served(args.jobs)
+        path = os.path.join(HERE, "served_sample.json")
+    elif args.big:
+        data = big()
+        path = os.path.join(HERE, "sir_2p27.json")
     else:
         data = configs()
         path = os.path.join(HERE, "configs.json")

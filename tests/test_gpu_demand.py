@@ -131,12 +131,13 @@ def test_demand_binning_in_batches(A, O):
         p.release()
 
 
-@pytest.mark.parametrize("poll", [0, 1])
+@pytest.mark.parametrize("poll", [0, 1, 2])
 def test_early_stop_of_a_long_call(A, O, poll):
     """One 200-step call that runs out of susceptible agents near step 40.
-    With polling on, the host stops enqueueing body launches at most 32
-    launches after the one that runs the remaining steps; with it off, every
-    launch is enqueued.  Both equal the oracle."""
+    Paced (2), the host stops enqueueing body launches at most 32 launches
+    after the one that runs the remaining steps; off (1), every launch is
+    enqueued; read-without-waiting (0, the default) stops wherever the host
+    first sees the device's word.  All equal the oracle."""
     n, L, beta, gamma, steps = 40000, 200, (1, 3), (1, 80), 200
     say(f"case early stop poll={poll}")
     ref = O.OracleRun(O.SIR, n, L, seed=11, stream=3, beta=beta, gamma=gamma)
@@ -155,28 +156,33 @@ def test_early_stop_of_a_long_call(A, O, poll):
     body = pop.kernel_times()["sir_body"][0]
     got, inv = pop.read(), pop.invariants()
     pop.release()
-    if poll == 0:
+    if poll == A.POLL_PACED:
         # the launch running the remaining steps is first_none + 3; polls come
         # every 16 launches, waiting for the launch 16 back
         assert body <= first_none + 3 + 2 * 16, body
-    else:
+    elif poll == A.POLL_OFF:
         assert body == steps - 1
+    else:
+        assert first_none + 3 <= body <= steps - 1, body
     for g, r in zip(got, ref.columns()):
         assert np.array_equal(g, r)
     assert inv["digest"] == ref.digest()
 
 
-def test_early_stop_in_batches(A, O):
+@pytest.mark.parametrize("poll", [0, 2])
+def test_early_stop_in_batches(A, O, poll):
     """Runs that reach the end of their susceptible agents at different steps,
-    stepped together in 90-step calls (polling on; a run leaves the later
-    launches once its remaining steps have run): every run equals the oracle."""
-    say("case early stop batched")
+    stepped together in 90-step calls (a run leaves the later launches once
+    its remaining steps have run, as soon as the host sees it): every run
+    equals the oracle, with the host reading without waiting (0) or paced
+    (2)."""
+    say(f"case early stop batched poll={poll}")
     specs = [(40000, 200, (1, 3), (1, 80)), (20000, 141, (1, 2), (1, 50)),
              (200, 5, (1, 300), (1, 400)), (30000, 173, (1, 2), (1, 40))]
     pops = []
     for k, (n, L, beta, gamma) in enumerate(specs):
         p = A.Population(A.SIR, n, L=L, seed=7, stream_id=20 + k, beta=beta, gamma=gamma)
-        p.tune(sir_form=A.SIR_PIPELINED, sir_count=A.COUNT_GATHER)
+        p.tune(sir_form=A.SIR_PIPELINED, sir_count=A.COUNT_GATHER, sir_poll=poll)
         pops.append(p)
     A.step_batch(pops, 90)
     A.step_batch(pops, 40)

@@ -343,7 +343,7 @@ def test_tuning_validation(A):
     pop = A.Population(A.RANDOM_WALK, 100, L=10)
     for bad in [dict(block=32), dict(block=1088), dict(block=100), dict(sir_form=3),
                 dict(max_groups_per_thread=3), dict(sir_count=6), dict(wealth_form=3),
-                dict(sir_tile=16), dict(sir_tile=48), dict(sir_poll=2)]:
+                dict(sir_tile=16), dict(sir_tile=48), dict(sir_poll=3)]:
         with pytest.raises(A.AmberError):
             pop.tune(**bad)
     st, t = A.amber_get_tuning(pop.handle)

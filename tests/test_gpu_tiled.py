@@ -169,10 +169,11 @@ def test_full_sir_1m_tiled(A, golden, tile):
 # ------------------------------------------------------------------ tiled, then gather
 # (n, L, beta, gamma, initial infected, chunks, sir_poll)
 SWITCH_CASES = [
-    (40000, 200, (1, 12), (1, 200), 0, [160], 0),          # switch while S > 0
-    (40000, 200, (1, 200), (1, 1000), 38900, [120], 0),     # S small from the start
-    (40000, 200, (1, 12), (1, 200), 0, [50, 110], 0),       # tiled call, then a switch
+    (40000, 200, (1, 12), (1, 200), 0, [160], 2),          # switch while S > 0
+    (40000, 200, (1, 200), (1, 1000), 38900, [120], 2),     # S small from the start
+    (40000, 200, (1, 12), (1, 200), 0, [50, 110], 2),       # tiled call, then a switch
     (40000, 200, (1, 12), (1, 200), 0, [160], 1),           # no polls: tiled throughout
+    (40000, 200, (1, 12), (1, 200), 0, [50, 110], 0),       # switch only if the count is there
 ]
 
 
@@ -184,7 +185,7 @@ def expected_tile_bodies(sus, n, chunks, poll):
     bodies = switches = t0 = 0
     for c in chunks:
         k = c
-        if poll == 0 and c > 32:
+        if poll == 2 and c > 32:
             for q in range(2, c // 16 + 1):
                 if 16 * q + 1 >= c:
                     break
@@ -206,7 +207,7 @@ def test_tiled_then_gather_matches_oracle(A, O, n, L, beta, gamma, i0, chunks, p
         ref.step(1)
         sus.append(ref.invariants()["n_s"])
     bodies, switches = expected_tile_bodies(sus, n, chunks, poll)
-    if poll == 0:
+    if poll == 2:
         assert switches >= 1
     pop = A.Population(A.SIR, n, L=L, seed=4, stream_id=9, beta=beta, gamma=gamma,
                        initial_infected=i0)
@@ -215,23 +216,33 @@ def test_tiled_then_gather_matches_oracle(A, O, n, L, beta, gamma, i0, chunks, p
     for c in chunks:
         pop.step(c)
     times = pop.kernel_times()
-    assert times["sir_tile_body"][0] == bodies, (times, bodies)
-    assert ("sir_body" in times and times["sir_body"][0] > 0) == (switches > 0), times
+    if poll == 0:
+        # the host switches at a poll whose count the device has already
+        # written, or never: at most the paced run's switches, no fewer bodies
+        paced_bodies, _ = expected_tile_bodies(sus, n, chunks, 2)
+        all_bodies, _ = expected_tile_bodies(sus, n, chunks, 1)
+        assert paced_bodies <= times["sir_tile_body"][0] <= all_bodies, times
+    else:
+        assert times["sir_tile_body"][0] == bodies, (times, bodies)
+        assert ("sir_body" in times and times["sir_body"][0] > 0) == (switches > 0), times
     assert_same(pop, ref, sum(chunks))
     pop.release()
 
 
 def test_automatic_modes_on_a_big_grid(A, O):
     """Grids above 16M cells: the automatic choice takes the box mode for a
-    call of fewer than 16 steps, the tiled mode up to 127 steps and tiled
-    then gather from 128 steps on; every call must still match the oracle."""
+    call of fewer than 16 steps, the tiled mode up to 127 steps and, from 128
+    steps on, the gather mode (tiled then gather when the host may pace the
+    call, sir_poll 2); every call must still match the oracle."""
     n, L, beta, gamma = 30000, 4200, (1, 2), (1, 50)
     say(f"case automatic big grid n={n} L={L}")
     pop = A.Population(A.SIR, n, L=L, seed=8, stream_id=1, beta=beta, gamma=gamma)
     pop.profile(True)
     ref = O.OracleRun(O.SIR, n, L, seed=8, stream=1, beta=beta, gamma=gamma)
     done = 0
-    for steps, kernel in ((10, "sir_box"), (40, "sir_tile_body"), (130, "sir_tile_count")):
+    for steps, kernel, poll in ((10, "sir_box", 0), (40, "sir_tile_body", 0),
+                                (130, "sir_body", 0), (130, "sir_tile_count", 2)):
+        pop.tune(sir_poll=poll)
         pop.profile(True)                        # zeroes the per-kernel totals
         pop.step(steps)
         done += steps

@@ -24,6 +24,13 @@ class FakePop:
     def invariants(self):
         return {"digest": self.req["stream"] * 1000 + self.steps}
 
+    def tune(self, **kw):
+        self.tuning = kw
+
+    def step(self, k):
+        FakePop.log.append(("alone", k))
+        self.steps += k
+
     def release(self):
         FakePop.live -= 1
         FakePop.live_bytes -= self.req["bytes"]
@@ -56,7 +63,17 @@ def test_every_request_completes_with_its_steps(fake):
     got = {r["id"]: r["digest"] for r in out["records"]}
     assert got == {0: 7, 1: 1003, 2: 2012}     # digest encodes id and steps taken
     assert out["agent_steps"] == 1000 * (7 + 3 + 12)
-    assert all(k <= 5 for _, k in fake.log)   # chunks never exceed the chunk size
+    batched = [k for w, k in fake.log if w != "alone"]
+    assert all(k <= 5 for k in batched)       # batched chunks never exceed the chunk size
+    # the last run left alone with nothing queued runs the rest in one call
+    assert fake.log[-1] == ("alone", 12 - 5 - 5)
+
+
+def test_a_lone_run_takes_one_paced_call(fake):
+    rs = reqs([(0.0, 40, 10)])
+    out = serve.serve(rs, budget_bytes=100, chunk=5, time_scale=1000.0)
+    assert fake.log == [("alone", 40)]
+    assert out["records"][0]["digest"] == 40
 
 
 def test_budget_limits_residency_and_keeps_fifo(fake):
