@@ -180,6 +180,30 @@ AMBER_API amber_status_t amber_init_population(const amber_run_desc_t *desc,
                                      const amber_buffers_t *bufs,
                                      void *hip_stream, amber_pop_t **out);
 
+/* Bytes of device scratch behind amber_init_population_noalloc, per GPU. */
+#define AMBER_NOALLOC_SCRATCH_BYTES (32u << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * bulk create as amber_init_population, but the run's workspace is a device
+ * array inside the library (AMBER_NOALLOC_SCRATCH_BYTES per GPU, held until
+ * the process ends) instead of a caller buffer.  The caller still owns the
+ * columns and the stream; bufs->workspace must be NULL and
+ * bufs->workspace_bytes 0.  Neither this call nor any later call on the
+ * handle allocates device or pinned host memory: the handle takes no pinned
+ * early-stop word, so its SIR calls never stop early or switch from the
+ * tiled to the gather mode (results unchanged).  The scratch is shared by
+ * every such handle on the GPU and keeps the last handle's contents; init
+ * rewrites what must start at zero.  At most one handle from this call may
+ * be live per GPU: a second returns AMBER_E_STATE until the first is
+ * released (calls that overlapped on one scratch would race).
+ * AMBER_E_UNSUPPORTED when amber_workspace_bytes(desc) exceeds the scratch
+ * (for instance SIR runs beyond a few hundred thousand agents); other errors
+ * as amber_init_population.  The handle is used and released as any other. */
+AMBER_API amber_status_t amber_init_population_noalloc(const amber_run_desc_t *desc,
+                                                       const amber_buffers_t *bufs,
+                                                       void *hip_stream, amber_pop_t **out);
+
 /* One model step composed of full-population, filtered and id-indexed
  * scatter updates over the columns (Sec. 3.1.1 listings and Sec. 3.3 view
  * API), applied with synchronous snapshot semantics (Sec. 3.4): every rule

@@ -32,7 +32,8 @@ MODEL_COLUMNS = {WEALTH: [COL_WEALTH], RANDOM_WALK: [COL_X, COL_Y],
                  SIR: [COL_X, COL_Y, COL_STATE]}
 
 EXPORTED = ["amber_abi_version", "amber_column_bytes", "amber_workspace_bytes",
-            "amber_infection_table", "amber_init_population", "amber_step",
+            "amber_infection_table", "amber_init_population",
+            "amber_init_population_noalloc", "amber_step",
             "amber_step_batch", "amber_read_columns", "amber_invariants",
             "amber_pop_info", "amber_set_tuning", "amber_get_tuning",
             "amber_profile_enable", "amber_profile_read",
@@ -126,6 +127,10 @@ def lib():
         L.amber_init_population.restype = ctypes.c_int
         L.amber_init_population.argtypes = [ctypes.POINTER(RunDesc), ctypes.POINTER(Buffers),
                                             P, ctypes.POINTER(P)]
+        L.amber_init_population_noalloc.restype = ctypes.c_int
+        L.amber_init_population_noalloc.argtypes = [ctypes.POINTER(RunDesc),
+                                                    ctypes.POINTER(Buffers), P,
+                                                    ctypes.POINTER(P)]
         L.amber_step.restype = ctypes.c_int
         L.amber_step.argtypes = [P, ctypes.c_uint32]
         L.amber_step_batch.restype = ctypes.c_int
@@ -193,6 +198,17 @@ def amber_init_population(desc, bufs, stream_ptr):
     st = lib().amber_init_population(ctypes.byref(desc), ctypes.byref(bufs),
                                      ctypes.c_void_p(stream_ptr), ctypes.byref(h))
     return st, h
+
+
+def amber_init_population_noalloc(desc, bufs, stream_ptr):
+    """Returns (status, handle); bufs must carry no workspace."""
+    h = ctypes.c_void_p()
+    st = lib().amber_init_population_noalloc(ctypes.byref(desc), ctypes.byref(bufs),
+                                             ctypes.c_void_p(stream_ptr), ctypes.byref(h))
+    return st, h
+
+
+NOALLOC_SCRATCH_BYTES = 32 << 20
 
 
 def amber_step(handle, n_steps):
@@ -290,7 +306,7 @@ class Population:
 
     def __init__(self, model, n, L=0, seed=0, stream_id=0, wealth_init=1, beta=(1, 20),
                  gamma=(1, 100), initial_infected=0, stream=None, device=None,
-                 buffers=None):
+                 buffers=None, noalloc=False):
         import torch
         self.desc = make_desc(model, n, L, seed, stream_id, wealth_init, beta, gamma,
                               initial_infected)
@@ -310,14 +326,20 @@ class Population:
                 t = torch.empty(nb // (1 if c == COL_STATE else 4), dtype=dtype, device=dev)
             self.cols[c] = t
             b.col[c] = t.data_ptr()
-        self.workspace = (buffers or {}).get("workspace")
-        if self.workspace is None:
-            self.workspace = torch.empty(ws, dtype=torch.uint8, device=dev)
-        b.workspace = self.workspace.data_ptr()
-        b.workspace_bytes = self.workspace.numel()
+        if noalloc:
+            # the library's device scratch is the workspace
+            self.workspace = None
+            b.workspace, b.workspace_bytes = None, 0
+        else:
+            self.workspace = (buffers or {}).get("workspace")
+            if self.workspace is None:
+                self.workspace = torch.empty(ws, dtype=torch.uint8, device=dev)
+            b.workspace = self.workspace.data_ptr()
+            b.workspace_bytes = self.workspace.numel()
         self.bufs = b
         self.handle = None
-        st, handle = amber_init_population(self.desc, b, self.stream.cuda_stream)
+        init = amber_init_population_noalloc if noalloc else amber_init_population
+        st, handle = init(self.desc, b, self.stream.cuda_stream)
         check(st)
         self.handle = handle
         _LIVE.add(self)

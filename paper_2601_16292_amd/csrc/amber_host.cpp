@@ -433,6 +433,7 @@ struct amber_pop {
     uint32_t *stop_host = nullptr, *stop_dev = nullptr;
     uint32_t call_seq = 0;
     hipEvent_t poll_ev[2] = {nullptr, nullptr};
+    bool scratch = false;              // workspace is the device's no-allocation scratch
     ~amber_pop();
 };
 
@@ -1330,6 +1331,140 @@ amber_status_t run_batch(amber_pop *const *pops, uint32_t n, uint32_t n_steps)
 
 // ------------------------------------------------------------------ ABI
 
+static_assert(NOALLOC_SCRATCH_BYTES == AMBER_NOALLOC_SCRATCH_BYTES,
+              "the scratch size in the header and in the library agree");
+
+namespace {
+// Devices whose no-allocation scratch is held by a live handle.
+bool g_scratch_held[NOALLOC_MAX_DEVICES] = {};
+
+// amber_init_population, and its no-allocation variant: with noalloc the
+// workspace is the device's scratch array instead of bufs->workspace, the
+// handle takes no pinned early-stop word (the SIR early stop and the
+// tiled-then-gather switch are then off, results unchanged), and at most one
+// such handle per device may be live.
+amber_status_t init_population(const amber_run_desc_t *desc, const amber_buffers_t *bufs,
+                               void *hip_stream, amber_pop_t **out, bool noalloc)
+{
+    if (!out) return fail(AMBER_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!bufs) return fail(AMBER_E_INVALID, "buffers are NULL");
+    Resolved r;
+    amber_status_t st = resolve(desc, r, true);
+    if (st != AMBER_OK) return st;
+    static const char *names[AMBER_NUM_COLS] = {"wealth column", "x column", "y column",
+                                                "state column"};
+    for (int c = 0; c < AMBER_NUM_COLS; ++c)
+        if (column_bytes(r, (amber_col_t)c) != 0 && !bufs->col[c])
+            return fail(AMBER_E_INVALID, "%s is NULL", names[c]);
+    amber_buffers_t b = *bufs;
+    if (noalloc) {
+        if (b.workspace || b.workspace_bytes)
+            return fail(AMBER_E_INVALID, "the no-allocation call takes no workspace (it must be "
+                                         "NULL with 0 bytes)");
+        if (r.ws_bytes > NOALLOC_SCRATCH_BYTES)
+            return fail(AMBER_E_UNSUPPORTED,
+                        "the run needs %llu bytes of workspace, above the %llu-byte device "
+                        "scratch of the no-allocation call",
+                        (unsigned long long)r.ws_bytes,
+                        (unsigned long long)NOALLOC_SCRATCH_BYTES);
+    } else {
+        if (!b.workspace) return fail(AMBER_E_INVALID, "workspace is NULL");
+        if (b.workspace_bytes < r.ws_bytes)
+            return fail(AMBER_E_NOMEM, "workspace has %zu bytes, the run needs %llu",
+                        b.workspace_bytes, (unsigned long long)r.ws_bytes);
+    }
+    int device = 0;
+    HIP_TRY(hipGetDevice(&device), "hipGetDevice");
+    for (int c = 0; c < AMBER_NUM_COLS; ++c) {
+        if (column_bytes(r, (amber_col_t)c) == 0) continue;
+        st = check_device_ptr(b.col[c], device, names[c], column_bytes(r, (amber_col_t)c));
+        if (st != AMBER_OK) return st;
+    }
+    if (noalloc) {
+        if (device < 0 || device >= (int)NOALLOC_MAX_DEVICES)
+            return fail(AMBER_E_UNSUPPORTED, "device %d is beyond the no-allocation scratch's "
+                                             "%u devices", device, NOALLOC_MAX_DEVICES);
+        void *scr = nullptr;
+        HIP_TRY(noalloc_scratch(device, &scr), "scratch symbol address");
+        b.workspace = scr;
+        b.workspace_bytes = NOALLOC_SCRATCH_BYTES;
+    } else {
+        st = check_device_ptr(b.workspace, device, "workspace", r.ws_bytes);
+        if (st != AMBER_OK) return st;
+    }
+    if (((uintptr_t)b.workspace & 255u) != 0)
+        return fail(AMBER_E_INVALID, "workspace is not 256-byte aligned");
+    if (noalloc) {
+        std::lock_guard<std::mutex> lk(g_live_mu);
+        if (g_scratch_held[device])
+            return fail(AMBER_E_STATE, "the no-allocation scratch of device %d is held by a live "
+                                       "handle (release it first)", device);
+        g_scratch_held[device] = true;
+    }
+    auto unhold = [&] {
+        if (!noalloc) return;
+        std::lock_guard<std::mutex> lk(g_live_mu);
+        g_scratch_held[device] = false;
+    };
+
+    amber_pop *p = new (std::nothrow) amber_pop;
+    if (!p) {
+        unhold();
+        return fail(AMBER_E_NOMEM, "host allocation of the handle failed");
+    }
+    p->r = std::move(r);
+    p->b = b;
+    p->stream = (hipStream_t)hip_stream;
+    p->device = device;
+    p->scratch = noalloc;
+    p->acc = (DevInvariants *)p->b.workspace;
+    const Resolved &rr = p->r;
+
+    auto bail = [&](amber_status_t s) {
+        delete p;
+        unhold();
+        return s;
+    };
+    // header: invariants result and the sticky device error word
+    hipError_t e = launch_zero_words((uint32_t *)p->b.workspace, 64, p->stream);
+    if (e != hipSuccess) return bail(hip_fail(e, "workspace clear"));
+    if (rr.model == AMBER_WEALTH) {
+        e = launch_init_wealth(col_i32(p, AMBER_COL_WEALTH), (int32_t *)ws_ptr(p, rr.off_inc0),
+                               (int32_t *)ws_ptr(p, rr.off_inc1), rr.n, rr.w_init, p->stream);
+    } else {
+        e = launch_init_positions(col_i32(p, AMBER_COL_X), col_i32(p, AMBER_COL_Y), rr.n,
+                                  (int32_t)rr.L, rr.seed, rr.stream, p->stream);
+        if (e == hipSuccess && rr.model == AMBER_SIR) {
+            e = launch_init_states((uint8_t *)p->b.col[AMBER_COL_STATE], rr.n, rr.i0, p->stream);
+            const uint64_t cell_words = (rr.off_count[1] - rr.off_count[0]) / 4;
+            if (e == hipSuccess)
+                e = launch_zero_words((uint32_t *)ws_ptr(p, rr.off_count[0]), 3 * cell_words,
+                                      p->stream);
+            if (e == hipSuccess)     // the demand-binning counts start at zero
+                e = launch_zero_words((uint32_t *)ws_ptr(p, rr.off_nsi),
+                                      (rr.off_dmap[0] - rr.off_nsi) / 4, p->stream);
+            if (e == hipSuccess)
+                p->persist_g = sir_persistent_groups_per_thread(rr.n, 8, &p->persist_blocks);
+            if (e == hipSuccess && !noalloc) e = stop_words().take(&p->stop_host, &p->stop_dev);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(ws_ptr(p, rr.off_table), rr.t_inf.data(),
+                                   rr.t_inf.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
+                                   p->stream);
+            // the table's host copy lives in the handle, which outlives the
+            // upload (amber_release waits for the stream)
+        }
+    }
+    if (e != hipSuccess) return bail(hip_fail(e, "init kernels"));
+    {
+        std::lock_guard<std::mutex> lk(g_live_mu);
+        g_live.insert(p);
+    }
+    *out = p;
+    return AMBER_OK;
+}
+}  // namespace
+
 extern "C" {
 
 uint32_t amber_abi_version(void) { return AMBER_ABI_VERSION; }
@@ -1365,82 +1500,14 @@ amber_status_t amber_infection_table(uint32_t beta_num, uint32_t beta_den, uint3
 amber_status_t amber_init_population(const amber_run_desc_t *desc, const amber_buffers_t *bufs,
                                      void *hip_stream, amber_pop_t **out)
 {
-    if (!out) return fail(AMBER_E_INVALID, "out is NULL");
-    *out = nullptr;
-    if (!bufs) return fail(AMBER_E_INVALID, "buffers are NULL");
-    Resolved r;
-    amber_status_t st = resolve(desc, r, true);
-    if (st != AMBER_OK) return st;
-    static const char *names[AMBER_NUM_COLS] = {"wealth column", "x column", "y column",
-                                                "state column"};
-    for (int c = 0; c < AMBER_NUM_COLS; ++c)
-        if (column_bytes(r, (amber_col_t)c) != 0 && !bufs->col[c])
-            return fail(AMBER_E_INVALID, "%s is NULL", names[c]);
-    if (!bufs->workspace) return fail(AMBER_E_INVALID, "workspace is NULL");
-    if (bufs->workspace_bytes < r.ws_bytes)
-        return fail(AMBER_E_NOMEM, "workspace has %zu bytes, the run needs %llu",
-                    bufs->workspace_bytes, (unsigned long long)r.ws_bytes);
-    int device = 0;
-    HIP_TRY(hipGetDevice(&device), "hipGetDevice");
-    for (int c = 0; c < AMBER_NUM_COLS; ++c) {
-        if (column_bytes(r, (amber_col_t)c) == 0) continue;
-        st = check_device_ptr(bufs->col[c], device, names[c], column_bytes(r, (amber_col_t)c));
-        if (st != AMBER_OK) return st;
-    }
-    st = check_device_ptr(bufs->workspace, device, "workspace", r.ws_bytes);
-    if (st != AMBER_OK) return st;
-    if (((uintptr_t)bufs->workspace & 255u) != 0)
-        return fail(AMBER_E_INVALID, "workspace is not 256-byte aligned");
+    return init_population(desc, bufs, hip_stream, out, false);
+}
 
-    amber_pop *p = new (std::nothrow) amber_pop;
-    if (!p) return fail(AMBER_E_NOMEM, "host allocation of the handle failed");
-    p->r = std::move(r);
-    p->b = *bufs;
-    p->stream = (hipStream_t)hip_stream;
-    p->device = device;
-    p->acc = (DevInvariants *)p->b.workspace;
-    const Resolved &rr = p->r;
-
-    auto bail = [&](amber_status_t s) {
-        delete p;
-        return s;
-    };
-    // header: invariants result and the sticky device error word
-    hipError_t e = launch_zero_words((uint32_t *)p->b.workspace, 64, p->stream);
-    if (e != hipSuccess) return bail(hip_fail(e, "workspace clear"));
-    if (rr.model == AMBER_WEALTH) {
-        e = launch_init_wealth(col_i32(p, AMBER_COL_WEALTH), (int32_t *)ws_ptr(p, rr.off_inc0),
-                               (int32_t *)ws_ptr(p, rr.off_inc1), rr.n, rr.w_init, p->stream);
-    } else {
-        e = launch_init_positions(col_i32(p, AMBER_COL_X), col_i32(p, AMBER_COL_Y), rr.n,
-                                  (int32_t)rr.L, rr.seed, rr.stream, p->stream);
-        if (e == hipSuccess && rr.model == AMBER_SIR) {
-            e = launch_init_states((uint8_t *)p->b.col[AMBER_COL_STATE], rr.n, rr.i0, p->stream);
-            const uint64_t cell_words = (rr.off_count[1] - rr.off_count[0]) / 4;
-            if (e == hipSuccess)
-                e = launch_zero_words((uint32_t *)ws_ptr(p, rr.off_count[0]), 3 * cell_words,
-                                      p->stream);
-            if (e == hipSuccess)     // the demand-binning counts start at zero
-                e = launch_zero_words((uint32_t *)ws_ptr(p, rr.off_nsi),
-                                      (rr.off_dmap[0] - rr.off_nsi) / 4, p->stream);
-            if (e == hipSuccess)
-                p->persist_g = sir_persistent_groups_per_thread(rr.n, 8, &p->persist_blocks);
-            if (e == hipSuccess) e = stop_words().take(&p->stop_host, &p->stop_dev);
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(ws_ptr(p, rr.off_table), rr.t_inf.data(),
-                                   rr.t_inf.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
-                                   p->stream);
-            // the table's host copy lives in the handle, which outlives the
-            // upload (amber_release waits for the stream)
-        }
-    }
-    if (e != hipSuccess) return bail(hip_fail(e, "init kernels"));
-    {
-        std::lock_guard<std::mutex> lk(g_live_mu);
-        g_live.insert(p);
-    }
-    *out = p;
-    return AMBER_OK;
+amber_status_t amber_init_population_noalloc(const amber_run_desc_t *desc,
+                                             const amber_buffers_t *bufs, void *hip_stream,
+                                             amber_pop_t **out)
+{
+    return init_population(desc, bufs, hip_stream, out, true);
 }
 
 amber_status_t amber_step(amber_pop_t *pop, uint32_t n_steps)
@@ -1657,6 +1724,11 @@ amber_status_t amber_release(amber_pop_t *pop)
         g_live.erase(pop);
     }
     hipError_t e = hipStreamSynchronize(pop->stream);
+    if (pop->scratch) {
+        // the scratch is free for the next handle once this one's work is done
+        std::lock_guard<std::mutex> lk(g_live_mu);
+        g_scratch_held[pop->device] = false;
+    }
     delete pop;
     if (e != hipSuccess) return hip_fail(e, "stream synchronize");
     return AMBER_OK;

@@ -110,6 +110,13 @@ hipError_t launch_init_positions(int32_t *x, int32_t *y, uint32_t n, int32_t L,
 hipError_t launch_init_states(uint8_t *s, uint32_t n, uint32_t i0, hipStream_t st);
 hipError_t launch_zero_words(uint32_t *p, uint64_t words, hipStream_t st);
 
+// Device workspace of the no-allocation handles: a file-scope device array
+// of NOALLOC_SCRATCH_BYTES per GPU.  noalloc_scratch returns its address on
+// `device`, which must be the current device (looked up once per device).
+constexpr uint64_t NOALLOC_SCRATCH_BYTES = 32ull << 20;
+constexpr uint32_t NOALLOC_MAX_DEVICES = 64;
+hipError_t noalloc_scratch(int device, void **ptr);
+
 // Random walk: steps t0 .. t0+n_steps-1 with positions held in registers.
 hipError_t launch_walk(int32_t *x, int32_t *y, uint32_t n, int32_t L, uint32_t k0,
                        uint32_t k1, uint32_t t0, uint32_t n_steps, const Tuning &tu,

@@ -97,6 +97,23 @@ def test_init_rejects_missing_buffers_before_touching_the_device():
     assert st == A.E_NOMEM and "workspace" in A.amber_last_error()
 
 
+def test_noalloc_init_checks_before_touching_the_device():
+    # takes no workspace, and refuses runs whose workspace exceeds its scratch
+    d = A.make_desc(A.RANDOM_WALK, 100, 10)
+    b = A.Buffers()
+    b.col[A.COL_X], b.col[A.COL_Y] = 0x1000, 0x2000
+    b.workspace, b.workspace_bytes = 0x100000, 1 << 20
+    st, _ = A.amber_init_population_noalloc(d, b, 0)
+    assert st == A.E_INVALID and "workspace" in A.amber_last_error()
+    big = A.make_desc(A.SIR, 2_000_000)
+    assert A.amber_workspace_bytes(big) > A.NOALLOC_SCRATCH_BYTES
+    b = A.Buffers()
+    for c in (A.COL_X, A.COL_Y, A.COL_STATE):
+        b.col[c] = 0x1000
+    st, _ = A.amber_init_population_noalloc(big, b, 0)
+    assert st == A.E_UNSUPPORTED and "scratch" in A.amber_last_error()
+
+
 def test_handle_misuse_is_reported():
     import ctypes
     bogus = ctypes.c_void_p(0xdeadbeef)
