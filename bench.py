@@ -33,7 +33,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, vendor figure
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2601_16292_amd", "csrc", f)
-                  for f in ("amber_device.hip", "amber_device_common.h")]
+                  for f in ("amber_device.hip", "amber_device_common.h", "amber_tiled.hip")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.json")
 BIG_GOLDEN = os.path.join(ROOT, "tests", "golden", "sir_2p27.json")
 
@@ -139,29 +139,27 @@ def roofline_for(times, bytes_per_kernel_total, traffic, extra=None):
            "algorithmic_bytes_per_launch": int(bytes_per_launch)}
     if extra and name in extra:
         out.update(extra[name])
-    if traffic and traffic.get("kernel") == name:
+    if traffic and name in traffic:
         # the number of launches of a call can vary (the host stops enqueueing
         # once one launch has run the call's remaining steps): bytes of the
         # whole call over this run's launches
-        if "bytes_per_call" in traffic:
-            out["traffic"] = int(traffic["bytes_per_call"] / launches)
-        else:
-            out["traffic"] = traffic.get("bytes_per_launch")
+        out["traffic"] = int(traffic[name]["bytes_per_call"] / launches)
+        out["traffic_launches_in_counter_run"] = traffic[name]["launches_per_call"]
     return out
 
 
-def load_traffic():
-    """HBM traffic of the headline call from the committed rocprofv3 counter
-    summary, valid only if the kernel source has not changed since it was
-    taken."""
+def load_traffic(tuning):
+    """HBM traffic per kernel of one headline call under `tuning`, from the
+    committed rocprofv3 counter summary: {kernel: entry}, empty when no entry
+    was taken with this tuning or the kernel sources changed since."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
-        return None
+        return {}
     if t.get("source_sha") != kernel_source_sha():
-        return None
-    return t
+        return {}
+    return {e["kernel"]: e for e in t.get("entries", []) if e.get("tuning") == tuning}
 
 
 # ------------------------------------------------------------------ timing helpers
@@ -621,7 +619,7 @@ def main():
         f"kernels {times}")
 
     priced, pextra = price_sir_run(n, L, counts, times, T)
-    roof = roofline_for(times, priced, load_traffic(), pextra)
+    roof = roofline_for(times, priced, load_traffic(tuning), pextra)
     if roof is not None:
         run_bytes = sum(sir_step_bytes(n, L, i, s) for s, i in counts)
         roof["run_algorithmic_GBs"] = round(run_bytes * args.steps / secs / 1e9, 1)

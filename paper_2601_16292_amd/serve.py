@@ -125,7 +125,7 @@ def serve(requests, budget_bytes, chunk=50, max_slots=512, time_scale=1.0, torch
                 done = now()
                 req = run.req
                 records.append(dict(id=req["stream"], model=req["model"], n=req["n"],
-                                    steps=req["steps"], digest=inv["digest"],
+                                    steps=req["steps"], digest=inv["digest"], invariants=inv,
                                     latency_s=(done - req["arrival"]) / time_scale,
                                     wait_s=(run.admitted - req["arrival"]) / time_scale))
                 work += req["n"] * req["steps"]
@@ -160,7 +160,8 @@ def serve_plain(requests, time_scale=1.0, log=None):
         done = now()
         pop.release()
         records.append(dict(id=req["stream"], model=req["model"], n=req["n"], steps=req["steps"],
-                            digest=inv["digest"], latency_s=(done - req["arrival"]) / time_scale,
+                            digest=inv["digest"], invariants=inv,
+                            latency_s=(done - req["arrival"]) / time_scale,
                             wait_s=(start - req["arrival"]) / time_scale))
         work += req["n"] * req["steps"]
         if log and i % 200 == 0:

@@ -54,7 +54,8 @@ def test_gather_body_bytes_per_call(bench):
 def test_traffic_per_call_over_this_runs_launches(bench):
     times = {"sir_body": (100, 2.0)}                  # launches, total ms
     priced = {"sir_body": 2_000_000_000}
-    traffic = {"kernel": "sir_body", "bytes_per_call": 3_000_000_000, "bytes_per_launch": 1}
+    traffic = {"sir_body": {"kernel": "sir_body", "bytes_per_call": 3_000_000_000,
+                            "launches_per_call": 90}}
     roof = bench.roofline_for(times, priced, traffic)
     assert roof["kernel"] == "sir_body"
     assert roof["traffic"] == 30_000_000
