@@ -12,7 +12,13 @@ Modules:
   brute      -- pure-Python brute force for tiny populations (its own
                 Philox, O(N^2) neighbour search), used to pin the C oracle.
 
+The oracle also holds the view primitives of Sec. 3.3 (full and filtered
+updates, id-indexed scatter-add on int32 / float32 columns) and resuming a
+run from host columns.
+
 Parity status: every function is pinned by the ``-m "not gpu"`` tests
-(rocRAND's Philox engine, mpmath/Decimal thresholds, numpy's ``add.at``,
-brute force, closed forms and invariants).  Nothing here is "parity unpinned".
+(rocRAND's Philox engine, mpmath/Decimal thresholds, numpy's ``add.at`` and
+int32 arithmetic, mpmath's exact fused multiply-add, SplitMix64's published
+outputs, invariants on planted bad rows, brute force, closed forms).
+Nothing here is "parity unpinned".
 """

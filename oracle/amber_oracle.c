@@ -31,6 +31,7 @@
  * Random Numbers: As Easy as 1, 2, 3", SC'11), keyed (seed, stream), with
  * counter (floor(g/4), t, purpose, 0) and word g mod 4, g = a*W + j.
  */
+#include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -306,6 +307,102 @@ void orc_invariants(uint32_t n, uint32_t L, const int32_t *w, const int32_t *x,
         out->out_of_bounds += bad;
     }
     if (!w) out->wealth_min = 0;
+}
+
+/* ------------------------------------------------------ view primitives */
+
+/* The three views of Sec. 3.3 on one typed column of n rows, written as the
+ * plain definitions (Sec. 3.1.1 listings):
+ *   full view      every row:            v <- a*v + b
+ *   filtered view  rows where p CMP thr: v <- a*v + b, the predicate read on
+ *                  the column values before the update (snapshot)
+ *   scatter view   for j = 0..m-1 in list order: col[ids[j]] += vals[j]
+ *                  (duplicates accumulate, as numpy's add.at does); ids
+ *                  outside [0, n) are skipped.
+ * int32 arithmetic wraps modulo 2^32; float32 updates are the fused
+ * multiply-add a*v + b with one rounding to nearest, and float32 scatter
+ * adds round after every addition, in list order. */
+
+enum { ORC_LT = 0, ORC_LE = 1, ORC_EQ = 2, ORC_NE = 3, ORC_GE = 4, ORC_GT = 5 };
+
+static int cmp_i32(int32_t v, int cmp, int32_t thr)
+{
+    switch (cmp) {
+    case ORC_LT: return v < thr;
+    case ORC_LE: return v <= thr;
+    case ORC_EQ: return v == thr;
+    case ORC_NE: return v != thr;
+    case ORC_GE: return v >= thr;
+    case ORC_GT: return v > thr;
+    }
+    return 0;
+}
+
+static int cmp_f32(float v, int cmp, float thr)
+{
+    switch (cmp) {
+    case ORC_LT: return v < thr;
+    case ORC_LE: return v <= thr;
+    case ORC_EQ: return v == thr;
+    case ORC_NE: return v != thr;
+    case ORC_GE: return v >= thr;
+    case ORC_GT: return v > thr;
+    }
+    return 0;
+}
+
+static int32_t affine_i32(int32_t v, int32_t a, int32_t b)
+{
+    return (int32_t)((uint32_t)a * (uint32_t)v + (uint32_t)b);
+}
+
+/* pred: NULL = full view; pred_f32 says which of pred_i / pred_f is the
+ * predicate column (it may be the updated column itself). */
+void orc_view_update_i32(uint64_t n, int32_t *col, int32_t a, int32_t b,
+                         const int32_t *pred_i, const float *pred_f, int cmp,
+                         int32_t thr_i, float thr_f)
+{
+    unsigned char *take = malloc(n ? n : 1);
+    if (!take) return;
+    for (uint64_t r = 0; r < n; r++)
+        take[r] = pred_i ? cmp_i32(pred_i[r], cmp, thr_i)
+                         : pred_f ? cmp_f32(pred_f[r], cmp, thr_f) : 1;
+    for (uint64_t r = 0; r < n; r++)
+        if (take[r]) col[r] = affine_i32(col[r], a, b);
+    free(take);
+}
+
+void orc_view_update_f32(uint64_t n, float *col, float a, float b,
+                         const int32_t *pred_i, const float *pred_f, int cmp,
+                         int32_t thr_i, float thr_f)
+{
+    unsigned char *take = malloc(n ? n : 1);
+    if (!take) return;
+    for (uint64_t r = 0; r < n; r++)
+        take[r] = pred_i ? cmp_i32(pred_i[r], cmp, thr_i)
+                         : pred_f ? cmp_f32(pred_f[r], cmp, thr_f) : 1;
+    for (uint64_t r = 0; r < n; r++)
+        if (take[r]) col[r] = fmaf(a, col[r], b);
+    free(take);
+}
+
+/* vals NULL: every entry adds *scalar. */
+void orc_view_scatter_add_i32(uint64_t n, int32_t *col, uint64_t m, const uint32_t *ids,
+                              const int32_t *vals, int32_t scalar)
+{
+    for (uint64_t j = 0; j < m; j++) {
+        if (ids[j] >= n) continue;
+        col[ids[j]] = (int32_t)((uint32_t)col[ids[j]] + (uint32_t)(vals ? vals[j] : scalar));
+    }
+}
+
+void orc_view_scatter_add_f32(uint64_t n, float *col, uint64_t m, const uint32_t *ids,
+                              const float *vals, float scalar)
+{
+    for (uint64_t j = 0; j < m; j++) {
+        if (ids[j] >= n) continue;
+        col[ids[j]] = col[ids[j]] + (vals ? vals[j] : scalar);
+    }
 }
 
 /* ------------------------------------------------------------ whole runs */

@@ -11,8 +11,10 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 
 def build(verbose: bool = False) -> str:
-    cmd = ["gcc", "-O2", "-std=gnu11", "-Wall", "-Wextra", "-fPIC", "-shared",
-           SRC, "-o", LIB + ".tmp"]
+    # -ffp-contract=off: no float expression is fused beyond what the source
+    # writes (fmaf is called where a fused multiply-add is meant)
+    cmd = ["gcc", "-O2", "-std=gnu11", "-Wall", "-Wextra", "-fPIC", "-shared", "-ffp-contract=off",
+           SRC, "-o", LIB + ".tmp", "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)

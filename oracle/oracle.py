@@ -57,6 +57,13 @@ def lib():
                                   _u32, _u32, _p, _p, _p, ctypes.c_int]
         for f in (L.orc_run_wealth, L.orc_run_walk, L.orc_walk_agents, L.orc_run_sir):
             f.restype = ctypes.c_int
+        u64 = ctypes.c_uint64
+        L.orc_view_update_i32.argtypes = [u64, _p, _i32, _i32, _p, _p, ctypes.c_int, _i32,
+                                          ctypes.c_float]
+        L.orc_view_update_f32.argtypes = [u64, _p, ctypes.c_float, ctypes.c_float, _p, _p,
+                                          ctypes.c_int, _i32, ctypes.c_float]
+        L.orc_view_scatter_add_i32.argtypes = [u64, _p, u64, _p, _p, _i32]
+        L.orc_view_scatter_add_f32.argtypes = [u64, _p, u64, _p, _p, ctypes.c_float]
         _lib = L
     return _lib
 
@@ -139,6 +146,57 @@ def invariants(n, L=0, w=None, x=None, y=None, s=None):
     return {f: getattr(out, f) for f, _ in _Inv._fields_}
 
 
+# ------------------------------------------------------------------ view primitives
+
+CMP = {"<": 0, "<=": 1, "==": 2, "!=": 3, ">=": 4, ">": 5}
+
+
+def view_update(col, a, b, pred=None, cmp="<", thr=0):
+    """Full view (pred None) or filtered view (rows where pred CMP thr, read
+    before the update): v <- a*v + b, in place on a copy; returns the copy.
+    int32 wraps modulo 2^32, float32 is one fused multiply-add."""
+    col = np.array(col)
+    assert col.dtype in (np.int32, np.float32)
+    pi = pf = None
+    if pred is not None:
+        pred = np.ascontiguousarray(pred)
+        if pred.dtype == np.int32:
+            pi = pred
+        elif pred.dtype == np.float32:
+            pf = pred
+        else:
+            raise TypeError("predicate column must be int32 or float32")
+        assert len(pred) == len(col)
+    if col.dtype == np.int32:
+        lib().orc_view_update_i32(len(col), _ptr(col), int(a), int(b), _ptr(pi), _ptr(pf),
+                                  CMP[cmp], int(thr) if pi is not None else 0,
+                                  float(thr) if pf is not None else 0.0)
+    else:
+        lib().orc_view_update_f32(len(col), _ptr(col), float(a), float(b), _ptr(pi), _ptr(pf),
+                                  CMP[cmp], int(thr) if pi is not None else 0,
+                                  float(thr) if pf is not None else 0.0)
+    return col
+
+
+def scatter_add(col, ids, vals=None, scalar=0):
+    """Scatter view: for j in list order col[ids[j]] += vals[j] (or scalar);
+    ids outside [0, len(col)) are skipped.  Returns the updated copy."""
+    col = np.array(col)
+    ids = np.ascontiguousarray(ids, dtype=np.uint32)
+    if vals is not None:
+        vals = np.ascontiguousarray(vals, dtype=col.dtype)
+        assert len(vals) == len(ids)
+    if col.dtype == np.int32:
+        lib().orc_view_scatter_add_i32(len(col), _ptr(col), len(ids), _ptr(ids), _ptr(vals),
+                                       int(scalar))
+    elif col.dtype == np.float32:
+        lib().orc_view_scatter_add_f32(len(col), _ptr(col), len(ids), _ptr(ids), _ptr(vals),
+                                       float(scalar))
+    else:
+        raise TypeError("column must be int32 or float32")
+    return col
+
+
 # ------------------------------------------------------------------ runs
 
 class OracleRun:
@@ -176,6 +234,28 @@ class OracleRun:
             raise ValueError("unknown model")
         if rc != 0:
             raise RuntimeError("oracle init failed")
+
+    @classmethod
+    def resume(cls, model, columns, t, L=0, seed=0, stream=0, beta=(1, 20), gamma=(1, 100)):
+        """A run continued from host columns holding its state after t steps
+        (the columns are copied)."""
+        self = cls.__new__(cls)
+        self.model, self.seed, self.stream, self.t = model, seed, stream, t
+        cols = [np.array(c) for c in columns]
+        self.n = len(cols[0])
+        if model == WEALTH:
+            self.L = 0
+            (self.w,) = [c.astype(np.int32) for c in cols]
+        else:
+            self.L = L if L else grid_side(self.n)
+            self.x, self.y = cols[0].astype(np.int32), cols[1].astype(np.int32)
+            if model == SIR:
+                self.s = cols[2].astype(np.uint8)
+                self.i0 = 0
+                self.t_inf, self.k_sat = thresholds.infection_table(*beta)
+                self.t_inf = np.array(self.t_inf, dtype=np.uint32)
+                self.t_rec = thresholds.recovery_threshold(*gamma)
+        return self
 
     def _sir(self, t0, k, do_init):
         return lib().orc_run_sir(self.n, self.L, self.seed, self.stream, self.i0,
