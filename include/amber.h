@@ -180,6 +180,22 @@ AMBER_API amber_status_t amber_init_population(const amber_run_desc_t *desc,
                                      const amber_buffers_t *bufs,
                                      void *hip_stream, amber_pop_t **out);
 
+/* A run continued from a state held in host memory (the columnar bulk
+ * create of Sec. 3.3, add_agents from arrays, here the state after `step`
+ * steps of this descriptor's run): as amber_init_population, then the first
+ * N rows of each column the model uses are copied from host_cols[c] (N
+ * int32 values, uint8 for the state column; host memory read before the
+ * call returns) and the handle's step count is `step`.  Stepping it on
+ * gives the same columns as the uninterrupted run, since every random word
+ * is addressed by (agent, step).  Synchronises the stream.  AMBER_E_INVALID,
+ * with nothing enqueued, for a state outside the model's domain (negative
+ * wealth or a wealth sum above 2^31-1, a coordinate off the grid, a state
+ * code above 2) or step > 2^32-1; other errors as amber_init_population. */
+AMBER_API amber_status_t amber_resume_population(const amber_run_desc_t *desc,
+                                                 const amber_buffers_t *bufs,
+                                                 const void *const *host_cols, uint64_t step,
+                                                 void *hip_stream, amber_pop_t **out);
+
 /* Bytes of device scratch behind amber_init_population_noalloc, per GPU. */
 #define AMBER_NOALLOC_SCRATCH_BYTES (32u << 20)
 
@@ -249,6 +265,55 @@ AMBER_API amber_status_t amber_invariants(amber_pop_t *pop, amber_invariants_t *
 
 /* Resolved parameters and step count of a handle (host only, no sync). */
 AMBER_API amber_status_t amber_pop_info(const amber_pop_t *pop, amber_pop_info_t *out);
+
+/* ------------------------------------------------------------------ views
+ * The view primitives of the method (Sec. 3.3 view API; Sec. 3.1.1
+ * listings) on any int32 or float32 column in device memory, outside any
+ * run: a full-population update, a filtered (predicate) update and an
+ * id-indexed scatter-add with duplicate ids accumulating.  Columns, ids,
+ * values and workspace are caller-owned device buffers on the current
+ * device (4-byte aligned; 16-byte alignment gives vector accesses); calls
+ * are enqueued on hip_stream (NULL = default stream) and do not synchronise.
+ * int32 arithmetic wraps modulo 2^32.  float32 updates are one fused
+ * multiply-add (a*v + b rounded once to nearest); a float32 scatter-add
+ * rounds after every addition, in the order of the list, so its result is
+ * that of numpy's add.at.  Every result is independent of launch shape. */
+typedef enum { AMBER_DT_I32 = 0, AMBER_DT_F32 = 1 } amber_dtype_t;
+typedef enum {
+    AMBER_CMP_LT = 0, AMBER_CMP_LE = 1, AMBER_CMP_EQ = 2,
+    AMBER_CMP_NE = 3, AMBER_CMP_GE = 4, AMBER_CMP_GT = 5
+} amber_cmp_t;
+typedef union { int32_t i; float f; } amber_value_t;   /* member by dtype */
+
+/* Full view (pred NULL): col[r] = a*col[r] + b for r < n.  Filtered view:
+ * the same for the rows where pred[r] CMP thr, pred being an int32 or
+ * float32 column of n rows (it may be col itself: it is read before the
+ * update), thr of pred's dtype; NaN compares false except under NE.
+ * AMBER_E_INVALID for a bad dtype or comparison, or a buffer that is NULL,
+ * misaligned, not device memory of the current device or shorter than n
+ * rows (nothing is enqueued); AMBER_E_UNSUPPORTED for n >= 2^40. */
+AMBER_API amber_status_t amber_view_update(void *col, uint32_t dtype, uint64_t n,
+                                           amber_value_t a, amber_value_t b, const void *pred,
+                                           uint32_t pred_dtype, uint32_t cmp, amber_value_t thr,
+                                           void *hip_stream);
+
+/* Device workspace bytes of amber_view_scatter_add for m entries (0 for
+ * int32, which needs none; 0 as well for a bad dtype or m > 2^31). */
+AMBER_API size_t amber_view_scatter_workspace_bytes(uint32_t dtype, uint64_t n, uint64_t m);
+
+/* Scatter view: for j = 0 .. m-1, col[ids[j]] += vals[j] (vals NULL: the
+ * scalar), duplicates accumulating; entries with ids[j] >= n are skipped.
+ * int32: one atomic add per entry (any order gives the same column).
+ * float32: the entries are ordered by (id, j) with a stable radix sort in
+ * the workspace, then each id's entries are added one after the other in
+ * list order (an id with k entries costs k dependent adds on one thread).
+ * AMBER_E_INVALID / AMBER_E_NOMEM for bad or short buffers (nothing is
+ * enqueued), AMBER_E_UNSUPPORTED for n >= 2^32 or m > 2^31. */
+AMBER_API amber_status_t amber_view_scatter_add(void *col, uint32_t dtype, uint64_t n,
+                                                const uint32_t *ids, uint64_t m,
+                                                const void *vals, amber_value_t scalar,
+                                                void *workspace, size_t workspace_bytes,
+                                                void *hip_stream);
 
 /* Launch-shape knobs.  They never change results (all arithmetic is integer
  * and every random word is addressed by agent and step), only speed. */

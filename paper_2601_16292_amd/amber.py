@@ -33,7 +33,9 @@ MODEL_COLUMNS = {WEALTH: [COL_WEALTH], RANDOM_WALK: [COL_X, COL_Y],
 
 EXPORTED = ["amber_abi_version", "amber_column_bytes", "amber_workspace_bytes",
             "amber_infection_table", "amber_init_population",
-            "amber_init_population_noalloc", "amber_step",
+            "amber_init_population_noalloc", "amber_resume_population",
+            "amber_view_update", "amber_view_scatter_workspace_bytes",
+            "amber_view_scatter_add", "amber_step",
             "amber_step_batch", "amber_read_columns", "amber_invariants",
             "amber_pop_info", "amber_set_tuning", "amber_get_tuning",
             "amber_profile_enable", "amber_profile_read",
@@ -91,6 +93,23 @@ class KernelTime(ctypes.Structure):
                 ("total_ms", ctypes.c_double)]
 
 
+DT_I32, DT_F32 = 0, 1
+CMP = {"<": 0, "<=": 1, "==": 2, "!=": 3, ">=": 4, ">": 5}
+
+
+class Value(ctypes.Union):
+    _fields_ = [("i", ctypes.c_int32), ("f", ctypes.c_float)]
+
+
+def value(dtype, v):
+    out = Value()
+    if dtype == DT_I32:
+        out.i = int(v)
+    else:
+        out.f = float(v)
+    return out
+
+
 class AmberError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
@@ -131,6 +150,19 @@ def lib():
         L.amber_init_population_noalloc.argtypes = [ctypes.POINTER(RunDesc),
                                                     ctypes.POINTER(Buffers), P,
                                                     ctypes.POINTER(P)]
+        L.amber_resume_population.restype = ctypes.c_int
+        L.amber_resume_population.argtypes = [ctypes.POINTER(RunDesc), ctypes.POINTER(Buffers),
+                                              ctypes.POINTER(P), ctypes.c_uint64, P,
+                                              ctypes.POINTER(P)]
+        L.amber_view_update.restype = ctypes.c_int
+        L.amber_view_update.argtypes = [P, ctypes.c_uint32, ctypes.c_uint64, Value, Value, P,
+                                        ctypes.c_uint32, ctypes.c_uint32, Value, P]
+        L.amber_view_scatter_workspace_bytes.restype = ctypes.c_size_t
+        L.amber_view_scatter_workspace_bytes.argtypes = [ctypes.c_uint32, ctypes.c_uint64,
+                                                         ctypes.c_uint64]
+        L.amber_view_scatter_add.restype = ctypes.c_int
+        L.amber_view_scatter_add.argtypes = [P, ctypes.c_uint32, ctypes.c_uint64, P,
+                                             ctypes.c_uint64, P, Value, P, ctypes.c_size_t, P]
         L.amber_step.restype = ctypes.c_int
         L.amber_step.argtypes = [P, ctypes.c_uint32]
         L.amber_step_batch.restype = ctypes.c_int
@@ -209,6 +241,30 @@ def amber_init_population_noalloc(desc, bufs, stream_ptr):
 
 
 NOALLOC_SCRATCH_BYTES = 32 << 20
+
+
+def amber_resume_population(desc, bufs, host_ptrs, step, stream_ptr):
+    """Returns (status, handle); host_ptrs[c] is the host address of column c."""
+    arr = (ctypes.c_void_p * NUM_COLS)(*host_ptrs)
+    h = ctypes.c_void_p()
+    st = lib().amber_resume_population(ctypes.byref(desc), ctypes.byref(bufs), arr, step,
+                                       ctypes.c_void_p(stream_ptr), ctypes.byref(h))
+    return st, h
+
+
+def amber_view_update(col_ptr, dtype, n, a, b, pred_ptr, pred_dtype, cmp, thr, stream_ptr):
+    return lib().amber_view_update(col_ptr, dtype, n, a, b, pred_ptr, pred_dtype, cmp, thr,
+                                   stream_ptr)
+
+
+def amber_view_scatter_workspace_bytes(dtype, n, m):
+    return lib().amber_view_scatter_workspace_bytes(dtype, n, m)
+
+
+def amber_view_scatter_add(col_ptr, dtype, n, ids_ptr, m, vals_ptr, scalar, ws_ptr, ws_bytes,
+                           stream_ptr):
+    return lib().amber_view_scatter_add(col_ptr, dtype, n, ids_ptr, m, vals_ptr, scalar, ws_ptr,
+                                        ws_bytes, stream_ptr)
 
 
 def amber_step(handle, n_steps):
@@ -302,11 +358,14 @@ def _release_all():
 
 class Population:
     """One run: device buffers (torch tensors on the current device) plus the
-    library handle.  ``stream`` is a torch.cuda.Stream (default: current)."""
+    library handle.  ``stream`` is a torch.cuda.Stream (default: current).
+    ``resume=(host_columns, step)`` continues a run from its state after
+    `step` steps (amber_resume_population); ``noalloc`` takes the library's
+    device scratch as the workspace (amber_init_population_noalloc)."""
 
     def __init__(self, model, n, L=0, seed=0, stream_id=0, wealth_init=1, beta=(1, 20),
                  gamma=(1, 100), initial_infected=0, stream=None, device=None,
-                 buffers=None, noalloc=False):
+                 buffers=None, noalloc=False, resume=None):
         import torch
         self.desc = make_desc(model, n, L, seed, stream_id, wealth_init, beta, gamma,
                               initial_infected)
@@ -338,8 +397,20 @@ class Population:
             b.workspace_bytes = self.workspace.numel()
         self.bufs = b
         self.handle = None
-        init = amber_init_population_noalloc if noalloc else amber_init_population
-        st, handle = init(self.desc, b, self.stream.cuda_stream)
+        if resume is not None:
+            host_cols, step = resume
+            import numpy as np
+            self._host = {}
+            ptrs = [None] * NUM_COLS
+            for c, h in zip(MODEL_COLUMNS[model], host_cols):
+                a = np.ascontiguousarray(h, dtype=np.uint8 if c == COL_STATE else np.int32)
+                self._host[c] = a
+                ptrs[c] = a.ctypes.data
+            st, handle = amber_resume_population(self.desc, b, ptrs, step,
+                                                 self.stream.cuda_stream)
+        else:
+            init = amber_init_population_noalloc if noalloc else amber_init_population
+            st, handle = init(self.desc, b, self.stream.cuda_stream)
         check(st)
         self.handle = handle
         _LIVE.add(self)
@@ -399,6 +470,49 @@ class Population:
             self.release()
         except Exception:
             pass
+
+
+def _dtype_of(t):
+    import torch
+    if t.dtype == torch.int32:
+        return DT_I32
+    if t.dtype == torch.float32:
+        return DT_F32
+    raise TypeError("view columns must be int32 or float32 tensors")
+
+
+def view_update(col, a, b, pred=None, cmp="<", thr=0, stream=None):
+    """Full (pred None) or filtered view update of a device tensor in place:
+    col[r] = a*col[r] + b where pred[r] CMP thr (pred read before the update)."""
+    import torch
+    st = stream if stream is not None else torch.cuda.current_stream(col.device)
+    dt = _dtype_of(col)
+    pdt = _dtype_of(pred) if pred is not None else DT_I32
+    check(amber_view_update(col.data_ptr(), dt, col.numel(), value(dt, a), value(dt, b),
+                            pred.data_ptr() if pred is not None else None, pdt, CMP[cmp],
+                            value(pdt, thr), st.cuda_stream))
+    return col
+
+
+def scatter_add(col, ids, vals=None, scalar=0, stream=None, workspace=None):
+    """Scatter view on a device tensor in place: col[ids[j]] += vals[j] (or
+    scalar) in list order, duplicates accumulating; ids a uint32-valued
+    int32 tensor on the device.  A float32 scatter needs a workspace; one is
+    allocated with torch when none is passed."""
+    import torch
+    st = stream if stream is not None else torch.cuda.current_stream(col.device)
+    dt = _dtype_of(col)
+    m = ids.numel()
+    need = amber_view_scatter_workspace_bytes(dt, col.numel(), m)
+    if need and workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=col.device)
+    check(amber_view_scatter_add(col.data_ptr(), dt, col.numel(), ids.data_ptr() if m else None,
+                                 m, vals.data_ptr() if vals is not None else None,
+                                 value(dt, scalar),
+                                 workspace.data_ptr() if workspace is not None else None,
+                                 workspace.numel() if workspace is not None else 0,
+                                 st.cuda_stream))
+    return col
 
 
 def step_batch(pops, n_steps):

@@ -565,6 +565,37 @@ amber_status_t check_device_ptr(const void *p, int device, const char *what, siz
     return AMBER_OK;
 }
 
+// A device buffer of `need` bytes at p for the view calls: element-aligned
+// (`align` bytes), device memory of `device`, inside its allocation where the
+// runtime reports the allocation's extent.
+amber_status_t check_view_ptr(const void *p, int device, const char *what, uint64_t need,
+                              uint32_t align)
+{
+    if (!p) return fail(AMBER_E_INVALID, "%s is NULL", what);
+    if (((uintptr_t)p % align) != 0)
+        return fail(AMBER_E_INVALID, "%s is not %u-byte aligned", what, align);
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(AMBER_E_INVALID, "%s is not a HIP device pointer", what);
+    }
+    if (attr.type != hipMemoryTypeDevice) return fail(AMBER_E_INVALID, "%s is not device memory", what);
+    if (attr.device != device)
+        return fail(AMBER_E_INVALID, "%s lives on device %d, current device is %d", what,
+                    attr.device, device);
+    hipDeviceptr_t base = nullptr;
+    size_t extent = 0;
+    if (hipMemGetAddressRange(&base, &extent, const_cast<void *>(p)) != hipSuccess) {
+        (void)hipGetLastError();
+        return AMBER_OK;
+    }
+    const uint64_t off = (uint64_t)((uintptr_t)p - (uintptr_t)base);
+    if ((uintptr_t)p < (uintptr_t)base || off > extent || extent - off < need)
+        return fail(AMBER_E_INVALID, "%s has fewer than the %llu bytes the call needs", what,
+                    (unsigned long long)need);
+    return AMBER_OK;
+}
+
 // After a synchronisation: report (and clear) the sticky device error word
 // that a persistent launch sets when one of its barrier waits gave up.
 amber_status_t check_device_flag(amber_pop *p, uint32_t flag)
@@ -1343,8 +1374,45 @@ bool g_scratch_held[NOALLOC_MAX_DEVICES] = {};
 // handle takes no pinned early-stop word (the SIR early stop and the
 // tiled-then-gather switch are then off, results unchanged), and at most one
 // such handle per device may be live.
+// A resumed run's host columns must hold a state of the model's domain:
+// wealth non-negative with a sum below 2^31 (so no agent can overflow),
+// coordinates on the grid (the kernels address the count grid with them),
+// state codes 0, 1 or 2.
+amber_status_t check_host_columns(const Resolved &r, const void *const *host)
+{
+    static const char *names[AMBER_NUM_COLS] = {"wealth", "x", "y", "state"};
+    for (int c = 0; c < AMBER_NUM_COLS; ++c)
+        if (column_bytes(r, (amber_col_t)c) != 0 && !host[c])
+            return fail(AMBER_E_INVALID, "host %s column is NULL", names[c]);
+    if (r.model == AMBER_WEALTH) {
+        const int32_t *w = (const int32_t *)host[AMBER_COL_WEALTH];
+        int64_t sum = 0;
+        for (uint32_t a = 0; a < r.n; ++a) {
+            if (w[a] < 0) return fail(AMBER_E_INVALID, "host wealth of agent %u is negative", a);
+            sum += w[a];
+        }
+        if (sum > INT32_MAX)
+            return fail(AMBER_E_INVALID, "host wealth sums to %lld, above 2^31-1", (long long)sum);
+        return AMBER_OK;
+    }
+    for (int c = AMBER_COL_X; c <= AMBER_COL_Y; ++c) {
+        const int32_t *v = (const int32_t *)host[c];
+        for (uint32_t a = 0; a < r.n; ++a)
+            if (v[a] < 0 || (uint32_t)v[a] >= r.L)
+                return fail(AMBER_E_INVALID, "host %s of agent %u is %d, off the %u-cell grid",
+                            names[c], a, v[a], r.L);
+    }
+    if (r.model == AMBER_SIR) {
+        const uint8_t *s = (const uint8_t *)host[AMBER_COL_STATE];
+        for (uint32_t a = 0; a < r.n; ++a)
+            if (s[a] > 2) return fail(AMBER_E_INVALID, "host state of agent %u is %u", a, s[a]);
+    }
+    return AMBER_OK;
+}
+
 amber_status_t init_population(const amber_run_desc_t *desc, const amber_buffers_t *bufs,
-                               void *hip_stream, amber_pop_t **out, bool noalloc)
+                               void *hip_stream, amber_pop_t **out, bool noalloc,
+                               const void *const *host_cols = nullptr, uint64_t t0 = 0)
 {
     if (!out) return fail(AMBER_E_INVALID, "out is NULL");
     *out = nullptr;
@@ -1357,6 +1425,10 @@ amber_status_t init_population(const amber_run_desc_t *desc, const amber_buffers
     for (int c = 0; c < AMBER_NUM_COLS; ++c)
         if (column_bytes(r, (amber_col_t)c) != 0 && !bufs->col[c])
             return fail(AMBER_E_INVALID, "%s is NULL", names[c]);
+    if (host_cols) {
+        if (t0 > 0xffffffffull) return fail(AMBER_E_INVALID, "step index above 2^32-1");
+        if ((st = check_host_columns(r, host_cols)) != AMBER_OK) return st;
+    }
     amber_buffers_t b = *bufs;
     if (noalloc) {
         if (b.workspace || b.workspace_bytes)
@@ -1456,6 +1528,20 @@ amber_status_t init_population(const amber_run_desc_t *desc, const amber_buffers
         }
     }
     if (e != hipSuccess) return bail(hip_fail(e, "init kernels"));
+    if (host_cols) {
+        // the state after t0 steps replaces the initial rows (the padding
+        // rows past N keep their initial, in-domain values); the host
+        // columns are read before the call returns
+        for (int c = 0; c < AMBER_NUM_COLS && e == hipSuccess; ++c) {
+            if (column_bytes(rr, (amber_col_t)c) == 0) continue;
+            e = hipMemcpyAsync(p->b.col[c], host_cols[c],
+                               (size_t)rr.n * (c == AMBER_COL_STATE ? 1 : 4),
+                               hipMemcpyHostToDevice, p->stream);
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+        if (e != hipSuccess) return bail(hip_fail(e, "column upload"));
+        p->step = t0;
+    }
     {
         std::lock_guard<std::mutex> lk(g_live_mu);
         g_live.insert(p);
@@ -1503,11 +1589,85 @@ amber_status_t amber_init_population(const amber_run_desc_t *desc, const amber_b
     return init_population(desc, bufs, hip_stream, out, false);
 }
 
+amber_status_t amber_resume_population(const amber_run_desc_t *desc, const amber_buffers_t *bufs,
+                                       const void *const *host_cols, uint64_t step,
+                                       void *hip_stream, amber_pop_t **out)
+{
+    if (!host_cols) return fail(AMBER_E_INVALID, "host_cols is NULL");
+    return init_population(desc, bufs, hip_stream, out, false, host_cols, step);
+}
+
 amber_status_t amber_init_population_noalloc(const amber_run_desc_t *desc,
                                              const amber_buffers_t *bufs, void *hip_stream,
                                              amber_pop_t **out)
 {
     return init_population(desc, bufs, hip_stream, out, true);
+}
+
+amber_status_t amber_view_update(void *col, uint32_t dtype, uint64_t n, amber_value_t a,
+                                 amber_value_t b, const void *pred, uint32_t pred_dtype,
+                                 uint32_t cmp, amber_value_t thr, void *hip_stream)
+{
+    if (dtype != AMBER_DT_I32 && dtype != AMBER_DT_F32)
+        return fail(AMBER_E_INVALID, "dtype must be AMBER_DT_I32 or AMBER_DT_F32");
+    if (pred && pred_dtype != AMBER_DT_I32 && pred_dtype != AMBER_DT_F32)
+        return fail(AMBER_E_INVALID, "pred_dtype must be AMBER_DT_I32 or AMBER_DT_F32");
+    if (pred && cmp > AMBER_CMP_GT) return fail(AMBER_E_INVALID, "cmp must be an amber_cmp_t");
+    if (n >= (1ull << 40)) return fail(AMBER_E_UNSUPPORTED, "columns of 2^40 rows or more");
+    if (n == 0) return AMBER_OK;
+    int device = 0;
+    HIP_TRY(hipGetDevice(&device), "hipGetDevice");
+    amber_status_t st = check_view_ptr(col, device, "column", 4 * n, 4);
+    if (st != AMBER_OK) return st;
+    if (pred && (st = check_view_ptr(pred, device, "predicate column", 4 * n, 4)) != AMBER_OK)
+        return st;
+    ViewValue va, vb, vt;
+    va.i = a.i;
+    vb.i = b.i;
+    vt.i = thr.i;
+    HIP_TRY(launch_view_update(col, dtype, n, va, vb, pred, pred_dtype, cmp, vt,
+                               (hipStream_t)hip_stream),
+            "view update kernel");
+    return AMBER_OK;
+}
+
+size_t amber_view_scatter_workspace_bytes(uint32_t dtype, uint64_t n, uint64_t m)
+{
+    (void)n;
+    if (dtype == AMBER_DT_I32) return 0;
+    if (dtype != AMBER_DT_F32 || m > (1ull << 31)) return 0;
+    return (size_t)view_scatter_f32_workspace(m);
+}
+
+amber_status_t amber_view_scatter_add(void *col, uint32_t dtype, uint64_t n, const uint32_t *ids,
+                                      uint64_t m, const void *vals, amber_value_t scalar,
+                                      void *workspace, size_t workspace_bytes, void *hip_stream)
+{
+    if (dtype != AMBER_DT_I32 && dtype != AMBER_DT_F32)
+        return fail(AMBER_E_INVALID, "dtype must be AMBER_DT_I32 or AMBER_DT_F32");
+    if (n > 0xffffffffull) return fail(AMBER_E_UNSUPPORTED, "columns of 2^32 rows or more");
+    if (m > (1ull << 31)) return fail(AMBER_E_UNSUPPORTED, "more than 2^31 scatter entries");
+    const uint64_t need = dtype == AMBER_DT_F32 ? view_scatter_f32_workspace(m) : 0;
+    if (m && need && !workspace) return fail(AMBER_E_INVALID, "workspace is NULL");
+    if (m && workspace_bytes < need)
+        return fail(AMBER_E_NOMEM, "workspace has %zu bytes, the call needs %llu", workspace_bytes,
+                    (unsigned long long)need);
+    if (m == 0) return AMBER_OK;
+    int device = 0;
+    HIP_TRY(hipGetDevice(&device), "hipGetDevice");
+    amber_status_t st = AMBER_OK;
+    if (n && (st = check_view_ptr(col, device, "column", 4 * n, 4)) != AMBER_OK) return st;
+    if ((st = check_view_ptr(ids, device, "ids", 4 * m, 4)) != AMBER_OK) return st;
+    if (vals && (st = check_view_ptr(vals, device, "vals", 4 * m, 4)) != AMBER_OK) return st;
+    if (need && (st = check_view_ptr(workspace, device, "workspace", need, 16)) != AMBER_OK)
+        return st;
+    if (n == 0) return AMBER_OK;                     // every id is out of range
+    ViewValue sv;
+    sv.i = scalar.i;
+    HIP_TRY(launch_view_scatter_add(col, dtype, n, ids, m, vals, sv, workspace,
+                                    (hipStream_t)hip_stream),
+            "view scatter-add kernels");
+    return AMBER_OK;
 }
 
 amber_status_t amber_step(amber_pop_t *pop, uint32_t n_steps)

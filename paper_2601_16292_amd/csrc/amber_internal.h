@@ -110,6 +110,22 @@ hipError_t launch_init_positions(int32_t *x, int32_t *y, uint32_t n, int32_t L,
 hipError_t launch_init_states(uint8_t *s, uint32_t n, uint32_t i0, hipStream_t st);
 hipError_t launch_zero_words(uint32_t *p, uint64_t words, hipStream_t st);
 
+// View primitives on arbitrary columns (amber_views.hip).
+union ViewValue {
+    int32_t i;
+    float f;
+};
+constexpr uint32_t VIEW_I32 = 0, VIEW_F32 = 1;
+// Workspace bytes of a float32 scatter-add of m entries.
+uint64_t view_scatter_f32_workspace(uint64_t m);
+hipError_t launch_view_update(void *col, uint32_t dtype, uint64_t n, ViewValue a, ViewValue b,
+                              const void *pred, uint32_t pred_dtype, uint32_t cmp, ViewValue thr,
+                              hipStream_t st);
+// ws: view_scatter_f32_workspace(m) bytes, 16-byte aligned (float32 only).
+hipError_t launch_view_scatter_add(void *col, uint32_t dtype, uint64_t n, const uint32_t *ids,
+                                   uint64_t m, const void *vals, ViewValue scalar, void *ws,
+                                   hipStream_t st);
+
 // Device workspace of the no-allocation handles: a file-scope device array
 // of NOALLOC_SCRATCH_BYTES per GPU.  noalloc_scratch returns its address on
 // `device`, which must be the current device (looked up once per device).

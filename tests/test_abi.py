@@ -114,6 +114,54 @@ def test_noalloc_init_checks_before_touching_the_device():
     assert st == A.E_UNSUPPORTED and "scratch" in A.amber_last_error()
 
 
+def test_view_calls_check_arguments_before_touching_the_device():
+    v = A.value(A.DT_I32, 1)
+    assert A.amber_view_update(0x1000, 7, 10, v, v, None, 0, 0, v, None) == A.E_INVALID
+    assert A.amber_view_update(0x1000, A.DT_I32, 10, v, v, 0x2000, 0, 9, v, None) == A.E_INVALID
+    assert A.amber_view_update(0x1000, A.DT_I32, 1 << 40, v, v, None, 0, 0, v, None) == \
+        A.E_UNSUPPORTED
+    assert A.amber_view_update(0x1000, A.DT_I32, 0, v, v, None, 0, 0, v, None) == A.OK
+    assert A.amber_view_scatter_workspace_bytes(A.DT_I32, 100, 1000) == 0
+    need = A.amber_view_scatter_workspace_bytes(A.DT_F32, 100, 1000)
+    assert need >= 16 * 1000
+    assert A.amber_view_scatter_add(0x1000, A.DT_F32, 100, 0x2000, 1000, None,
+                                    A.value(A.DT_F32, 1.0), None, 0, None) == A.E_INVALID
+    assert A.amber_view_scatter_add(0x1000, A.DT_F32, 100, 0x2000, 1000, None,
+                                    A.value(A.DT_F32, 1.0), 0x3000, need - 1, None) == A.E_NOMEM
+    assert A.amber_view_scatter_add(0x1000, A.DT_I32, 1 << 32, 0x2000, 10, None, v, None, 0,
+                                    None) == A.E_UNSUPPORTED
+    assert A.amber_view_scatter_add(0x1000, A.DT_I32, 100, None, 0, None, v, None, 0, None) == A.OK
+
+
+@pytest.mark.parametrize("model,bad", [(A.WEALTH, "negative"), (A.WEALTH, "sum"),
+                                       (A.RANDOM_WALK, "x"), (A.SIR, "y"), (A.SIR, "state")])
+def test_resume_rejects_states_outside_the_domain(model, bad):
+    import numpy as np
+    n, L = 100, 10
+    d = A.make_desc(model, n, L)
+    b = A.Buffers()
+    for c in A.MODEL_COLUMNS[model]:
+        b.col[c] = 0x1000 * (c + 1)
+    b.workspace, b.workspace_bytes = 0x100000, A.amber_workspace_bytes(d)
+    cols = {A.COL_WEALTH: np.ones(n, np.int32), A.COL_X: np.zeros(n, np.int32),
+            A.COL_Y: np.full(n, L - 1, np.int32), A.COL_STATE: np.full(n, 2, np.uint8)}
+    if bad == "negative":
+        cols[A.COL_WEALTH][5] = -1
+    elif bad == "sum":
+        cols[A.COL_WEALTH][:] = 2**30
+    elif bad == "x":
+        cols[A.COL_X][7] = L
+    elif bad == "y":
+        cols[A.COL_Y][0] = -1
+    else:
+        cols[A.COL_STATE][99] = 3
+    ptrs = [cols[c].ctypes.data if c in A.MODEL_COLUMNS[model] else None for c in range(4)]
+    st, _ = A.amber_resume_population(d, b, ptrs, 5, 0)
+    assert st == A.E_INVALID and "host" in A.amber_last_error()
+    st, _ = A.amber_resume_population(d, b, ptrs, 1 << 32, 0)
+    assert st == A.E_INVALID
+
+
 def test_handle_misuse_is_reported():
     import ctypes
     bogus = ctypes.c_void_p(0xdeadbeef)
