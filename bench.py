@@ -363,6 +363,13 @@ def roofline_big(torch, A, log2n):
         pop.release()
         torch.cuda.empty_cache()
 
+    # view primitives on 2^27-row columns: a full and a filtered int32
+    # update (8 B per row, plus 4 B per row of predicate), a float32 update,
+    # and int32 / float32 scatter-adds of 2^25 entries (ids and values read,
+    # one 8-B read-modify-write per entry)
+    res["views"] = view_roofline(torch, A, n)
+    torch.cuda.empty_cache()
+
     # whole SIR runs at this size: 499 steps in one call after one step,
     # in the automatic mode (the gather mode when the call is not paced;
     # tiled, then gather when it is), all gather and all tiled
@@ -393,6 +400,47 @@ def roofline_big(torch, A, log2n):
         pass
     res["sir_whole_run_500_steps"] = runs
     return res
+
+
+def view_roofline(torch, A, n, m=1 << 25):
+    out = {"rows": n, "scatter_entries": m}
+    g = torch.Generator(device="cuda").manual_seed(7)
+    col = torch.randint(-1000, 1000, (n,), dtype=torch.int32, device="cuda", generator=g)
+    colf = torch.rand(n, dtype=torch.float32, device="cuda", generator=g)
+    pred = torch.randint(-5, 6, (n,), dtype=torch.int32, device="cuda", generator=g)
+    ids = torch.randint(0, n, (m,), dtype=torch.int32, device="cuda", generator=g)
+    vals = torch.randint(-9, 9, (m,), dtype=torch.int32, device="cuda", generator=g)
+    valsf = torch.rand(m, dtype=torch.float32, device="cuda", generator=g)
+
+    def timed(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3 / reps
+
+    def entry(secs, nbytes):
+        gbs = nbytes / secs / 1e9
+        return {"avg_call_us": round(secs * 1e6, 2), "algorithmic_bytes": int(nbytes),
+                "achieved_GBs": round(gbs, 1), "frac_of_hbm_peak": round(gbs / PEAK_HBM_GBS, 4)}
+
+    out["update_full_i32"] = entry(timed(lambda: A.view_update(col, 3, 1)), 8 * n)
+    out["update_filtered_i32"] = entry(timed(lambda: A.view_update(col, 1, -1, pred=pred, cmp=">",
+                                                                   thr=0)), 12 * n)
+    out["update_full_f32"] = entry(timed(lambda: A.view_update(colf, 1.5, 0.25)), 8 * n)
+    out["scatter_add_i32"] = entry(timed(lambda: A.scatter_add(col, ids, vals)), 16 * m)
+    ws = torch.empty(A.amber_view_scatter_workspace_bytes(A.DT_F32, n, m), dtype=torch.uint8,
+                     device="cuda")
+    out["scatter_add_f32"] = entry(timed(lambda: A.scatter_add(colf, ids, valsf, workspace=ws),
+                                         reps=2), 16 * m)
+    out["scatter_add_f32"]["note"] = ("list order: a stable radix sort of the 2^25 (id, position) "
+                                      "pairs (7 passes of 4 bits at 2^27 rows), then one pass "
+                                      "over the sorted entries")
+    return out
 
 
 def sweep_block(torch, A):

@@ -10,16 +10,23 @@ SRC = os.path.join(HERE, "amber_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
 
-def build(verbose: bool = False) -> str:
+SANITIZE = ["-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+            "-fno-omit-frame-pointer"]
+
+
+def build(verbose: bool = False, sanitize: bool = False, out: str = None) -> str:
+    """liboracle.so; with sanitize, an AddressSanitizer + UndefinedBehavior
+    Sanitizer build (load it with gcc's libasan preloaded) at `out`."""
+    lib = out or (os.path.join(HERE, "liboracle_asan.so") if sanitize else LIB)
     # -ffp-contract=off: no float expression is fused beyond what the source
     # writes (fmaf is called where a fused multiply-add is meant)
     cmd = ["gcc", "-O2", "-std=gnu11", "-Wall", "-Wextra", "-fPIC", "-shared", "-ffp-contract=off",
-           SRC, "-o", LIB + ".tmp", "-lm"]
+           *(SANITIZE if sanitize else []), SRC, "-o", lib + ".tmp", "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(lib + ".tmp", lib)
+    return lib
 
 
 if __name__ == "__main__":

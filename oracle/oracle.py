@@ -18,7 +18,8 @@ import numpy as np
 from . import thresholds
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liboracle.so")
+# AMBER_ORACLE_LIB: another build of the same source (the sanitizer test)
+LIB_PATH = os.environ.get("AMBER_ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 
 WEALTH, RANDOM_WALK, SIR = 0, 1, 2
 P_INIT_POS, P_MOVE, P_EPI, P_RECIPIENT = 0, 1, 2, 3

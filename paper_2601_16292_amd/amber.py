@@ -15,7 +15,8 @@ import os
 import weakref
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libamber.so")
+# AMBER_LIB_PATH: another build of the same sources (the host-sanitizer test)
+LIB_PATH = os.environ.get("AMBER_LIB_PATH") or os.path.join(PKG, "libamber.so")
 
 ABI_VERSION = 1
 MAX_TABLE = 8192
