@@ -61,7 +61,7 @@ void orc_philox4x32_10(const uint32_t ctr_in[4], uint32_t k0, uint32_t k1,
 }
 
 /* Purposes of the random stream and their words per agent. */
-enum { P_INIT_POS = 0, P_MOVE = 1, P_EPI = 2, P_RECIPIENT = 3 };
+enum { P_INIT_POS = 0, P_MOVE = 1, P_EPI = 2, P_RECIPIENT = 3, P_ORDER = 4 };
 
 /* Word j of agent a for purpose p at step t. */
 uint32_t orc_word(uint32_t seed, uint32_t stream, uint32_t purpose,
@@ -403,6 +403,71 @@ void orc_view_scatter_add_f32(uint64_t n, float *col, uint64_t m, const uint32_t
         if (ids[j] >= n) continue;
         col[ids[j]] = col[ids[j]] + (vals ? vals[j] : scalar);
     }
+}
+
+/* Buffered per-agent writes (Sec. 3.2.1: record / update_data calls are kept
+ * in a pending-writes dictionary keyed by agent and flushed once per step by
+ * one update on id): the log entries j = 0..m-1 are applied in log order,
+ * col[ids[j]] = vals[j], so the last write to an id is the one that stays;
+ * ids outside [0, n) are skipped.  Values are copied bit for bit (either
+ * dtype: 4-byte words). */
+void orc_view_write_log(uint64_t n, uint32_t *col, uint64_t m, const uint32_t *ids,
+                        const uint32_t *vals)
+{
+    for (uint64_t j = 0; j < m; j++)
+        if (ids[j] < n) col[ids[j]] = vals[j];
+}
+
+/* ------------------------------------------------- asynchronous semantics */
+
+/* Asynchronous (sequential) updates (Sec. 3.4): within a step the agents act
+ * one after another and each sees what the agents before it did.  The order
+ * of step t is a random permutation: agents sorted by (ORDER word, id),
+ * where agent a's ORDER word is word(seed, stream, ORDER, 1, t, a, 0).
+ * Wealth transfer under this semantics: in that order, an agent whose
+ * current wealth is positive gives one unit to its recipient (the same
+ * RECIPIENT draw as the synchronous model). */
+typedef struct { uint32_t key, id; } orc_order_t;
+
+static int order_cmp(const void *pa, const void *pb)
+{
+    const orc_order_t *a = pa, *b = pb;
+    if (a->key != b->key) return a->key < b->key ? -1 : 1;
+    return a->id < b->id ? -1 : (a->id > b->id ? 1 : 0);
+}
+
+/* The permutation of step t: out[i] = the i-th agent to act. */
+int orc_async_order(uint32_t n, uint32_t seed, uint32_t stream, uint32_t t, uint32_t *out)
+{
+    orc_order_t *o = malloc((size_t)(n ? n : 1) * sizeof(orc_order_t));
+    if (!o) return -1;
+    for (uint32_t a = 0; a < n; a++) {
+        o[a].key = orc_word(seed, stream, P_ORDER, 1, t, a, 0);
+        o[a].id = a;
+    }
+    qsort(o, n, sizeof(orc_order_t), order_cmp);
+    for (uint32_t i = 0; i < n; i++) out[i] = o[i].id;
+    free(o);
+    return 0;
+}
+
+int orc_run_wealth_async(uint32_t n, uint32_t seed, uint32_t stream, uint32_t t0,
+                         uint32_t n_steps, int32_t *w)
+{
+    uint32_t *order = malloc((size_t)(n ? n : 1) * sizeof(uint32_t));
+    if (!order) return -1;
+    for (uint32_t t = t0; t < t0 + n_steps; t++) {
+        if (orc_async_order(n, seed, stream, t, order) != 0) { free(order); return -1; }
+        for (uint32_t i = 0; i < n; i++) {
+            const uint32_t a = order[i];
+            if (w[a] > 0) {
+                w[a] -= 1;
+                w[orc_recipient(n, seed, stream, t, a)] += 1;
+            }
+        }
+    }
+    free(order);
+    return 0;
 }
 
 /* ------------------------------------------------------------ whole runs */

@@ -28,7 +28,8 @@ def philox_block(c, key):
     return c
 
 
-PURPOSE = {"init_pos": (0, 2), "move": (1, 1), "epi": (2, 1), "recipient": (3, 2)}
+PURPOSE = {"init_pos": (0, 2), "move": (1, 1), "epi": (2, 1), "recipient": (3, 2),
+           "order": (4, 1)}
 
 
 def draw(seed, stream, purpose, t, a, j):
@@ -66,6 +67,23 @@ def wealth_run(n, w_init, seed, stream, steps):
             nw[a] -= 1
             nw[r] += 1
         w = nw
+    return w
+
+
+def wealth_run_async(w, seed, stream, t0, steps):
+    """Asynchronous (sequential) semantics, Sec. 3.4: each step the agents act
+    one at a time in the order of their ORDER draws (ties by id), each seeing
+    the wealth as the agents before it left it."""
+    w = list(w)
+    n = len(w)
+    for t in range(t0, t0 + steps):
+        order = sorted(range(n), key=lambda a: (draw(seed, stream, "order", t, a, 0), a))
+        for a in order:
+            if w[a] > 0:
+                u = (draw(seed, stream, "recipient", t, a, 0) << 32) | \
+                    draw(seed, stream, "recipient", t, a, 1)
+                w[a] -= 1
+                w[(u * n) >> 64] += 1
     return w
 
 

@@ -65,6 +65,11 @@ def lib():
                                           ctypes.c_int, _i32, ctypes.c_float]
         L.orc_view_scatter_add_i32.argtypes = [u64, _p, u64, _p, _p, _i32]
         L.orc_view_scatter_add_f32.argtypes = [u64, _p, u64, _p, _p, ctypes.c_float]
+        L.orc_view_write_log.argtypes = [u64, _p, u64, _p, _p]
+        L.orc_async_order.argtypes = [_u32, _u32, _u32, _u32, _p]
+        L.orc_async_order.restype = ctypes.c_int
+        L.orc_run_wealth_async.argtypes = [_u32, _u32, _u32, _u32, _u32, _p]
+        L.orc_run_wealth_async.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -196,6 +201,36 @@ def scatter_add(col, ids, vals=None, scalar=0):
     else:
         raise TypeError("column must be int32 or float32")
     return col
+
+
+def write_log(col, ids, vals):
+    """Buffered writes flushed once: in log order col[ids[j]] = vals[j] (the
+    last write to an id stays); ids outside the column skipped.  int32 or
+    float32 columns, values copied bit for bit.  Returns the updated copy."""
+    col = np.array(col)
+    assert col.dtype in (np.int32, np.float32)
+    ids = np.ascontiguousarray(ids, dtype=np.uint32)
+    vals = np.ascontiguousarray(vals, dtype=col.dtype)
+    assert len(vals) == len(ids)
+    lib().orc_view_write_log(len(col), _ptr(col), len(ids), _ptr(ids), _ptr(vals))
+    return col
+
+
+def async_order(n, seed, stream, t):
+    """The acting order of step t under asynchronous semantics."""
+    out = np.zeros(n, dtype=np.uint32)
+    if lib().orc_async_order(n, seed, stream, t, _ptr(out)) != 0:
+        raise RuntimeError("oracle async_order failed")
+    return out
+
+
+def run_wealth_async(w, seed, stream, t0, n_steps):
+    """Wealth transfer with asynchronous (sequential) updates, steps
+    t0..t0+n_steps-1 from the column w (copied)."""
+    w = np.array(w, dtype=np.int32)
+    if lib().orc_run_wealth_async(len(w), seed, stream, t0, n_steps, _ptr(w)) != 0:
+        raise RuntimeError("oracle run_wealth_async failed")
+    return w
 
 
 # ------------------------------------------------------------------ runs
