@@ -315,6 +315,42 @@ AMBER_API amber_status_t amber_view_scatter_add(void *col, uint32_t dtype, uint6
                                                 void *workspace, size_t workspace_bytes,
                                                 void *hip_stream);
 
+/* The buffered per-agent write path (Sec. 3.2.1: record / update_data calls
+ * kept in a pending-writes dictionary and flushed once per step by one
+ * update on id), as a device write log: entries j = 0 .. m-1 are applied in
+ * log order, col[ids[j]] = vals[j], so the last write to an id stays; ids
+ * >= n are skipped; values are copied bit for bit (int32 or float32 columns
+ * alike).  The entries are ordered by (id, j) with a stable radix sort in the
+ * workspace (amber_view_write_log_workspace_bytes(m) bytes, 16-byte
+ * aligned), then the last entry of each id writes.  Errors as
+ * amber_view_scatter_add. */
+AMBER_API size_t amber_view_write_log_workspace_bytes(uint64_t m);
+AMBER_API amber_status_t amber_view_write_log(void *col, uint32_t dtype, uint64_t n,
+                                              const uint32_t *ids, uint64_t m, const void *vals,
+                                              void *workspace, size_t workspace_bytes,
+                                              void *hip_stream);
+
+/* Asynchronous (sequential) update semantics (Sec. 3.4): within step t the
+ * agents act one at a time and each sees what the agents before it did.  The
+ * order of step t is the agents sorted by (ORDER word, id), the ORDER word of
+ * agent a being word (a mod 4) of the Philox block at counter (floor(a/4),
+ * t, 4, 0).  WEALTH: in that order an agent with positive wealth gives one
+ * unit to its recipient (the RECIPIENT draw of the synchronous model).
+ * RANDOM_WALK: no agent reads another's state, so the step is the
+ * synchronous one.  SIR: AMBER_E_UNSUPPORTED.
+ * The GPU builds the donor set as a fixed point (an agent gives iff it starts
+ * with wealth or a donor acting before it draws it), in at most 64
+ * generations per step, then applies every transfer; a step whose donor set
+ * is not closed by then raises the sticky device error (reported as
+ * AMBER_E_DEVICE by the next synchronising call).  Enqueued on the handle's
+ * stream, no synchronisation; steps t .. t+n_steps-1 as amber_step, and the
+ * two may alternate on one handle.  workspace: caller-owned device memory
+ * of amber_async_workspace_bytes(desc) bytes, 16-byte aligned, free for
+ * other use between calls. */
+AMBER_API size_t amber_async_workspace_bytes(const amber_run_desc_t *desc);
+AMBER_API amber_status_t amber_step_async(amber_pop_t *pop, uint32_t n_steps, void *workspace,
+                                          size_t workspace_bytes);
+
 /* Launch-shape knobs.  They never change results (all arithmetic is integer
  * and every random word is addressed by agent and step), only speed. */
 typedef struct {

@@ -36,7 +36,9 @@ EXPORTED = ["amber_abi_version", "amber_column_bytes", "amber_workspace_bytes",
             "amber_infection_table", "amber_init_population",
             "amber_init_population_noalloc", "amber_resume_population",
             "amber_view_update", "amber_view_scatter_workspace_bytes",
-            "amber_view_scatter_add", "amber_step",
+            "amber_view_scatter_add", "amber_view_write_log_workspace_bytes",
+            "amber_view_write_log", "amber_async_workspace_bytes", "amber_step_async",
+            "amber_step",
             "amber_step_batch", "amber_read_columns", "amber_invariants",
             "amber_pop_info", "amber_set_tuning", "amber_get_tuning",
             "amber_profile_enable", "amber_profile_read",
@@ -164,6 +166,15 @@ def lib():
         L.amber_view_scatter_add.restype = ctypes.c_int
         L.amber_view_scatter_add.argtypes = [P, ctypes.c_uint32, ctypes.c_uint64, P,
                                              ctypes.c_uint64, P, Value, P, ctypes.c_size_t, P]
+        L.amber_view_write_log_workspace_bytes.restype = ctypes.c_size_t
+        L.amber_view_write_log_workspace_bytes.argtypes = [ctypes.c_uint64]
+        L.amber_view_write_log.restype = ctypes.c_int
+        L.amber_view_write_log.argtypes = [P, ctypes.c_uint32, ctypes.c_uint64, P,
+                                           ctypes.c_uint64, P, P, ctypes.c_size_t, P]
+        L.amber_async_workspace_bytes.restype = ctypes.c_size_t
+        L.amber_async_workspace_bytes.argtypes = [ctypes.POINTER(RunDesc)]
+        L.amber_step_async.restype = ctypes.c_int
+        L.amber_step_async.argtypes = [P, ctypes.c_uint32, P, ctypes.c_size_t]
         L.amber_step.restype = ctypes.c_int
         L.amber_step.argtypes = [P, ctypes.c_uint32]
         L.amber_step_batch.restype = ctypes.c_int
@@ -421,6 +432,18 @@ class Population:
         check(amber_step(self.handle, n_steps))
         return self
 
+    def step_async(self, n_steps=1):
+        """Steps under asynchronous (sequential) semantics (amber_step_async);
+        the workspace is allocated with torch on first use."""
+        import torch
+        need = amber_async_workspace_bytes(self.desc)
+        ws = getattr(self, "_async_ws", None)
+        if ws is None or ws.numel() < need:
+            ws = self._async_ws = torch.empty(max(need, 16), dtype=torch.uint8,
+                                              device=self.stream.device)
+        check(amber_step_async(self.handle, n_steps, ws.data_ptr(), ws.numel()))
+        return self
+
     def info(self):
         st, inf = amber_pop_info(self.handle)
         check(st)
@@ -471,6 +494,40 @@ class Population:
             self.release()
         except Exception:
             pass
+
+
+def amber_view_write_log_workspace_bytes(m):
+    return lib().amber_view_write_log_workspace_bytes(m)
+
+
+def amber_view_write_log(col_ptr, dtype, n, ids_ptr, m, vals_ptr, ws_ptr, ws_bytes, stream_ptr):
+    return lib().amber_view_write_log(col_ptr, dtype, n, ids_ptr, m, vals_ptr, ws_ptr, ws_bytes,
+                                      stream_ptr)
+
+
+def amber_async_workspace_bytes(desc):
+    return lib().amber_async_workspace_bytes(ctypes.byref(desc))
+
+
+def amber_step_async(handle, n_steps, ws_ptr, ws_bytes):
+    return lib().amber_step_async(handle, n_steps, ws_ptr, ws_bytes)
+
+
+def write_log(col, ids, vals, stream=None, workspace=None):
+    """Buffered writes flushed once into a device tensor, in log order: the
+    last write to an id stays; ids outside the column are skipped."""
+    import torch
+    st = stream if stream is not None else torch.cuda.current_stream(col.device)
+    dt = _dtype_of(col)
+    m = ids.numel()
+    need = amber_view_write_log_workspace_bytes(m)
+    if m and workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=col.device)
+    check(amber_view_write_log(col.data_ptr(), dt, col.numel(), ids.data_ptr() if m else None, m,
+                               vals.data_ptr() if m else None,
+                               workspace.data_ptr() if workspace is not None else None,
+                               workspace.numel() if workspace is not None else 0, st.cuda_stream))
+    return col
 
 
 def _dtype_of(t):

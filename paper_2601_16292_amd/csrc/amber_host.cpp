@@ -607,6 +607,9 @@ amber_status_t check_device_flag(amber_pop *p, uint32_t flag)
     if (flag & ERR_TILE_LISTS)
         return fail(AMBER_E_DEVICE, "the tiled SIR mode found its record lists out of range; "
                                     "the run's state is invalid");
+    if (flag & ERR_ASYNC_GENERATIONS)
+        return fail(AMBER_E_DEVICE, "an asynchronous wealth step did not close its donor set "
+                                    "within its generations; the run's state is invalid");
     return fail(AMBER_E_DEVICE, "a device-wide barrier of the persistent SIR form timed out; "
                                 "the run's state is invalid");
 }
@@ -1639,6 +1642,11 @@ size_t amber_view_scatter_workspace_bytes(uint32_t dtype, uint64_t n, uint64_t m
     return (size_t)view_scatter_f32_workspace(m);
 }
 
+size_t amber_view_write_log_workspace_bytes(uint64_t m)
+{
+    return m > (1ull << 31) ? 0 : (size_t)view_scatter_f32_workspace(m);
+}
+
 amber_status_t amber_view_scatter_add(void *col, uint32_t dtype, uint64_t n, const uint32_t *ids,
                                       uint64_t m, const void *vals, amber_value_t scalar,
                                       void *workspace, size_t workspace_bytes, void *hip_stream)
@@ -1667,6 +1675,77 @@ amber_status_t amber_view_scatter_add(void *col, uint32_t dtype, uint64_t n, con
     HIP_TRY(launch_view_scatter_add(col, dtype, n, ids, m, vals, sv, workspace,
                                     (hipStream_t)hip_stream),
             "view scatter-add kernels");
+    return AMBER_OK;
+}
+
+size_t amber_async_workspace_bytes(const amber_run_desc_t *desc)
+{
+    Resolved r;
+    if (resolve(desc, r, false) != AMBER_OK) return 0;
+    if (r.model == AMBER_WEALTH) return (size_t)async_wealth_workspace(r.n);
+    return r.model == AMBER_RANDOM_WALK ? 16u : 0u;
+}
+
+amber_status_t amber_step_async(amber_pop_t *pop, uint32_t n_steps, void *workspace,
+                                size_t workspace_bytes)
+{
+    if (!is_live(pop)) return fail(AMBER_E_STATE, "unknown or released handle");
+    const Resolved &r = pop->r;
+    if (r.model == AMBER_SIR)
+        return fail(AMBER_E_UNSUPPORTED, "asynchronous semantics are built for the wealth and "
+                                         "random-walk models only");
+    if (pop->step + n_steps > 0xffffffffull)
+        return fail(AMBER_E_INVALID, "step index would exceed 2^32-1");
+    if (n_steps == 0) return AMBER_OK;
+    if (r.model == AMBER_RANDOM_WALK) {
+        // no agent reads another's state: the sequential step is the
+        // synchronous one
+        return amber_step(pop, n_steps);
+    }
+    const uint64_t need = async_wealth_workspace(r.n);
+    if (!workspace) return fail(AMBER_E_INVALID, "workspace is NULL");
+    if (workspace_bytes < need)
+        return fail(AMBER_E_NOMEM, "workspace has %zu bytes, the asynchronous step needs %llu",
+                    workspace_bytes, (unsigned long long)need);
+    amber_status_t st = check_view_ptr(workspace, pop->device, "workspace", need, 16);
+    if (st != AMBER_OK) return st;
+    HIP_TRY(timed(pop, "wealth_async", [&] {
+                return launch_wealth_async(col_i32(pop, AMBER_COL_WEALTH), r.n, r.seed, r.stream,
+                                           (uint32_t)pop->step, n_steps, workspace,
+                                           (uint32_t *)ws_ptr(pop, ERR_FLAG_OFFSET), pop->stream);
+            }),
+            "asynchronous wealth kernels");
+    const hipError_t te = timer_cut(pop);
+    if (te != hipSuccess) return hip_fail(te, "timing event");
+    pop->step += n_steps;
+    return AMBER_OK;
+}
+
+amber_status_t amber_view_write_log(void *col, uint32_t dtype, uint64_t n, const uint32_t *ids,
+                                    uint64_t m, const void *vals, void *workspace,
+                                    size_t workspace_bytes, void *hip_stream)
+{
+    if (dtype != AMBER_DT_I32 && dtype != AMBER_DT_F32)
+        return fail(AMBER_E_INVALID, "dtype must be AMBER_DT_I32 or AMBER_DT_F32");
+    if (n > 0xffffffffull) return fail(AMBER_E_UNSUPPORTED, "columns of 2^32 rows or more");
+    if (m > (1ull << 31)) return fail(AMBER_E_UNSUPPORTED, "more than 2^31 log entries");
+    if (m == 0) return AMBER_OK;
+    const uint64_t need = view_scatter_f32_workspace(m);
+    if (!workspace) return fail(AMBER_E_INVALID, "workspace is NULL");
+    if (workspace_bytes < need)
+        return fail(AMBER_E_NOMEM, "workspace has %zu bytes, the call needs %llu", workspace_bytes,
+                    (unsigned long long)need);
+    int device = 0;
+    HIP_TRY(hipGetDevice(&device), "hipGetDevice");
+    amber_status_t st = AMBER_OK;
+    if (n && (st = check_view_ptr(col, device, "column", 4 * n, 4)) != AMBER_OK) return st;
+    if ((st = check_view_ptr(ids, device, "ids", 4 * m, 4)) != AMBER_OK) return st;
+    if ((st = check_view_ptr(vals, device, "vals", 4 * m, 4)) != AMBER_OK) return st;
+    if ((st = check_view_ptr(workspace, device, "workspace", need, 16)) != AMBER_OK) return st;
+    if (n == 0) return AMBER_OK;
+    HIP_TRY(launch_view_write_log((uint32_t *)col, n, ids, m, (const uint32_t *)vals, workspace,
+                                  (hipStream_t)hip_stream),
+            "write-log kernels");
     return AMBER_OK;
 }
 

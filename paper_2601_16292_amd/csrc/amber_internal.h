@@ -8,7 +8,7 @@
 namespace amber {
 
 // Purposes of the counter-based random stream (counter word 2).
-enum : uint32_t { P_INIT_POS = 0, P_MOVE = 1, P_EPI = 2, P_RECIPIENT = 3 };
+enum : uint32_t { P_INIT_POS = 0, P_MOVE = 1, P_EPI = 2, P_RECIPIENT = 3, P_ORDER = 4 };
 
 // State codes of the SIR column.
 enum : uint8_t { ST_S = 0, ST_I = 1, ST_R = 2 };
@@ -125,6 +125,23 @@ hipError_t launch_view_update(void *col, uint32_t dtype, uint64_t n, ViewValue a
 hipError_t launch_view_scatter_add(void *col, uint32_t dtype, uint64_t n, const uint32_t *ids,
                                    uint64_t m, const void *vals, ViewValue scalar, void *ws,
                                    hipStream_t st);
+// The write log: in log order col[ids[j]] = vals[j] (last write stays); ws as
+// for the float32 scatter-add.
+hipError_t launch_view_write_log(uint32_t *col, uint64_t n, const uint32_t *ids, uint64_t m,
+                                 const uint32_t *vals, void *ws, hipStream_t st);
+// Stable LSD radix sort of entries j < m by key min(ids[j], n) (n below 2^32;
+// n = 2^32 - 1 sorts the full 32-bit values), carrying j.  ws holds
+// view_scatter_f32_workspace(m) bytes; *keys / *pos receive the sorted
+// arrays inside it.
+hipError_t radix_sort_ids(const uint32_t *ids, uint64_t n, uint64_t m, void *ws, hipStream_t st,
+                          const uint32_t **keys, const uint32_t **pos);
+
+// Asynchronous (sequential) wealth steps t0 .. t0 + n_steps - 1 on the column
+// w; ws holds async_wealth_workspace(n) bytes (16-byte aligned); err is the
+// handle's sticky device error word.
+uint64_t async_wealth_workspace(uint32_t n);
+hipError_t launch_wealth_async(int32_t *w, uint32_t n, uint32_t k0, uint32_t k1, uint32_t t0,
+                               uint32_t n_steps, void *ws, uint32_t *err, hipStream_t st);
 
 // Device workspace of the no-allocation handles: a file-scope device array
 // of NOALLOC_SCRATCH_BYTES per GPU.  noalloc_scratch returns its address on
@@ -226,6 +243,7 @@ struct TileParams {
 // Bits of the sticky device error word at ERR_FLAG_OFFSET.
 constexpr uint32_t ERR_BARRIER = 1u;      // a persistent-form barrier wait gave up
 constexpr uint32_t ERR_TILE_LISTS = 2u;   // tiled mode: record lists out of range
+constexpr uint32_t ERR_ASYNC_GENERATIONS = 4u;   // asynchronous step: donor set not closed
 // Tile count per axis for side T (0 when the grid is too small for it).
 uint32_t sir_tile_count(uint32_t L, uint32_t T);
 // Words of the tiled buffers for grid side L with the smallest tile side.

@@ -256,6 +256,20 @@ __global__ __launch_bounds__(256) void k_segment_add_f32(float *__restrict__ col
     }
 }
 
+// After the sort: the last entry of each id's run (the latest in the log)
+// writes its value.
+__global__ __launch_bounds__(256) void k_write_last(uint32_t *__restrict__ col, uint64_t n,
+                                                    const uint32_t *__restrict__ keys,
+                                                    const uint32_t *__restrict__ pos,
+                                                    const uint32_t *__restrict__ vals, uint64_t m)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < m; k += stride) {
+        const uint32_t id = keys[k];
+        if (id < n && (k + 1 == m || keys[k + 1] != id)) col[id] = vals[pos[k]];
+    }
+}
+
 uint32_t launch_grid(uint64_t items, uint32_t block, uint32_t cap)
 {
     const uint64_t g = (items + block - 1) / block;
@@ -304,16 +318,9 @@ hipError_t launch_view_update(void *col, uint32_t dtype, uint64_t n, ViewValue a
     return hipGetLastError();
 }
 
-hipError_t launch_view_scatter_add(void *col, uint32_t dtype, uint64_t n, const uint32_t *ids,
-                                   uint64_t m, const void *vals, ViewValue scalar, void *ws,
-                                   hipStream_t st)
+hipError_t radix_sort_ids(const uint32_t *ids, uint64_t n, uint64_t m, void *ws, hipStream_t st,
+                          const uint32_t **keys_out, const uint32_t **pos_out)
 {
-    if (m == 0) return hipSuccess;
-    if (dtype == VIEW_I32) {
-        hipLaunchKernelGGL(k_scatter_add_i32, dim3(launch_grid(m, 256, 8192)), dim3(256), 0, st,
-                           (int32_t *)col, n, ids, (const int32_t *)vals, scalar.i, m);
-        return hipGetLastError();
-    }
     const uint32_t blocks = (uint32_t)((m + RS_TILE - 1) / RS_TILE);
     uint32_t *keys[2] = {(uint32_t *)ws, (uint32_t *)ws + m};
     uint32_t *pos[2] = {(uint32_t *)ws + 2 * m, (uint32_t *)ws + 3 * m};
@@ -334,9 +341,38 @@ hipError_t launch_view_scatter_add(void *col, uint32_t dtype, uint64_t n, const 
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    const uint32_t last = (passes - 1) & 1;
+    *keys_out = keys[(passes - 1) & 1];
+    *pos_out = pos[(passes - 1) & 1];
+    return hipSuccess;
+}
+
+hipError_t launch_view_scatter_add(void *col, uint32_t dtype, uint64_t n, const uint32_t *ids,
+                                   uint64_t m, const void *vals, ViewValue scalar, void *ws,
+                                   hipStream_t st)
+{
+    if (m == 0) return hipSuccess;
+    if (dtype == VIEW_I32) {
+        hipLaunchKernelGGL(k_scatter_add_i32, dim3(launch_grid(m, 256, 8192)), dim3(256), 0, st,
+                           (int32_t *)col, n, ids, (const int32_t *)vals, scalar.i, m);
+        return hipGetLastError();
+    }
+    const uint32_t *keys = nullptr, *pos = nullptr;
+    const hipError_t e = radix_sort_ids(ids, n, m, ws, st, &keys, &pos);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_segment_add_f32, dim3(launch_grid(m, 256, 8192)), dim3(256), 0, st,
-                       (float *)col, n, keys[last], pos[last], (const float *)vals, scalar.f, m);
+                       (float *)col, n, keys, pos, (const float *)vals, scalar.f, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_view_write_log(uint32_t *col, uint64_t n, const uint32_t *ids, uint64_t m,
+                                 const uint32_t *vals, void *ws, hipStream_t st)
+{
+    if (m == 0) return hipSuccess;
+    const uint32_t *keys = nullptr, *pos = nullptr;
+    const hipError_t e = radix_sort_ids(ids, n, m, ws, st, &keys, &pos);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_write_last, dim3(launch_grid(m, 256, 8192)), dim3(256), 0, st, col, n,
+                       keys, pos, vals, m);
     return hipGetLastError();
 }
 

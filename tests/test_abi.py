@@ -162,6 +162,22 @@ def test_resume_rejects_states_outside_the_domain(model, bad):
     assert st == A.E_INVALID
 
 
+def test_write_log_and_async_sizes_and_checks():
+    assert A.amber_view_write_log_workspace_bytes(1000) >= 16 * 1000
+    assert A.amber_view_write_log_workspace_bytes((1 << 31) + 1) == 0
+    assert A.amber_view_write_log(0x1000, 5, 10, 0x2000, 10, 0x3000, 0x4000, 1 << 20,
+                                  None) == A.E_INVALID
+    assert A.amber_view_write_log(0x1000, A.DT_I32, 10, 0x2000, 10, 0x3000, None, 0,
+                                  None) == A.E_INVALID
+    assert A.amber_view_write_log(0x1000, A.DT_I32, 10, 0x2000, 10, 0x3000, 0x4000, 8,
+                                  None) == A.E_NOMEM
+    assert A.amber_view_write_log(0x1000, A.DT_I32, 10, None, 0, None, None, 0, None) == A.OK
+    w = A.make_desc(A.WEALTH, 1000)
+    assert A.amber_async_workspace_bytes(w) >= 16 * 1000 + 4 * 4 * 1000
+    assert A.amber_async_workspace_bytes(A.make_desc(A.SIR, 1000)) == 0
+    assert A.amber_async_workspace_bytes(A.make_desc(A.RANDOM_WALK, 1000)) > 0
+
+
 def test_handle_misuse_is_reported():
     import ctypes
     bogus = ctypes.c_void_p(0xdeadbeef)
