@@ -470,6 +470,137 @@ int orc_run_wealth_async(uint32_t n, uint32_t seed, uint32_t stream, uint32_t t0
     return 0;
 }
 
+/* ---------------------------------------------------- spatial environments */
+
+/* Environments of Sec. 4.1: grid lattices of ndim <= 4 dimensions (cell of
+ * coordinates c_0..c_{d-1} is sum c_i * stride_i with stride_0 = 1 and
+ * stride_i = stride_{i-1} * dims_{i-1}; in 2-D that is y * L + x) with Moore
+ * or von Neumann neighbourhoods, torus-wrapped or bounded, and networks
+ * given as adjacency lists (CSR: the neighbours of node i are
+ * col[row[i] .. row[i+1]-1]). */
+
+static int cell_of(uint32_t ndim, const uint32_t *dims, const int32_t *const *pos, uint64_t a,
+                   uint64_t *cell)
+{
+    uint64_t c = 0, stride = 1;
+    for (uint32_t i = 0; i < ndim; i++) {
+        const int32_t v = pos[i][a];
+        if (v < 0 || (uint32_t)v >= dims[i]) return 0;
+        c += (uint64_t)v * stride;
+        stride *= dims[i];
+    }
+    *cell = c;
+    return 1;
+}
+
+/* counts[c] = number of agents a with state[a] == match (every agent when
+ * state is NULL) whose position is cell c; agents off the lattice are not
+ * counted.  counts is overwritten. */
+void orc_grid_count(uint32_t ndim, const uint32_t *dims, uint64_t n, const int32_t *const *pos,
+                    const uint8_t *state, uint32_t match, uint32_t *counts)
+{
+    uint64_t cells = 1;
+    for (uint32_t i = 0; i < ndim; i++) cells *= dims[i];
+    memset(counts, 0, cells * sizeof(uint32_t));
+    for (uint64_t a = 0; a < n; a++) {
+        uint64_t c;
+        if (state && state[a] != match) continue;
+        if (cell_of(ndim, dims, pos, a, &c)) counts[c] += 1;
+    }
+}
+
+/* out[c] = sum of counts over the distinct cells of c's neighbourhood, c
+ * itself included: Moore (every offset in {-1,0,1}^d) or von Neumann (the
+ * offsets with |o_0| + ... + |o_{d-1}| <= 1).  torus: coordinates wrap, and
+ * a cell reached by two offsets (a side below 3) counts once; bounded:
+ * offsets that leave the lattice are dropped. */
+void orc_grid_neighbour_sum(uint32_t ndim, const uint32_t *dims, int von_neumann, int torus_wrap,
+                            const uint32_t *counts, uint32_t *out)
+{
+    uint64_t cells = 1;
+    for (uint32_t i = 0; i < ndim; i++) cells *= dims[i];
+    uint32_t noff = 1;
+    for (uint32_t i = 0; i < ndim; i++) noff *= 3;
+    for (uint64_t c = 0; c < cells; c++) {
+        int64_t co[4];
+        uint64_t rest = c;
+        for (uint32_t i = 0; i < ndim; i++) {
+            co[i] = (int64_t)(rest % dims[i]);
+            rest /= dims[i];
+        }
+        uint64_t seen[81];
+        uint32_t nseen = 0;
+        uint64_t sum = 0;
+        for (uint32_t o = 0; o < noff; o++) {
+            uint32_t code = o, manhattan = 0;
+            int inside = 1;
+            uint64_t nb = 0, stride = 1;
+            for (uint32_t i = 0; i < ndim; i++) {
+                const int64_t d = (int64_t)(code % 3) - 1;
+                code /= 3;
+                manhattan += d != 0;
+                int64_t v = co[i] + d;
+                if (torus_wrap) {
+                    v = ((v % (int64_t)dims[i]) + dims[i]) % dims[i];
+                } else if (v < 0 || v >= (int64_t)dims[i]) {
+                    inside = 0;
+                }
+                nb += (uint64_t)v * stride;
+                stride *= dims[i];
+            }
+            if (!inside || (von_neumann && manhattan > 1)) continue;
+            int dup = 0;
+            for (uint32_t k = 0; k < nseen; k++) if (seen[k] == nb) dup = 1;
+            if (dup) continue;
+            seen[nseen++] = nb;
+            sum += counts[nb];
+        }
+        out[c] = (uint32_t)sum;
+    }
+}
+
+/* out[a] = table[cell of agent a], 0 for an agent off the lattice. */
+void orc_grid_gather(uint32_t ndim, const uint32_t *dims, uint64_t n, const int32_t *const *pos,
+                     const uint32_t *table, uint32_t *out)
+{
+    for (uint64_t a = 0; a < n; a++) {
+        uint64_t c;
+        out[a] = cell_of(ndim, dims, pos, a, &c) ? table[c] : 0;
+    }
+}
+
+/* out[i] = number of neighbours j of node i with state[j] == match, each
+ * adjacency entry counted (a repeated edge counts twice); entries naming a
+ * node outside [0, n) are not counted. */
+void orc_graph_count(uint64_t n, const uint32_t *row, const uint32_t *col, const uint8_t *state,
+                     uint32_t match, uint32_t *out)
+{
+    for (uint64_t i = 0; i < n; i++) {
+        uint32_t k = 0;
+        for (uint32_t e = row[i]; e < row[i + 1]; e++)
+            if (col[e] < n && state[col[e]] == match) k++;
+        out[i] = k;
+    }
+}
+
+/* The SIR transition of step t on its own, given each agent's infected
+ * neighbour count k: S with k >= 1 becomes I iff its EPI word is below
+ * T_inf[min(k, k_sat)], I becomes R iff its EPI word is below T_rec. */
+void orc_sir_transition(uint64_t n, uint8_t *s, const uint32_t *k, uint32_t seed,
+                        uint32_t stream, uint32_t t, const uint32_t *t_inf, uint32_t k_sat,
+                        uint32_t t_rec)
+{
+    for (uint64_t a = 0; a < n; a++) {
+        if (s[a] == S_SUS && k[a] >= 1) {
+            const uint32_t u = orc_word(seed, stream, P_EPI, 1, t, (uint32_t)a, 0);
+            if (u < t_inf[k[a] < k_sat ? k[a] : k_sat]) s[a] = S_INF;
+        } else if (s[a] == S_INF) {
+            const uint32_t u = orc_word(seed, stream, P_EPI, 1, t, (uint32_t)a, 0);
+            if (u < t_rec) s[a] = S_REC;
+        }
+    }
+}
+
 /* ------------------------------------------------------------ whole runs */
 
 /* Run a whole simulation from init for n_steps steps (steps 0..n_steps-1).

@@ -66,6 +66,11 @@ def lib():
         L.orc_view_scatter_add_i32.argtypes = [u64, _p, u64, _p, _p, _i32]
         L.orc_view_scatter_add_f32.argtypes = [u64, _p, u64, _p, _p, ctypes.c_float]
         L.orc_view_write_log.argtypes = [u64, _p, u64, _p, _p]
+        L.orc_grid_count.argtypes = [_u32, _p, u64, _p, _p, _u32, _p]
+        L.orc_grid_neighbour_sum.argtypes = [_u32, _p, ctypes.c_int, ctypes.c_int, _p, _p]
+        L.orc_grid_gather.argtypes = [_u32, _p, u64, _p, _p, _p]
+        L.orc_graph_count.argtypes = [u64, _p, _p, _p, _u32, _p]
+        L.orc_sir_transition.argtypes = [u64, _p, _p, _u32, _u32, _u32, _p, _u32, _u32]
         L.orc_async_order.argtypes = [_u32, _u32, _u32, _u32, _p]
         L.orc_async_order.restype = ctypes.c_int
         L.orc_run_wealth_async.argtypes = [_u32, _u32, _u32, _u32, _u32, _p]
@@ -214,6 +219,60 @@ def write_log(col, ids, vals):
     assert len(vals) == len(ids)
     lib().orc_view_write_log(len(col), _ptr(col), len(ids), _ptr(ids), _ptr(vals))
     return col
+
+
+def _pos_array(pos):
+    pos = [np.ascontiguousarray(p, dtype=np.int32) for p in pos]
+    arr = (ctypes.c_void_p * len(pos))(*[p.ctypes.data for p in pos])
+    return pos, arr
+
+
+def grid_count(dims, pos, state=None, match=1):
+    """Agents per cell of an n-D lattice (cell index with the first axis
+    fastest), counting agents with state == match (all if state is None)."""
+    dims = np.ascontiguousarray(dims, dtype=np.uint32)
+    keep, arr = _pos_array(pos)
+    out = np.zeros(int(np.prod(dims.astype(np.uint64))), dtype=np.uint32)
+    st = None if state is None else np.ascontiguousarray(state, dtype=np.uint8)
+    lib().orc_grid_count(len(dims), _ptr(dims), len(keep[0]), arr, _ptr(st), match, _ptr(out))
+    return out
+
+
+def grid_neighbour_sum(dims, counts, von_neumann=False, torus=True):
+    dims = np.ascontiguousarray(dims, dtype=np.uint32)
+    counts = np.ascontiguousarray(counts, dtype=np.uint32)
+    out = np.zeros_like(counts)
+    lib().orc_grid_neighbour_sum(len(dims), _ptr(dims), int(von_neumann), int(torus),
+                                 _ptr(counts), _ptr(out))
+    return out
+
+
+def grid_gather(dims, pos, table):
+    dims = np.ascontiguousarray(dims, dtype=np.uint32)
+    keep, arr = _pos_array(pos)
+    table = np.ascontiguousarray(table, dtype=np.uint32)
+    out = np.zeros(len(keep[0]), dtype=np.uint32)
+    lib().orc_grid_gather(len(dims), _ptr(dims), len(keep[0]), arr, _ptr(table), _ptr(out))
+    return out
+
+
+def graph_count(row, col, state, match=1):
+    row = np.ascontiguousarray(row, dtype=np.uint32)
+    col = np.ascontiguousarray(col, dtype=np.uint32)
+    state = np.ascontiguousarray(state, dtype=np.uint8)
+    out = np.zeros(len(row) - 1, dtype=np.uint32)
+    lib().orc_graph_count(len(row) - 1, _ptr(row), _ptr(col), _ptr(state), match, _ptr(out))
+    return out
+
+
+def sir_transition(state, k, seed, stream, t, beta=(1, 20), gamma=(1, 100)):
+    s = np.array(state, dtype=np.uint8)
+    k = np.ascontiguousarray(k, dtype=np.uint32)
+    t_inf, k_sat = thresholds.infection_table(*beta)
+    t_inf = np.array(t_inf, dtype=np.uint32)
+    lib().orc_sir_transition(len(s), _ptr(s), _ptr(k), seed, stream, t, _ptr(t_inf), k_sat,
+                             thresholds.recovery_threshold(*gamma))
+    return s
 
 
 def async_order(n, seed, stream, t):

@@ -69,3 +69,49 @@ def served_stream(n_requests=10_000, rate_per_s=50.0, seed=0x5EED_0005, n_lo=1e4
             req["beta"], req["gamma"] = (1, 20), (1, 100)
         reqs.append(req)
     return reqs
+
+
+# -------------------------------------------------------------- networks
+
+def graph_csr(kind, n, seed=0, degree=6, rewire=0.1):
+    """Undirected network of n nodes as CSR arrays (row offsets uint32[n+1],
+    neighbour ids uint32[2 |E|], each edge listed from both ends), for the
+    network environment's three generators: "er" (Erdos-Renyi G(n, M) with
+    M = n * degree / 2 distinct edges), "ws" (Watts-Strogatz: ring lattice of
+    `degree` neighbours, each edge rewired with probability `rewire`), "ba"
+    (Barabasi-Albert, degree / 2 edges per new node).  Generated with
+    NetworkX (the paper's network library) from a fixed seed."""
+    import networkx as nx
+    if kind == "er":
+        g = nx.gnm_random_graph(n, n * degree // 2, seed=seed)
+    elif kind == "ws":
+        g = nx.watts_strogatz_graph(n, degree, rewire, seed=seed)
+    elif kind == "ba":
+        g = nx.barabasi_albert_graph(n, max(1, degree // 2), seed=seed)
+    else:
+        raise ValueError(kind)
+    e = np.array(g.edges(), dtype=np.int64).reshape(-1, 2)
+    src = np.concatenate([e[:, 0], e[:, 1]])
+    dst = np.concatenate([e[:, 1], e[:, 0]])
+    order = np.lexsort((dst, src))
+    src, dst = src[order], dst[order]
+    row = np.zeros(n + 1, dtype=np.uint32)
+    np.add.at(row, src + 1, 1)
+    return np.cumsum(row, dtype=np.uint32), dst.astype(np.uint32)
+
+
+def random_graph_csr(n, degree, seed=0):
+    """A large random multigraph for throughput runs: n * degree / 2 edges
+    with both ends uniform over the nodes (self loops and repeats kept, as
+    adjacency entries), as CSR arrays; numpy's PCG64 from a fixed seed."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    m = n * degree // 2
+    a = rng.integers(0, n, m, dtype=np.int64)
+    b = rng.integers(0, n, m, dtype=np.int64)
+    src = np.concatenate([a, b])
+    dst = np.concatenate([b, a])
+    order = np.argsort(src, kind="stable")
+    src, dst = src[order], dst[order]
+    row = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(row, src + 1, 1)
+    return np.cumsum(row).astype(np.uint32), dst.astype(np.uint32)
