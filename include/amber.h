@@ -351,6 +351,71 @@ AMBER_API size_t amber_async_workspace_bytes(const amber_run_desc_t *desc);
 AMBER_API amber_status_t amber_step_async(amber_pop_t *pop, uint32_t n_steps, void *workspace,
                                           size_t workspace_bytes);
 
+/* ----------------------------------------------------------- environments
+ * The spatial environments of the method (Sec. 4.1) as device primitives:
+ * grid lattices of 1 to AMBER_MAX_DIMS axes with Moore or von Neumann
+ * neighbourhoods, torus-wrapped or bounded, and networks given as CSR
+ * adjacency lists (the neighbours of node i are col[row[i] .. row[i+1]-1]).
+ * A grid cell's index is sum_i pos_i * stride_i with stride_0 = 1 and
+ * stride_i = stride_{i-1} * dims_{i-1} (first axis fastest; in 2-D y*L + x,
+ * the SIR model's count grid).  pos is a host array of ndim device columns
+ * (int32, n rows each); dims a host array.  Device buffers are caller-owned
+ * and on the current device; calls are enqueued on hip_stream and do not
+ * synchronise.  Agents off the lattice (a coordinate outside [0, dims_i))
+ * are neither counted nor looked up.  AMBER_E_INVALID for a bad argument or
+ * a buffer that is NULL, misaligned, not device memory of the current device
+ * or shorter than the call needs (nothing is enqueued); AMBER_E_UNSUPPORTED
+ * for lattices of 2^32 cells or more, 2^32 agents or more. */
+#define AMBER_MAX_DIMS 4u
+typedef enum { AMBER_MOORE = 0, AMBER_VON_NEUMANN = 1 } amber_neighbourhood_t;
+
+/* counts[c] (overwritten) = number of agents a whose cell is c and, when
+ * state is not NULL, whose state[a] == match. */
+AMBER_API amber_status_t amber_grid_count(const int32_t *const *pos, uint32_t ndim,
+                                          const uint32_t *dims, uint64_t n, const uint8_t *state,
+                                          uint32_t match, uint32_t *counts, void *hip_stream);
+
+/* out[c] = sum of counts over the distinct cells of c's neighbourhood, c
+ * included: Moore, every offset in {-1,0,1}^ndim; von Neumann, the offsets
+ * with at most one non-zero component.  torus != 0: coordinates wrap (a side
+ * below 3 reaches a cell twice, which counts once); torus == 0: cells off
+ * the lattice are left out.  out must not alias counts. */
+AMBER_API amber_status_t amber_grid_neighbour_sum(const uint32_t *counts, uint32_t ndim,
+                                                  const uint32_t *dims, uint32_t neighbourhood,
+                                                  uint32_t torus, uint32_t *out,
+                                                  void *hip_stream);
+
+/* out[a] = table[cell of agent a] (0 for an agent off the lattice). */
+AMBER_API amber_status_t amber_grid_gather(const uint32_t *table, const int32_t *const *pos,
+                                           uint32_t ndim, const uint32_t *dims, uint64_t n,
+                                           uint32_t *out, void *hip_stream);
+
+/* Network neighbour query: out[i] = number of adjacency entries j of node i
+ * (i < n) with state[j] == match; a repeated entry counts each time, and
+ * entries past nnz or naming no node (j >= n) are not counted.  row holds
+ * n+1 offsets, col nnz ids. */
+AMBER_API amber_status_t amber_graph_neighbour_count(const uint32_t *row, const uint32_t *col,
+                                                     uint64_t n, uint64_t nnz,
+                                                     const uint8_t *state, uint32_t match,
+                                                     uint32_t *out, void *hip_stream);
+
+/* T_rec = floor(2^32 * gamma) for gamma = gamma_num / gamma_den, computed
+ * exactly (the recovery threshold of the SIR model). */
+AMBER_API amber_status_t amber_recovery_threshold(uint32_t gamma_num, uint32_t gamma_den,
+                                                  uint32_t *out);
+
+/* The SIR transition of step t on its own (Sec. 5.1.2 with exact
+ * thresholds), for SIR variants built from the environment primitives:
+ * given k[a], the infected count agent a sees, an S agent with k >= 1
+ * becomes I iff its EPI word is below t_inf[min(k, table_len-1)], and an I
+ * agent becomes R iff its EPI word is below t_rec; EPI words as in the SIR
+ * model (key (seed, stream_id)).  t_inf: a device copy of the table of
+ * amber_infection_table (table_len = k_sat + 1 entries). */
+AMBER_API amber_status_t amber_sir_transition(uint8_t *state, const uint32_t *k, uint64_t n,
+                                              uint32_t seed, uint32_t stream_id, uint32_t t,
+                                              const uint32_t *t_inf, uint32_t table_len,
+                                              uint32_t t_rec, void *hip_stream);
+
 /* Launch-shape knobs.  They never change results (all arithmetic is integer
  * and every random word is addressed by agent and step), only speed. */
 typedef struct {

@@ -38,6 +38,8 @@ EXPORTED = ["amber_abi_version", "amber_column_bytes", "amber_workspace_bytes",
             "amber_view_update", "amber_view_scatter_workspace_bytes",
             "amber_view_scatter_add", "amber_view_write_log_workspace_bytes",
             "amber_view_write_log", "amber_async_workspace_bytes", "amber_step_async",
+            "amber_grid_count", "amber_grid_neighbour_sum", "amber_grid_gather",
+            "amber_graph_neighbour_count", "amber_sir_transition", "amber_recovery_threshold",
             "amber_step",
             "amber_step_batch", "amber_read_columns", "amber_invariants",
             "amber_pop_info", "amber_set_tuning", "amber_get_tuning",
@@ -175,6 +177,21 @@ def lib():
         L.amber_async_workspace_bytes.argtypes = [ctypes.POINTER(RunDesc)]
         L.amber_step_async.restype = ctypes.c_int
         L.amber_step_async.argtypes = [P, ctypes.c_uint32, P, ctypes.c_size_t]
+        PP = ctypes.POINTER(P)
+        U32P = ctypes.POINTER(ctypes.c_uint32)
+        u32, u64 = ctypes.c_uint32, ctypes.c_uint64
+        L.amber_grid_count.restype = ctypes.c_int
+        L.amber_grid_count.argtypes = [PP, u32, U32P, u64, P, u32, P, P]
+        L.amber_grid_neighbour_sum.restype = ctypes.c_int
+        L.amber_grid_neighbour_sum.argtypes = [P, u32, U32P, u32, u32, P, P]
+        L.amber_grid_gather.restype = ctypes.c_int
+        L.amber_grid_gather.argtypes = [P, PP, u32, U32P, u64, P, P]
+        L.amber_graph_neighbour_count.restype = ctypes.c_int
+        L.amber_graph_neighbour_count.argtypes = [P, P, u64, u64, P, u32, P, P]
+        L.amber_sir_transition.restype = ctypes.c_int
+        L.amber_sir_transition.argtypes = [P, P, u64, u32, u32, u32, P, u32, u32, P]
+        L.amber_recovery_threshold.restype = ctypes.c_int
+        L.amber_recovery_threshold.argtypes = [u32, u32, ctypes.POINTER(ctypes.c_uint32)]
         L.amber_step.restype = ctypes.c_int
         L.amber_step.argtypes = [P, ctypes.c_uint32]
         L.amber_step_batch.restype = ctypes.c_int
@@ -528,6 +545,105 @@ def write_log(col, ids, vals, stream=None, workspace=None):
                                workspace.data_ptr() if workspace is not None else None,
                                workspace.numel() if workspace is not None else 0, st.cuda_stream))
     return col
+
+
+MOORE, VON_NEUMANN = 0, 1
+
+
+def _dims_arr(dims):
+    return (ctypes.c_uint32 * len(dims))(*[int(d) for d in dims])
+
+
+def _pos_arr(pos):
+    return (ctypes.c_void_p * len(pos))(*[p.data_ptr() for p in pos])
+
+
+def amber_grid_count(pos_ptrs, dims, n, state_ptr, match, counts_ptr, stream_ptr):
+    return lib().amber_grid_count((ctypes.c_void_p * len(pos_ptrs))(*pos_ptrs), len(dims),
+                                  _dims_arr(dims), n, state_ptr, match, counts_ptr, stream_ptr)
+
+
+def amber_grid_neighbour_sum(counts_ptr, dims, neighbourhood, torus, out_ptr, stream_ptr):
+    return lib().amber_grid_neighbour_sum(counts_ptr, len(dims), _dims_arr(dims), neighbourhood,
+                                          torus, out_ptr, stream_ptr)
+
+
+def amber_grid_gather(table_ptr, pos_ptrs, dims, n, out_ptr, stream_ptr):
+    return lib().amber_grid_gather(table_ptr, (ctypes.c_void_p * len(pos_ptrs))(*pos_ptrs),
+                                   len(dims), _dims_arr(dims), n, out_ptr, stream_ptr)
+
+
+def amber_graph_neighbour_count(row_ptr, col_ptr, n, nnz, state_ptr, match, out_ptr, stream_ptr):
+    return lib().amber_graph_neighbour_count(row_ptr, col_ptr, n, nnz, state_ptr, match, out_ptr,
+                                             stream_ptr)
+
+
+def amber_sir_transition(state_ptr, k_ptr, n, seed, stream_id, t, t_inf_ptr, table_len, t_rec,
+                         stream_ptr):
+    return lib().amber_sir_transition(state_ptr, k_ptr, n, seed, stream_id, t, t_inf_ptr,
+                                      table_len, t_rec, stream_ptr)
+
+
+def _cur(dev_tensor, stream):
+    import torch
+    return (stream if stream is not None else torch.cuda.current_stream(dev_tensor.device)).cuda_stream
+
+
+def grid_count(dims, pos, state=None, match=1, out=None, stream=None):
+    """Agents per cell of an n-D lattice (device tensors; pos = list of int32
+    columns), counting those with state == match (all if state is None)."""
+    import math
+    import torch
+    cells = math.prod(int(d) for d in dims)
+    out = out if out is not None else torch.empty(cells, dtype=torch.int32, device=pos[0].device)
+    check(amber_grid_count([p.data_ptr() for p in pos], dims, pos[0].numel(),
+                           state.data_ptr() if state is not None else None, match,
+                           out.data_ptr(), _cur(out, stream)))
+    return out
+
+
+def grid_neighbour_sum(dims, counts, neighbourhood=MOORE, torus=True, out=None, stream=None):
+    import torch
+    out = out if out is not None else torch.empty_like(counts)
+    check(amber_grid_neighbour_sum(counts.data_ptr(), dims, neighbourhood, 1 if torus else 0,
+                                   out.data_ptr(), _cur(out, stream)))
+    return out
+
+
+def grid_gather(dims, pos, table, out=None, stream=None):
+    import torch
+    n = pos[0].numel()
+    out = out if out is not None else torch.empty(n, dtype=torch.int32, device=table.device)
+    check(amber_grid_gather(table.data_ptr(), [p.data_ptr() for p in pos], dims, n,
+                            out.data_ptr(), _cur(out, stream)))
+    return out
+
+
+def graph_neighbour_count(row, col, state, match=1, out=None, stream=None):
+    import torch
+    n = row.numel() - 1
+    out = out if out is not None else torch.empty(n, dtype=torch.int32, device=row.device)
+    check(amber_graph_neighbour_count(row.data_ptr(), col.data_ptr() if col.numel() else None, n,
+                                      col.numel(), state.data_ptr(), match, out.data_ptr(),
+                                      _cur(out, stream)))
+    return out
+
+
+def sir_transition(state, k, seed, stream_id, t, beta=(1, 20), gamma=(1, 100), stream=None):
+    """The SIR transition of step t in place on a device uint8 state column,
+    given each agent's infected count k (device int32/uint32)."""
+    import numpy as np
+    import torch
+    st, table, k_sat = amber_infection_table(*beta)
+    check(st)
+    t_rec = ctypes.c_uint32(0)
+    check(lib().amber_recovery_threshold(gamma[0], gamma[1], ctypes.byref(t_rec)))
+    dev_table = torch.from_numpy(np.array(table, dtype=np.uint32).view(np.int32)).to(state.device)
+    check(amber_sir_transition(state.data_ptr(), k.data_ptr(), state.numel(), seed, stream_id, t,
+                               dev_table.data_ptr(), len(table), t_rec.value, _cur(state, stream)))
+    if stream is not None:
+        dev_table.record_stream(stream)     # kept until the kernel on `stream` has read it
+    return state
 
 
 def _dtype_of(t):

@@ -1749,6 +1749,155 @@ amber_status_t amber_view_write_log(void *col, uint32_t dtype, uint64_t n, const
     return AMBER_OK;
 }
 
+namespace {
+// Checks a lattice description and fills g (positions from pos when given).
+amber_status_t grid_desc(const int32_t *const *pos, uint32_t ndim, const uint32_t *dims,
+                         GridDesc &g, uint64_t &cells)
+{
+    if (ndim < 1 || ndim > MAX_DIMS)
+        return fail(AMBER_E_INVALID, "ndim must be 1 .. %u", MAX_DIMS);
+    if (!dims) return fail(AMBER_E_INVALID, "dims is NULL");
+    std::memset(&g, 0, sizeof g);
+    g.ndim = ndim;
+    cells = 1;
+    for (uint32_t i = 0; i < ndim; ++i) {
+        if (dims[i] < 1) return fail(AMBER_E_INVALID, "dims[%u] is 0", i);
+        g.dims[i] = dims[i];
+        g.stride[i] = (uint32_t)cells;
+        cells *= dims[i];
+        if (cells > 0xffffffffull)
+            return fail(AMBER_E_UNSUPPORTED, "lattices of 2^32 cells or more");
+        if (pos) {
+            if (!pos[i]) return fail(AMBER_E_INVALID, "pos[%u] is NULL", i);
+            g.pos[i] = pos[i];
+        }
+    }
+    return AMBER_OK;
+}
+}  // namespace
+
+amber_status_t amber_grid_count(const int32_t *const *pos, uint32_t ndim, const uint32_t *dims,
+                                uint64_t n, const uint8_t *state, uint32_t match,
+                                uint32_t *counts, void *hip_stream)
+{
+    if (!pos) return fail(AMBER_E_INVALID, "pos is NULL");
+    GridDesc g;
+    uint64_t cells = 0;
+    amber_status_t st = grid_desc(pos, ndim, dims, g, cells);
+    if (st != AMBER_OK) return st;
+    if (n > 0xffffffffull) return fail(AMBER_E_UNSUPPORTED, "more than 2^32-1 agents");
+    if (match > 255) return fail(AMBER_E_INVALID, "match must be a state code (0 .. 255)");
+    int device = 0;
+    HIP_TRY(hipGetDevice(&device), "hipGetDevice");
+    if ((st = check_view_ptr(counts, device, "counts", 4 * cells, 4)) != AMBER_OK) return st;
+    if (n) {
+        for (uint32_t i = 0; i < ndim; ++i)
+            if ((st = check_view_ptr(pos[i], device, "position column", 4 * n, 4)) != AMBER_OK)
+                return st;
+        if (state && (st = check_view_ptr(state, device, "state column", n, 1)) != AMBER_OK)
+            return st;
+    }
+    HIP_TRY(launch_grid_count(g, n, state, match, counts, cells, (hipStream_t)hip_stream),
+            "grid count kernels");
+    return AMBER_OK;
+}
+
+amber_status_t amber_grid_neighbour_sum(const uint32_t *counts, uint32_t ndim,
+                                        const uint32_t *dims, uint32_t neighbourhood,
+                                        uint32_t torus, uint32_t *out, void *hip_stream)
+{
+    GridDesc g;
+    uint64_t cells = 0;
+    amber_status_t st = grid_desc(nullptr, ndim, dims, g, cells);
+    if (st != AMBER_OK) return st;
+    if (neighbourhood != AMBER_MOORE && neighbourhood != AMBER_VON_NEUMANN)
+        return fail(AMBER_E_INVALID, "neighbourhood must be AMBER_MOORE or AMBER_VON_NEUMANN");
+    int device = 0;
+    HIP_TRY(hipGetDevice(&device), "hipGetDevice");
+    if ((st = check_view_ptr(counts, device, "counts", 4 * cells, 4)) != AMBER_OK) return st;
+    if ((st = check_view_ptr(out, device, "out", 4 * cells, 4)) != AMBER_OK) return st;
+    if (counts == out) return fail(AMBER_E_INVALID, "out must not be counts");
+    uint32_t dedup = 0;
+    for (uint32_t i = 0; i < ndim; ++i) dedup |= torus && dims[i] < 3;
+    HIP_TRY(launch_grid_neighbour_sum(g, cells, neighbourhood == AMBER_VON_NEUMANN, torus ? 1 : 0,
+                                      dedup, counts, out, (hipStream_t)hip_stream),
+            "grid neighbour kernel");
+    return AMBER_OK;
+}
+
+amber_status_t amber_grid_gather(const uint32_t *table, const int32_t *const *pos, uint32_t ndim,
+                                 const uint32_t *dims, uint64_t n, uint32_t *out,
+                                 void *hip_stream)
+{
+    if (!pos) return fail(AMBER_E_INVALID, "pos is NULL");
+    GridDesc g;
+    uint64_t cells = 0;
+    amber_status_t st = grid_desc(pos, ndim, dims, g, cells);
+    if (st != AMBER_OK) return st;
+    if (n > 0xffffffffull) return fail(AMBER_E_UNSUPPORTED, "more than 2^32-1 agents");
+    if (n == 0) return AMBER_OK;
+    int device = 0;
+    HIP_TRY(hipGetDevice(&device), "hipGetDevice");
+    if ((st = check_view_ptr(table, device, "table", 4 * cells, 4)) != AMBER_OK) return st;
+    if ((st = check_view_ptr(out, device, "out", 4 * n, 4)) != AMBER_OK) return st;
+    for (uint32_t i = 0; i < ndim; ++i)
+        if ((st = check_view_ptr(pos[i], device, "position column", 4 * n, 4)) != AMBER_OK)
+            return st;
+    HIP_TRY(launch_grid_gather(g, n, table, out, (hipStream_t)hip_stream), "grid gather kernel");
+    return AMBER_OK;
+}
+
+amber_status_t amber_graph_neighbour_count(const uint32_t *row, const uint32_t *col, uint64_t n,
+                                           uint64_t nnz, const uint8_t *state, uint32_t match,
+                                           uint32_t *out, void *hip_stream)
+{
+    if (n > 0xffffffffull || nnz > 0xffffffffull)
+        return fail(AMBER_E_UNSUPPORTED, "graphs of 2^32 nodes or adjacency entries or more");
+    if (match > 255) return fail(AMBER_E_INVALID, "match must be a state code (0 .. 255)");
+    if (n == 0) return AMBER_OK;
+    int device = 0;
+    HIP_TRY(hipGetDevice(&device), "hipGetDevice");
+    amber_status_t st = AMBER_OK;
+    if ((st = check_view_ptr(row, device, "row offsets", 4 * (n + 1), 4)) != AMBER_OK) return st;
+    if (nnz && (st = check_view_ptr(col, device, "neighbour ids", 4 * nnz, 4)) != AMBER_OK)
+        return st;
+    if ((st = check_view_ptr(state, device, "state column", n, 1)) != AMBER_OK) return st;
+    if ((st = check_view_ptr(out, device, "out", 4 * n, 4)) != AMBER_OK) return st;
+    HIP_TRY(launch_graph_count(row, col, n, nnz, state, match, out, (hipStream_t)hip_stream),
+            "graph count kernel");
+    return AMBER_OK;
+}
+
+amber_status_t amber_recovery_threshold(uint32_t gamma_num, uint32_t gamma_den, uint32_t *out)
+{
+    if (!out) return fail(AMBER_E_INVALID, "out is NULL");
+    if (gamma_den == 0 || gamma_num >= gamma_den)
+        return fail(AMBER_E_INVALID, "need 0 <= gamma_num < gamma_den");
+    *out = bernoulli_threshold(gamma_num, gamma_den);
+    return AMBER_OK;
+}
+
+amber_status_t amber_sir_transition(uint8_t *state, const uint32_t *k, uint64_t n, uint32_t seed,
+                                    uint32_t stream_id, uint32_t t, const uint32_t *t_inf,
+                                    uint32_t table_len, uint32_t t_rec, void *hip_stream)
+{
+    if (table_len < 1 || table_len > AMBER_MAX_TABLE)
+        return fail(AMBER_E_INVALID, "table_len must be 1 .. %u", AMBER_MAX_TABLE);
+    if (n > 0xffffffffull) return fail(AMBER_E_UNSUPPORTED, "more than 2^32-1 agents");
+    if (n == 0) return AMBER_OK;
+    int device = 0;
+    HIP_TRY(hipGetDevice(&device), "hipGetDevice");
+    amber_status_t st = AMBER_OK;
+    if ((st = check_view_ptr(state, device, "state column", n, 1)) != AMBER_OK) return st;
+    if ((st = check_view_ptr(k, device, "counts", 4 * n, 4)) != AMBER_OK) return st;
+    if ((st = check_view_ptr(t_inf, device, "infection table", 4ull * table_len, 4)) != AMBER_OK)
+        return st;
+    HIP_TRY(launch_sir_transition_only(state, k, n, seed, stream_id, t, t_inf, table_len, t_rec,
+                                       (hipStream_t)hip_stream),
+            "SIR transition kernel");
+    return AMBER_OK;
+}
+
 amber_status_t amber_step(amber_pop_t *pop, uint32_t n_steps)
 {
     if (!is_live(pop)) return fail(AMBER_E_STATE, "unknown or released handle");

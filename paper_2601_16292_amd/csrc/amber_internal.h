@@ -136,6 +136,29 @@ hipError_t launch_view_write_log(uint32_t *col, uint64_t n, const uint32_t *ids,
 hipError_t radix_sort_ids(const uint32_t *ids, uint64_t n, uint64_t m, void *ws, hipStream_t st,
                           const uint32_t **keys, const uint32_t **pos);
 
+// Environments (amber_env.hip): a lattice of ndim <= MAX_DIMS axes, cell
+// index sum pos_i * stride_i with stride_0 = 1 (first axis fastest).
+constexpr uint32_t MAX_DIMS = 4;
+struct GridDesc {
+    const int32_t *pos[MAX_DIMS];
+    uint32_t dims[MAX_DIMS];
+    uint32_t stride[MAX_DIMS];
+    uint32_t ndim;
+};
+// counts (cells words) is overwritten with the agents per cell.
+hipError_t launch_grid_count(const GridDesc &g, uint64_t n, const uint8_t *state, uint32_t match,
+                             uint32_t *counts, uint64_t cells, hipStream_t st);
+hipError_t launch_grid_neighbour_sum(const GridDesc &g, uint64_t cells, uint32_t von_neumann,
+                                     uint32_t torus, uint32_t dedup, const uint32_t *counts,
+                                     uint32_t *out, hipStream_t st);
+hipError_t launch_grid_gather(const GridDesc &g, uint64_t n, const uint32_t *table, uint32_t *out,
+                              hipStream_t st);
+hipError_t launch_graph_count(const uint32_t *row, const uint32_t *col, uint64_t n, uint64_t nnz,
+                              const uint8_t *state, uint32_t match, uint32_t *out, hipStream_t st);
+hipError_t launch_sir_transition_only(uint8_t *s, const uint32_t *k, uint64_t n, uint32_t k0,
+                                      uint32_t k1, uint32_t t, const uint32_t *t_inf,
+                                      uint32_t table_len, uint32_t t_rec, hipStream_t st);
+
 // Asynchronous (sequential) wealth steps t0 .. t0 + n_steps - 1 on the column
 // w; ws holds async_wealth_workspace(n) bytes (16-byte aligned); err is the
 // handle's sticky device error word.
