@@ -61,7 +61,7 @@ void orc_philox4x32_10(const uint32_t ctr_in[4], uint32_t k0, uint32_t k1,
 }
 
 /* Purposes of the random stream and their words per agent. */
-enum { P_INIT_POS = 0, P_MOVE = 1, P_EPI = 2, P_RECIPIENT = 3, P_ORDER = 4 };
+enum { P_INIT_POS = 0, P_MOVE = 1, P_EPI = 2, P_RECIPIENT = 3, P_ORDER = 4, P_STEP = 5 };
 
 /* Word j of agent a for purpose p at step t. */
 uint32_t orc_word(uint32_t seed, uint32_t stream, uint32_t purpose,
@@ -599,6 +599,100 @@ void orc_sir_transition(uint64_t n, uint8_t *s, const uint32_t *k, uint32_t seed
             if (u < t_rec) s[a] = S_REC;
         }
     }
+}
+
+/* ------------------------------------------------------ continuous space */
+
+/* The benchmark models as the paper states them (Sec. 5.1.2): agents in a
+ * continuous W x W world (float32 coordinates in [0, W]).
+ *   init      x = float(u >> 8) * 2^-24 * W and likewise y, from the two
+ *             INIT_POS words of the agent (the product rounds once);
+ *   walk      each step x <- min(max(x + dx, 0), W), y likewise, with
+ *             dx = float(u >> 8) * 2^-23 - 1 (exact, uniform on [-1, 1)) from
+ *             the agent's first STEP word of the step and dy from its second;
+ *   SIR       move as the walk, then every susceptible agent counts the
+ *             agents infected at the start of the step whose post-move
+ *             position lies within distance r:
+ *             (xa - xb)^2 + (ya - yb)^2 <= r^2, evaluated in float32 in that
+ *             order with a rounding after every operation; with k >= 1 it
+ *             becomes infected iff its EPI word is below T_inf[min(k, k_sat)]
+ *             (probability 1 - (1 - p)^k); an infected agent counts one more
+ *             day and recovers once it has counted `recover` days; recovered
+ *             agents stay recovered.  Agents 0..I0-1 start infected, day 0.
+ * The contact search is the all-pairs test the paper describes. */
+
+static float cont_coord(uint32_t u, float W)
+{
+    return (float)(u >> 8) * (1.0f / 16777216.0f) * W;
+}
+
+static float cont_delta(uint32_t u)
+{
+    return (float)(u >> 8) * (1.0f / 8388608.0f) - 1.0f;
+}
+
+static float clampf(float v, float W)
+{
+    return v < 0.0f ? 0.0f : (v > W ? W : v);
+}
+
+void orc_cont_init(uint32_t n, float W, uint32_t seed, uint32_t stream, float *x, float *y)
+{
+    for (uint32_t a = 0; a < n; a++) {
+        x[a] = cont_coord(orc_word(seed, stream, P_INIT_POS, 2, 0, a, 0), W);
+        y[a] = cont_coord(orc_word(seed, stream, P_INIT_POS, 2, 0, a, 1), W);
+    }
+}
+
+static void cont_move(uint32_t n, float W, uint32_t seed, uint32_t stream, uint32_t t, float *x,
+                      float *y)
+{
+    for (uint32_t a = 0; a < n; a++) {
+        x[a] = clampf(x[a] + cont_delta(orc_word(seed, stream, P_STEP, 2, t, a, 0)), W);
+        y[a] = clampf(y[a] + cont_delta(orc_word(seed, stream, P_STEP, 2, t, a, 1)), W);
+    }
+}
+
+void orc_cont_walk(uint32_t n, float W, uint32_t seed, uint32_t stream, uint32_t t0,
+                   uint32_t n_steps, float *x, float *y)
+{
+    for (uint32_t t = t0; t < t0 + n_steps; t++) cont_move(n, W, seed, stream, t, x, y);
+}
+
+int orc_cont_sir(uint32_t n, float W, float r, uint32_t seed, uint32_t stream,
+                 const uint32_t *t_inf, uint32_t k_sat, uint32_t recover, uint32_t t0,
+                 uint32_t n_steps, float *x, float *y, uint8_t *s, uint8_t *days)
+{
+    uint8_t *s0 = malloc(n ? n : 1);
+    if (!s0) return -1;
+    const float r2 = r * r;
+    for (uint32_t t = t0; t < t0 + n_steps; t++) {
+        cont_move(n, W, seed, stream, t, x, y);
+        memcpy(s0, s, n);
+        for (uint32_t a = 0; a < n; a++) {
+            if (s0[a] == S_SUS) {
+                uint32_t k = 0;
+                for (uint32_t b = 0; b < n; b++) {
+                    if (s0[b] != S_INF) continue;
+                    const float dx = x[a] - x[b], dy = y[a] - y[b];
+                    const float dx2 = dx * dx, dy2 = dy * dy;
+                    if (dx2 + dy2 <= r2) k++;
+                }
+                if (k >= 1) {
+                    const uint32_t u = orc_word(seed, stream, P_EPI, 1, t, a, 0);
+                    if (u < t_inf[k < k_sat ? k : k_sat]) {
+                        s[a] = S_INF;
+                        days[a] = 0;
+                    }
+                }
+            } else if (s0[a] == S_INF) {
+                days[a] += 1;
+                if (days[a] >= recover) s[a] = S_REC;
+            }
+        }
+    }
+    free(s0);
+    return 0;
 }
 
 /* ------------------------------------------------------------ whole runs */

@@ -29,7 +29,7 @@ def philox_block(c, key):
 
 
 PURPOSE = {"init_pos": (0, 2), "move": (1, 1), "epi": (2, 1), "recipient": (3, 2),
-           "order": (4, 1)}
+           "order": (4, 1), "step": (5, 2)}
 
 
 def draw(seed, stream, purpose, t, a, j):
@@ -134,3 +134,46 @@ def sir_run(n, L, seed, stream, steps, beta=(1, 20), gamma=(1, 100), i0=None,
             record.append(list(states))
         states = new
     return [ag["x"] for ag in agents], [ag["y"] for ag in agents], states
+
+
+def cont_run(model, n, W, r, seed, stream, steps, p=(1, 10), recover=14, i0=5):
+    """The continuous-space walk ("walk") or SIR ("sir") of Sec. 5.1.2 with
+    numpy float32 scalars (every operation rounds to float32) and an
+    all-pairs contact test written as a distance check per pair."""
+    import numpy as np
+    f = np.float32
+    W = f(W)
+
+    def unit(u, scale):
+        return f(u >> 8) * f(scale)
+
+    xs = [unit(draw(seed, stream, "init_pos", 0, a, 0), 2.0 ** -24) * W for a in range(n)]
+    ys = [unit(draw(seed, stream, "init_pos", 0, a, 1), 2.0 ** -24) * W for a in range(n)]
+    state = [1 if a < i0 else 0 for a in range(n)]
+    days = [0] * n
+    table, k_sat = thresholds.infection_table(*p)
+    r2 = f(r) * f(r)
+    for t in range(steps):
+        for a in range(n):
+            dx = unit(draw(seed, stream, "step", t, a, 0), 2.0 ** -23) - f(1)
+            dy = unit(draw(seed, stream, "step", t, a, 1), 2.0 ** -23) - f(1)
+            xs[a] = min(max(xs[a] + dx, f(0)), W)
+            ys[a] = min(max(ys[a] + dy, f(0)), W)
+        if model == "walk":
+            continue
+        before = list(state)
+        for a in range(n):
+            if before[a] == 0:
+                k = 0
+                for b in range(n):
+                    if before[b] == 1:
+                        ddx, ddy = xs[a] - xs[b], ys[a] - ys[b]
+                        if ddx * ddx + ddy * ddy <= r2:
+                            k += 1
+                if k and draw(seed, stream, "epi", t, a, 0) < table[min(k, k_sat)]:
+                    state[a], days[a] = 1, 0
+            elif before[a] == 1:
+                days[a] += 1
+                if days[a] >= recover:
+                    state[a] = 2
+    return xs, ys, state, days

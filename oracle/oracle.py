@@ -71,6 +71,12 @@ def lib():
         L.orc_grid_gather.argtypes = [_u32, _p, u64, _p, _p, _p]
         L.orc_graph_count.argtypes = [u64, _p, _p, _p, _u32, _p]
         L.orc_sir_transition.argtypes = [u64, _p, _p, _u32, _u32, _u32, _p, _u32, _u32]
+        f32 = ctypes.c_float
+        L.orc_cont_init.argtypes = [_u32, f32, _u32, _u32, _p, _p]
+        L.orc_cont_walk.argtypes = [_u32, f32, _u32, _u32, _u32, _u32, _p, _p]
+        L.orc_cont_sir.argtypes = [_u32, f32, f32, _u32, _u32, _p, _u32, _u32, _u32, _u32, _p, _p,
+                                   _p, _p]
+        L.orc_cont_sir.restype = ctypes.c_int
         L.orc_async_order.argtypes = [_u32, _u32, _u32, _u32, _p]
         L.orc_async_order.restype = ctypes.c_int
         L.orc_run_wealth_async.argtypes = [_u32, _u32, _u32, _u32, _u32, _p]
@@ -273,6 +279,45 @@ def sir_transition(state, k, seed, stream, t, beta=(1, 20), gamma=(1, 100)):
     lib().orc_sir_transition(len(s), _ptr(s), _ptr(k), seed, stream, t, _ptr(t_inf), k_sat,
                              thresholds.recovery_threshold(*gamma))
     return s
+
+
+class ContRun:
+    """The paper's continuous-space models (Sec. 5.1.2) held on the host:
+    model RANDOM_WALK (clamped walk) or SIR (contacts within radius r,
+    probability p per contact, recovery after `recover` days), in a W x W
+    world; float32 coordinates; ``step(k)`` advances steps t..t+k-1."""
+
+    def __init__(self, model, n, W=100.0, r=5.0, seed=0, stream=0, p=(1, 10), recover=14,
+                 initial_infected=5):
+        self.model, self.n, self.W, self.r = model, n, float(W), float(r)
+        self.seed, self.stream, self.recover, self.t = seed, stream, recover, 0
+        self.x = np.zeros(n, dtype=np.float32)
+        self.y = np.zeros(n, dtype=np.float32)
+        lib().orc_cont_init(n, self.W, seed, stream, _ptr(self.x), _ptr(self.y))
+        if model == SIR:
+            self.s = np.zeros(n, dtype=np.uint8)
+            self.s[:initial_infected] = 1
+            self.days = np.zeros(n, dtype=np.uint8)
+            t_inf, self.k_sat = thresholds.infection_table(*p)
+            self.t_inf = np.array(t_inf, dtype=np.uint32)
+
+    def step(self, k=1):
+        if self.model == RANDOM_WALK:
+            lib().orc_cont_walk(self.n, self.W, self.seed, self.stream, self.t, k, _ptr(self.x),
+                                _ptr(self.y))
+        else:
+            rc = lib().orc_cont_sir(self.n, self.W, self.r, self.seed, self.stream,
+                                    _ptr(self.t_inf), self.k_sat, self.recover, self.t, k,
+                                    _ptr(self.x), _ptr(self.y), _ptr(self.s), _ptr(self.days))
+            if rc != 0:
+                raise RuntimeError("oracle cont_sir failed")
+        self.t += k
+        return self
+
+    def columns(self):
+        if self.model == RANDOM_WALK:
+            return [self.x, self.y]
+        return [self.x, self.y, self.s, self.days]
 
 
 def async_order(n, seed, stream, t):

@@ -40,7 +40,8 @@ def test_oracle_under_asan_and_ubsan(tmp_path):
     out = _run({"LD_PRELOAD": asan, "AMBER_ORACLE_LIB": lib},
                ["tests/test_oracle_models.py", "tests/test_oracle_invariants.py",
                 "tests/test_oracle_views.py", "tests/test_oracle_thresholds.py",
-                "tests/test_oracle_async_log.py", "tests/test_oracle_environments.py"])
+                "tests/test_oracle_async_log.py", "tests/test_oracle_environments.py",
+                "tests/test_oracle_continuous.py"])
     assert " passed" in out
 
 
