@@ -416,6 +416,46 @@ AMBER_API amber_status_t amber_sir_transition(uint8_t *state, const uint32_t *k,
                                               const uint32_t *t_inf, uint32_t table_len,
                                               uint32_t t_rec, void *hip_stream);
 
+/* ------------------------------------------------------- continuous space
+ * The paper's own benchmark models (Sec. 5.1.2) in continuous space, on
+ * caller-owned float32 columns x, y (and uint8 state and days for the SIR),
+ * n agents in a W x W world; keys (seed, stream_id) and step indices as for
+ * the grid models.  Every float operation is one IEEE float32 operation
+ * rounded to nearest, in the order written, so results are bit-exact.
+ *   init   x = float(u >> 8) * 2^-24 * W, y likewise (INIT_POS words); SIR:
+ *          agents 0 .. initial_infected-1 infected, the rest susceptible,
+ *          days 0.  state and days both NULL: the walk.
+ *   walk   per step x <- min(max(x + dx, 0), W), y likewise, with
+ *          dx = float(u >> 8) * 2^-23 - 1 from the agent's first STEP word
+ *          of the step (purpose 5, two words per agent) and dy from its
+ *          second.
+ *   SIR    the walk's move; then a susceptible agent counts the agents
+ *          infected at the start of the step within distance r of it,
+ *          (xa - xb)^2 + (ya - yb)^2 <= r^2, and with k >= 1 becomes infected
+ *          iff its EPI word is below floor(2^32 (1 - (1 - p)^k)), p =
+ *          p_num / p_den exactly (the paper: p = 0.1 per contact); an infected
+ *          agent adds a day and recovers at `recover` days (the paper: 14).
+ * The contact search uses a cell list of side r (the infected agents of the
+ * step counting-sorted by cell in the workspace); W / r must stay below
+ * 4096 (AMBER_E_UNSUPPORTED).  Calls are enqueued and do not synchronise,
+ * except that amber_cont_sir builds its threshold table on the host.
+ * AMBER_E_INVALID for bad arguments or short buffers (nothing enqueued). */
+AMBER_API amber_status_t amber_cont_init(float *x, float *y, uint8_t *state, uint8_t *days,
+                                         uint64_t n, float W, uint32_t seed, uint32_t stream_id,
+                                         uint32_t initial_infected, void *hip_stream);
+AMBER_API amber_status_t amber_cont_walk(float *x, float *y, uint64_t n, float W, uint32_t seed,
+                                         uint32_t stream_id, uint32_t t0, uint32_t n_steps,
+                                         void *hip_stream);
+/* Workspace bytes of amber_cont_sir (0 for arguments it would refuse). */
+AMBER_API size_t amber_cont_sir_workspace_bytes(uint64_t n, float W, float r, uint32_t p_num,
+                                                uint32_t p_den);
+AMBER_API amber_status_t amber_cont_sir(float *x, float *y, uint8_t *state, uint8_t *days,
+                                        uint64_t n, float W, float r, uint32_t seed,
+                                        uint32_t stream_id, uint32_t p_num, uint32_t p_den,
+                                        uint32_t recover, uint32_t t0, uint32_t n_steps,
+                                        void *workspace, size_t workspace_bytes,
+                                        void *hip_stream);
+
 /* Launch-shape knobs.  They never change results (all arithmetic is integer
  * and every random word is addressed by agent and step), only speed. */
 typedef struct {

@@ -40,7 +40,8 @@ EXPORTED = ["amber_abi_version", "amber_column_bytes", "amber_workspace_bytes",
             "amber_view_write_log", "amber_async_workspace_bytes", "amber_step_async",
             "amber_grid_count", "amber_grid_neighbour_sum", "amber_grid_gather",
             "amber_graph_neighbour_count", "amber_sir_transition", "amber_recovery_threshold",
-            "amber_step",
+            "amber_cont_init", "amber_cont_walk", "amber_cont_sir_workspace_bytes",
+            "amber_cont_sir", "amber_step",
             "amber_step_batch", "amber_read_columns", "amber_invariants",
             "amber_pop_info", "amber_set_tuning", "amber_get_tuning",
             "amber_profile_enable", "amber_profile_read",
@@ -192,6 +193,16 @@ def lib():
         L.amber_sir_transition.argtypes = [P, P, u64, u32, u32, u32, P, u32, u32, P]
         L.amber_recovery_threshold.restype = ctypes.c_int
         L.amber_recovery_threshold.argtypes = [u32, u32, ctypes.POINTER(ctypes.c_uint32)]
+        f32 = ctypes.c_float
+        L.amber_cont_init.restype = ctypes.c_int
+        L.amber_cont_init.argtypes = [P, P, P, P, u64, f32, u32, u32, u32, P]
+        L.amber_cont_walk.restype = ctypes.c_int
+        L.amber_cont_walk.argtypes = [P, P, u64, f32, u32, u32, u32, u32, P]
+        L.amber_cont_sir_workspace_bytes.restype = ctypes.c_size_t
+        L.amber_cont_sir_workspace_bytes.argtypes = [u64, f32, f32, u32, u32]
+        L.amber_cont_sir.restype = ctypes.c_int
+        L.amber_cont_sir.argtypes = [P, P, P, P, u64, f32, f32, u32, u32, u32, u32, u32, u32, u32,
+                                     P, ctypes.c_size_t, P]
         L.amber_step.restype = ctypes.c_int
         L.amber_step.argtypes = [P, ctypes.c_uint32]
         L.amber_step_batch.restype = ctypes.c_int
@@ -644,6 +655,53 @@ def sir_transition(state, k, seed, stream_id, t, beta=(1, 20), gamma=(1, 100), s
     if stream is not None:
         dev_table.record_stream(stream)     # kept until the kernel on `stream` has read it
     return state
+
+
+class ContRun:
+    """The paper's continuous-space walk (sir=False) or SIR in a W x W world,
+    on device columns allocated with torch; every step runs in the library's
+    kernels (amber_cont_*)."""
+
+    def __init__(self, n, W=100.0, r=5.0, seed=0, stream_id=0, sir=False, p=(1, 10),
+                 recover=14, initial_infected=5, stream=None):
+        import torch
+        self.n, self.W, self.r, self.seed, self.stream_id = n, float(W), float(r), seed, stream_id
+        self.sir, self.p, self.recover, self.t = sir, p, recover, 0
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        dev = self.stream.device
+        self.x = torch.empty(n, dtype=torch.float32, device=dev)
+        self.y = torch.empty(n, dtype=torch.float32, device=dev)
+        self.s = self.days = self.ws = None
+        if sir:
+            self.s = torch.empty(n, dtype=torch.uint8, device=dev)
+            self.days = torch.empty(n, dtype=torch.uint8, device=dev)
+            need = lib().amber_cont_sir_workspace_bytes(n, self.W, self.r, p[0], p[1])
+            if need == 0:
+                raise AmberError(E_INVALID, "continuous SIR arguments refused")
+            self.ws = torch.empty(need, dtype=torch.uint8, device=dev)
+        ptr = lambda t: t.data_ptr() if t is not None else None
+        check(lib().amber_cont_init(self.x.data_ptr(), self.y.data_ptr(), ptr(self.s),
+                                    ptr(self.days), n, self.W, seed, stream_id,
+                                    initial_infected if sir else 0, self.stream.cuda_stream))
+
+    def step(self, k=1):
+        if self.sir:
+            check(lib().amber_cont_sir(self.x.data_ptr(), self.y.data_ptr(), self.s.data_ptr(),
+                                       self.days.data_ptr(), self.n, self.W, self.r, self.seed,
+                                       self.stream_id, self.p[0], self.p[1], self.recover, self.t,
+                                       k, self.ws.data_ptr(), self.ws.numel(),
+                                       self.stream.cuda_stream))
+        else:
+            check(lib().amber_cont_walk(self.x.data_ptr(), self.y.data_ptr(), self.n, self.W,
+                                        self.seed, self.stream_id, self.t, k,
+                                        self.stream.cuda_stream))
+        self.t += k
+        return self
+
+    def read(self):
+        self.stream.synchronize()
+        cols = [self.x, self.y] + ([self.s, self.days] if self.sir else [])
+        return [c.cpu().numpy() for c in cols]
 
 
 def _dtype_of(t):

@@ -11,7 +11,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libamber.so")
 
 SOURCES = ["amber_device.hip", "amber_batch.hip", "amber_tiled.hip", "amber_views.hip",
-           "amber_async.hip", "amber_env.hip", "amber_noalloc.hip", "amber_host.cpp"]
+           "amber_async.hip", "amber_env.hip", "amber_cont.hip", "amber_noalloc.hip",
+           "amber_host.cpp"]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

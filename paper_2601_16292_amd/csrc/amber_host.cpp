@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cstdarg>
 #include <cstdio>
+#include <cmath>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -1895,6 +1896,112 @@ amber_status_t amber_sir_transition(uint8_t *state, const uint32_t *k, uint64_t 
     HIP_TRY(launch_sir_transition_only(state, k, n, seed, stream_id, t, t_inf, table_len, t_rec,
                                        (hipStream_t)hip_stream),
             "SIR transition kernel");
+    return AMBER_OK;
+}
+
+namespace {
+// Cells per axis of the continuous SIR's cell list, 0 when the world does
+// not fit (W / r above CONT_MAX_CELLS).
+constexpr uint32_t CONT_MAX_CELLS = 4096;
+uint32_t cont_cells(float W, float r)
+{
+    if (!(r > 0.0f) || !(W >= 0.0f) || !std::isfinite(W) || !std::isfinite(r)) return 0;
+    const double q = std::floor((double)W / (double)r);
+    return q + 1 > CONT_MAX_CELLS ? 0u : (uint32_t)q + 1;
+}
+}  // namespace
+
+amber_status_t amber_cont_init(float *x, float *y, uint8_t *state, uint8_t *days, uint64_t n,
+                               float W, uint32_t seed, uint32_t stream_id,
+                               uint32_t initial_infected, void *hip_stream)
+{
+    if (n == 0 || n > 0x7fffffffull) return fail(AMBER_E_INVALID, "n must be 1 .. 2^31-1");
+    if (!(W >= 0.0f) || !std::isfinite(W)) return fail(AMBER_E_INVALID, "W must be finite and >= 0");
+    if ((state == nullptr) != (days == nullptr))
+        return fail(AMBER_E_INVALID, "state and days are both given (SIR) or both NULL (walk)");
+    if (state && initial_infected > n)
+        return fail(AMBER_E_INVALID, "initial_infected exceeds n");
+    int device = 0;
+    HIP_TRY(hipGetDevice(&device), "hipGetDevice");
+    amber_status_t st = AMBER_OK;
+    if ((st = check_view_ptr(x, device, "x", 4 * n, 4)) != AMBER_OK) return st;
+    if ((st = check_view_ptr(y, device, "y", 4 * n, 4)) != AMBER_OK) return st;
+    if (state) {
+        if ((st = check_view_ptr(state, device, "state", n, 1)) != AMBER_OK) return st;
+        if ((st = check_view_ptr(days, device, "days", n, 1)) != AMBER_OK) return st;
+    }
+    hipStream_t hs = (hipStream_t)hip_stream;
+    HIP_TRY(launch_cont_init(x, y, (uint32_t)n, W, seed, stream_id, hs), "continuous init kernel");
+    if (state)
+        HIP_TRY(launch_cont_states(state, days, (uint32_t)n, initial_infected, hs),
+                "continuous states kernel");
+    return AMBER_OK;
+}
+
+amber_status_t amber_cont_walk(float *x, float *y, uint64_t n, float W, uint32_t seed,
+                               uint32_t stream_id, uint32_t t0, uint32_t n_steps,
+                               void *hip_stream)
+{
+    if (n == 0 || n > 0x7fffffffull) return fail(AMBER_E_INVALID, "n must be 1 .. 2^31-1");
+    if (!(W >= 0.0f) || !std::isfinite(W)) return fail(AMBER_E_INVALID, "W must be finite and >= 0");
+    if ((uint64_t)t0 + n_steps > 0xffffffffull)
+        return fail(AMBER_E_INVALID, "step index would exceed 2^32-1");
+    if (n_steps == 0) return AMBER_OK;
+    int device = 0;
+    HIP_TRY(hipGetDevice(&device), "hipGetDevice");
+    amber_status_t st = AMBER_OK;
+    if ((st = check_view_ptr(x, device, "x", 4 * n, 4)) != AMBER_OK) return st;
+    if ((st = check_view_ptr(y, device, "y", 4 * n, 4)) != AMBER_OK) return st;
+    HIP_TRY(launch_cont_walk(x, y, (uint32_t)n, W, seed, stream_id, t0, n_steps,
+                             (hipStream_t)hip_stream),
+            "continuous walk kernel");
+    return AMBER_OK;
+}
+
+size_t amber_cont_sir_workspace_bytes(uint64_t n, float W, float r, uint32_t p_num,
+                                      uint32_t p_den)
+{
+    const uint32_t nc = cont_cells(W, r);
+    std::vector<uint32_t> t;
+    if (!nc || n == 0 || n > 0x7fffffffull || build_infection_table(p_num, p_den, t) != AMBER_OK)
+        return 0;
+    return (size_t)cont_sir_workspace((uint32_t)n, nc, (uint32_t)t.size());
+}
+
+amber_status_t amber_cont_sir(float *x, float *y, uint8_t *state, uint8_t *days, uint64_t n,
+                              float W, float r, uint32_t seed, uint32_t stream_id, uint32_t p_num,
+                              uint32_t p_den, uint32_t recover, uint32_t t0, uint32_t n_steps,
+                              void *workspace, size_t workspace_bytes, void *hip_stream)
+{
+    if (n == 0 || n > 0x7fffffffull) return fail(AMBER_E_INVALID, "n must be 1 .. 2^31-1");
+    if (!(W >= 0.0f) || !std::isfinite(W)) return fail(AMBER_E_INVALID, "W must be finite and >= 0");
+    const uint32_t nc = cont_cells(W, r);
+    if (!nc)
+        return fail(!(r > 0.0f) || !std::isfinite(r) ? AMBER_E_INVALID : AMBER_E_UNSUPPORTED,
+                    "r must be finite and > 0, with W / r below %u", CONT_MAX_CELLS);
+    if (recover < 1 || recover > 255) return fail(AMBER_E_INVALID, "recover must be 1 .. 255");
+    if ((uint64_t)t0 + n_steps > 0xffffffffull)
+        return fail(AMBER_E_INVALID, "step index would exceed 2^32-1");
+    std::vector<uint32_t> table;
+    amber_status_t st = build_infection_table(p_num, p_den, table);
+    if (st != AMBER_OK) return st;
+    const uint64_t need = cont_sir_workspace((uint32_t)n, nc, (uint32_t)table.size());
+    if (!workspace) return fail(AMBER_E_INVALID, "workspace is NULL");
+    if (workspace_bytes < need)
+        return fail(AMBER_E_NOMEM, "workspace has %zu bytes, the call needs %llu", workspace_bytes,
+                    (unsigned long long)need);
+    if (n_steps == 0) return AMBER_OK;
+    int device = 0;
+    HIP_TRY(hipGetDevice(&device), "hipGetDevice");
+    if ((st = check_view_ptr(x, device, "x", 4 * n, 4)) != AMBER_OK) return st;
+    if ((st = check_view_ptr(y, device, "y", 4 * n, 4)) != AMBER_OK) return st;
+    if ((st = check_view_ptr(state, device, "state", n, 1)) != AMBER_OK) return st;
+    if ((st = check_view_ptr(days, device, "days", n, 1)) != AMBER_OK) return st;
+    if ((st = check_view_ptr(workspace, device, "workspace", need, 16)) != AMBER_OK) return st;
+    HIP_TRY(launch_cont_sir(x, y, state, days, (uint32_t)n, W, r, nc, seed, stream_id, table.data(),
+                            (uint32_t)table.size(), recover, t0, n_steps, workspace,
+                            (hipStream_t)hip_stream),
+            "continuous SIR kernels");
     return AMBER_OK;
 }
 

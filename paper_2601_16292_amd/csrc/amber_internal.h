@@ -8,7 +8,8 @@
 namespace amber {
 
 // Purposes of the counter-based random stream (counter word 2).
-enum : uint32_t { P_INIT_POS = 0, P_MOVE = 1, P_EPI = 2, P_RECIPIENT = 3, P_ORDER = 4 };
+enum : uint32_t { P_INIT_POS = 0, P_MOVE = 1, P_EPI = 2, P_RECIPIENT = 3, P_ORDER = 4,
+                  P_STEP = 5 };
 
 // State codes of the SIR column.
 enum : uint8_t { ST_S = 0, ST_I = 1, ST_R = 2 };
@@ -158,6 +159,20 @@ hipError_t launch_graph_count(const uint32_t *row, const uint32_t *col, uint64_t
 hipError_t launch_sir_transition_only(uint8_t *s, const uint32_t *k, uint64_t n, uint32_t k0,
                                       uint32_t k1, uint32_t t, const uint32_t *t_inf,
                                       uint32_t table_len, uint32_t t_rec, hipStream_t st);
+
+// Continuous-space walk and SIR (amber_cont.hip); nc = cells per axis of the
+// SIR's cell list (floor(W / r) + 1).
+uint64_t cont_sir_workspace(uint32_t n, uint32_t nc, uint32_t table_len);
+hipError_t launch_cont_init(float *x, float *y, uint32_t n, float W, uint32_t k0, uint32_t k1,
+                            hipStream_t st);
+// SIR states: agents below i0 infected, the rest susceptible, days 0.
+hipError_t launch_cont_states(uint8_t *s, uint8_t *days, uint32_t n, uint32_t i0, hipStream_t st);
+hipError_t launch_cont_walk(float *x, float *y, uint32_t n, float W, uint32_t k0, uint32_t k1,
+                            uint32_t t0, uint32_t n_steps, hipStream_t st);
+hipError_t launch_cont_sir(float *x, float *y, uint8_t *s, uint8_t *days, uint32_t n, float W,
+                           float r, uint32_t nc, uint32_t k0, uint32_t k1, const uint32_t *table,
+                           uint32_t table_len, uint32_t recover, uint32_t t0, uint32_t n_steps,
+                           void *ws, hipStream_t st);
 
 // Asynchronous (sequential) wealth steps t0 .. t0 + n_steps - 1 on the column
 // w; ws holds async_wealth_workspace(n) bytes (16-byte aligned); err is the
