@@ -402,6 +402,55 @@ def roofline_big(torch, A, log2n):
     return res
 
 
+# The paper's Table 1 (AMBER vectorized, Apple Silicon laptop, ms per 50-step
+# run): context only, another machine and its own model variants.
+PAPER_TABLE1_MS = {"wealth": {500: 4.4, 1000: 6.4, 5000: 21.0},
+                   "random_walk": {500: 2.7, 1000: 2.7, 5000: 6.2},
+                   "sir": {500: 95.0, 1000: 119.0, 5000: 687.0}}
+
+
+def paper_models(torch, A, sizes=(500, 1000, 5000), steps=50, reps=20):
+    """The paper's benchmark models at its own sizes (Sec. 5.1.2, 50 steps):
+    wealth transfer, the continuous clamped walk (100 x 100) and the
+    continuous SIR (radius 5, p = 0.1, recovery after 14 days, five
+    infected).  One run = init, 50 steps, result on the host; median of
+    `reps` runs."""
+    import statistics
+    out = {}
+
+    def run_wealth(n):
+        p = A.Population(A.WEALTH, n, wealth_init=1)
+        p.step(steps)
+        p.invariants()
+        p.release()
+
+    def run_cont(n, sir):
+        g = A.ContRun(n, sir=sir)
+        g.step(steps)
+        g.stream.synchronize()
+
+    for name, fn in (("wealth", run_wealth), ("random_walk", lambda n: run_cont(n, False)),
+                     ("sir", lambda n: run_cont(n, True))):
+        out[name] = {}
+        for n in sizes:
+            fn(n)
+            times = []
+            for _ in range(reps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                fn(n)
+                times.append(time.perf_counter() - t0)
+            ms = statistics.median(times) * 1e3
+            out[name][str(n)] = {"ms_per_run": round(ms, 4),
+                                 "agent_steps_per_s": round(n * steps / ms * 1e3, 1),
+                                 "paper_amber_ms": PAPER_TABLE1_MS[name][n]}
+    out["note"] = ("median wall time of a whole run (init, 50 steps, result on the host) on one "
+                   "MI355X; paper_amber_ms is the paper's Table 1 AMBER (vectorized) figure on an "
+                   "Apple Silicon laptop, context only; the wealth rule lets a donor draw itself "
+                   "(the paper's listing), the walk and SIR are the continuous-space models")
+    return out
+
+
 def view_roofline(torch, A, n, m=1 << 25):
     out = {"rows": n, "scatter_entries": m}
     g = torch.Generator(device="cuda").manual_seed(7)
@@ -713,6 +762,7 @@ def main():
 
     if not args.no_extra:
         out["extra"] = extras(torch, A)
+        out["extra"]["paper_models"] = paper_models(torch, A)
         log(f"bench: extra {out['extra']}")
     if not args.no_big:
         h["bufs"] = None
