@@ -18,7 +18,7 @@
 // thread, as one 16-byte access per column when the pointers allow it.
 #include <type_traits>
 
-#include "amber_internal.h"
+#include "amber_device_common.h"
 
 namespace amber {
 namespace {
@@ -161,6 +161,39 @@ __global__ __launch_bounds__(1024) void k_rs_scan(uint32_t *__restrict__ hist, u
     }
 }
 
+// The digit counts of a big sort are scanned in three launches: the sum of
+// every 4096-word tile, a one-workgroup scan of those sums, then each tile's
+// own scan plus its tile's offset.
+constexpr uint32_t SCAN_TILE = 4096;
+
+__global__ __launch_bounds__(1024) void k_scan_tile_sums(const uint32_t *__restrict__ d,
+                                                         uint64_t count, uint32_t *__restrict__ sums)
+{
+    __shared__ uint32_t red[16];
+    const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE;
+    uint32_t s = 0;
+    for (uint32_t i = threadIdx.x; i < SCAN_TILE; i += 1024)
+        if (base + i < count) s += d[base + i];
+    for (uint32_t off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if ((threadIdx.x & 63u) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (uint32_t w = 0; w < 16; ++w) t += red[w];
+        sums[blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_scan_tiles(uint32_t *__restrict__ d, uint64_t count,
+                                                     const uint32_t *__restrict__ offs)
+{
+    const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE;
+    const uint32_t n = (uint32_t)(count - base < SCAN_TILE ? count - base : SCAN_TILE);
+    block_exclusive_scan<1024, SCAN_TILE / 1024>(d + base, d + base, n);
+    const uint32_t add = offs[blockIdx.x];
+    for (uint32_t i = threadIdx.x; i < n; i += 1024) d[base + i] += add;
+}
+
 // Stable scatter of one tile by one digit.  Thread t holds the tile's
 // entries t*8 .. t*8+7 in list order; an entry's destination is the digit's
 // global offset for this tile, plus the entries of that digit held by
@@ -283,7 +316,8 @@ uint32_t launch_grid(uint64_t items, uint32_t block, uint32_t cap)
 uint64_t view_scatter_f32_workspace(uint64_t m)
 {
     const uint64_t blocks = (m + RS_TILE - 1) / RS_TILE;
-    return 16 * m + 4ull * RS_DIGITS * (blocks ? blocks : 1) + 256;
+    const uint64_t counts = RS_DIGITS * (blocks ? blocks : 1);
+    return 16 * m + 4 * counts + 4 * ((counts + SCAN_TILE - 1) / SCAN_TILE) + 256;
 }
 
 namespace {
@@ -325,6 +359,7 @@ hipError_t radix_sort_ids(const uint32_t *ids, uint64_t n, uint64_t m, void *ws,
     uint32_t *keys[2] = {(uint32_t *)ws, (uint32_t *)ws + m};
     uint32_t *pos[2] = {(uint32_t *)ws + 2 * m, (uint32_t *)ws + 3 * m};
     uint32_t *hist = (uint32_t *)ws + 4 * m;
+    uint32_t *tile_sums = hist + (uint64_t)RS_DIGITS * blocks;
     uint32_t bits = 1;                                   // keys lie in [0, n]
     while (bits < 32 && (n >> bits) != 0) ++bits;
     const uint32_t passes = (bits + RS_BITS - 1) / RS_BITS;
@@ -334,8 +369,17 @@ hipError_t radix_sort_ids(const uint32_t *ids, uint64_t n, uint64_t m, void *ws,
         const uint32_t *pin = p ? pos[(p - 1) & 1] : nullptr;
         hipLaunchKernelGGL(k_rs_hist, dim3(blocks), dim3(RS_THREADS), 0, st, kin, ids, n, m, shift,
                            hist);
-        hipLaunchKernelGGL(k_rs_scan, dim3(1), dim3(1024), 0, st, hist,
-                           (uint64_t)RS_DIGITS * blocks);
+        const uint64_t counts = (uint64_t)RS_DIGITS * blocks;
+        if (counts <= SCAN_TILE) {
+            hipLaunchKernelGGL(k_rs_scan, dim3(1), dim3(1024), 0, st, hist, counts);
+        } else {
+            const uint32_t tiles = (uint32_t)((counts + SCAN_TILE - 1) / SCAN_TILE);
+            hipLaunchKernelGGL(k_scan_tile_sums, dim3(tiles), dim3(1024), 0, st, hist, counts,
+                               tile_sums);
+            hipLaunchKernelGGL(k_rs_scan, dim3(1), dim3(1024), 0, st, tile_sums, (uint64_t)tiles);
+            hipLaunchKernelGGL(k_scan_tiles, dim3(tiles), dim3(1024), 0, st, hist, counts,
+                               tile_sums);
+        }
         hipLaunchKernelGGL(k_rs_scatter, dim3(blocks), dim3(RS_THREADS), 0, st, kin, pin, ids, n, m,
                            shift, hist, keys[p & 1], pos[p & 1]);
         const hipError_t e = hipGetLastError();
