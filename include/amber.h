@@ -503,7 +503,13 @@ typedef struct {
                                   1 = global atomic scatter-add, 2 = partition
                                   exchange (recipient ids counting-sorted by
                                   destination in LDS, counted by the owner;
-                                  AMBER_E_UNSUPPORTED above 2^27 agents)         */
+                                  AMBER_E_UNSUPPORTED above 2^27 agents),
+                                  3 = as 2, with the owners of partitions of
+                                  2^15 and 2^16 agents (above 2^24 agents)
+                                  counting in 32-bit words in two passes, the
+                                  form they take by themselves only when one
+                                  agent receives 65536 units in a step (slower;
+                                  below 2^24 agents the same as 2)               */
     uint32_t sir_tile;         /* tiled count mode: tile side 32 or 64 cells
                                   (0 = automatic)                                 */
     uint32_t sir_poll;         /* SIR calls of more than 32 steps in the gather

@@ -90,7 +90,7 @@ class Tuning(ctypes.Structure):
 
 SIR_AUTO, SIR_PIPELINED, SIR_PERSISTENT = 0, 1, 2
 COUNT_AUTO, COUNT_GATHER, COUNT_BOX, COUNT_EXCHANGE, COUNT_TILED, COUNT_TILED_GATHER = 0, 1, 2, 3, 4, 5
-WEALTH_AUTO, WEALTH_ATOMIC, WEALTH_EXCHANGE = 0, 1, 2
+WEALTH_AUTO, WEALTH_ATOMIC, WEALTH_EXCHANGE, WEALTH_EXCHANGE_WIDE = 0, 1, 2, 3
 POLL_NOWAIT, POLL_OFF, POLL_PACED = 0, 1, 2
 
 

@@ -113,13 +113,18 @@ __global__ __launch_bounds__(NT) void k_wealth_x(WealthXParams x, uint32_t t, ui
                                             hist, pcount, poff);
 }
 
-__global__ __launch_bounds__(1024) void k_wealth_x15(WealthXParams x, uint32_t t, uint32_t parity_in,
-                                                     uint32_t mode)
+// The 16-bit form of the exchange (see wealth_exchange_partition16), for
+// partitions of 2^15 and 2^16 agents; mode bit 2 asks for the 32-bit fold.
+template <int XB, int PMAX, int NT>
+__global__ __launch_bounds__(NT) void k_wealth_x16(WealthXParams x, uint32_t t, uint32_t parity_in,
+                                                   uint32_t mode)
 {
-    __shared__ __align__(16) int32_t hist[1u << 15];
-    __shared__ uint32_t buf[WX15_BUF];
-    wealth_exchange_partition15(x, xcd_partition(blockIdx.x, gridDim.x), t, parity_in,
-                                (mode & 1u) != 0, (mode & 2u) != 0, hist, buf);
+    __shared__ __align__(16) uint32_t h2[1u << (XB - 1)];
+    __shared__ uint32_t c32[PMAX + 2];
+    __shared__ uint32_t flag;
+    wealth_exchange_partition16<XB, PMAX, NT>(x, xcd_partition(blockIdx.x, gridDim.x), t,
+                                              parity_in, (mode & 1u) != 0, (mode & 2u) != 0,
+                                              (mode & 4u) != 0, h2, c32, &flag);
 }
 
 // head: move + bin(t).  The gather-mode head also clears demand map 2 and
@@ -608,7 +613,8 @@ uint32_t wealth_exchange_bits(uint32_t n)
     if (n <= (1u << 20)) return 11;            // up to 512 partitions of 2048 agents
     if (n <= (1u << 21)) return 12;            // up to 512 partitions of 4096 agents
     if (n <= (1u << 24)) return 14;            // up to 1024 partitions of 16384 agents
-    if (n <= (1u << 27)) return 15;            // up to 4096 partitions of 32768 agents
+    if (n <= (5u << 23)) return 15;            // up to 1280 partitions of 32768 agents
+    if (n <= (1u << 27)) return 16;            // 641 to 2048 partitions of 65536 agents
     return 0;                                  // too many partitions: atomic path
 }
 
@@ -628,8 +634,13 @@ hipError_t launch_wealth_exchange(const WealthXParams &x, uint32_t t, uint32_t p
         hipLaunchKernelGGL((k_wealth_x<14, 1024, 1024>), dim3(x.P), dim3(1024), 0, st, x, t,
                            parity_in, mode);
     } else if (bits == 15) {
-        if (x.P > WX15_PMAX) return hipErrorInvalidValue;
-        hipLaunchKernelGGL(k_wealth_x15, dim3(x.P), dim3(1024), 0, st, x, t, parity_in, mode);
+        if (x.P > 1280) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_wealth_x16<15, 1280, 1024>), dim3(x.P), dim3(1024), 0, st, x, t,
+                           parity_in, mode);
+    } else if (bits == 16) {
+        if (x.P > 2048) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_wealth_x16<16, 2048, 1024>), dim3(x.P), dim3(1024), 0, st, x, t,
+                           parity_in, mode);
     } else {
         return hipErrorInvalidValue;
     }

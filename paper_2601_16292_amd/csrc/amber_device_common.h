@@ -144,10 +144,10 @@ __device__ __forceinline__ void wealth_fold_group(int4 *__restrict__ base, int4 
 
 // Exclusive prefix sum of in[0..n) into out[0..n) by a workgroup of THREADS
 // threads (a multiple of 64, at most 1024), n <= THREADS * PER (each thread
-// scans up to PER consecutive entries).  in and out may alias.  Ends with a
-// barrier.
-template <uint32_t THREADS, uint32_t PER>
-__device__ __forceinline__ void block_exclusive_scan(const uint32_t *in, uint32_t *out, uint32_t n)
+// scans up to PER consecutive entries); T is a 32- or 16-bit unsigned type
+// whose range holds every sum.  in and out may alias.  Ends with a barrier.
+template <uint32_t THREADS, uint32_t PER, typename T>
+__device__ __forceinline__ void block_exclusive_scan(const T *in, T *out, uint32_t n)
 {
     constexpr uint32_t WAVES = THREADS / 64;
     __shared__ uint32_t wave_total[WAVES];
@@ -183,7 +183,7 @@ __device__ __forceinline__ void block_exclusive_scan(const uint32_t *in, uint32_
 #pragma unroll
     for (uint32_t e = 0; e < PER; ++e) {
         const uint32_t idx = start + e;
-        if (e < per && idx < n) out[idx] = base + part[e];
+        if (e < per && idx < n) out[idx] = (T)(base + part[e]);
     }
     __syncthreads();
 }
@@ -341,54 +341,148 @@ __device__ __forceinline__ void wealth_exchange_partition(const WealthXParams &x
     for (uint32_t d = tid; d < P; d += NT) tab_out[d] = (poff[d] << 16) | pcount[d];
 }
 
-// Partitions of 2^15 agents (populations above 2^24, up to 2^27 agents in
-// 4096 partitions).  The histogram takes 128 KB of LDS; a thread folds up to
-// four sources, and the producer scans its per-destination counts in place
-// (one array of P + 1 words).  buf holds at least WX15_BUF words.
-constexpr uint32_t WX15_PMAX = 4096;
-constexpr uint32_t WX15_BUF = 5120;
-__device__ __forceinline__ void wealth_exchange_partition15(const WealthXParams &x, uint32_t p,
+// The same exchange with 16-bit fold counters and 16-bit records, for
+// partitions of XR = 2^XB agents, XB = 15 or 16 (populations above 2^24).
+// A record is the recipient's index within its destination partition (the
+// segment it sits in names the source, its table entry the destination), so
+// it takes two bytes.  LDS holds
+//   h2[XR / 2]     the fold histogram, two 16-bit counters per word (agent 2i
+//                  in the low half); after the produce loop, the stage of the
+//                  outgoing records;
+//   c32[PMAX + 2]  per-destination counts, then offsets (entry P = total),
+//                  then placement cursors.
+// With 2^16-agent partitions the table has a quarter of the entries of
+// 2^15-agent ones and every owner reads half as many pieces, each twice as
+// long: scattered reads bound the fold, so fewer and longer pieces win.
+//
+// A table entry is off << 16 | (cnt - 1) for a non-empty piece, all ones for
+// an empty one (off + cnt <= XR, so a non-empty piece never encodes as all
+// ones).
+//
+// A 16-bit fold counter wraps only if one agent receives 65536 units in one
+// step.  Every add returns the word's previous value, so a wrap is seen;
+// the owner then clears the histogram and folds again in two passes over
+// half the partition each, with 32-bit counters added into the wealth
+// column (`wide` takes that form from the start).
+//
+// Within one destination the records are placed in the order the LDS
+// atomics grant the cursors; the owner only counts them, so the result does
+// not depend on that order.
+constexpr uint32_t WX16_EMPTY = 0xffffffffu;
+
+// Adds the records of one source's piece [off, end) found in the aligned
+// 8-record window u at position k to the 16-bit histogram; returns nonzero
+// if a counter wrapped.  Branch-free: a record outside the piece adds 0 (to
+// the word its bits name, masked into the partition).
+template <int XB>
+__device__ __forceinline__ uint32_t wealth_fold16_window(uint32_t *h2, const uint4 &u, uint32_t k,
+                                                         uint32_t off, uint32_t end)
+{
+    const uint32_t wd[4] = {u.x, u.y, u.z, u.w};
+    const int32_t lo = (int32_t)(off - k), hi = (int32_t)(end - k);
+    uint32_t wrap = 0;
+#pragma unroll
+    for (int32_t j = 0; j < 8; ++j) {
+        const uint32_t v = (wd[j >> 1] >> (16 * (j & 1))) & ((1u << XB) - 1u);
+        const uint32_t sh = 16 * (v & 1u);
+        const uint32_t one = (j >= lo && j < hi) ? 1u : 0u;
+        const uint32_t old = atomicAdd(&h2[v >> 1], one << sh);
+        wrap |= (((old >> sh) & 0xffffu) + one) >> 16;
+    }
+    return wrap;
+}
+
+// The wide fold: the records of the piece whose index falls in half `half`
+// of the partition, counted in 32-bit words (h32 spans XR / 2 agents).
+template <int XB>
+__device__ __forceinline__ void wealth_fold_wide(uint32_t *h32, const uint16_t *seg, uint32_t off,
+                                                 uint32_t cnt, uint32_t half)
+{
+    const uint32_t end = off + cnt;
+    for (uint32_t k = off; k < end; ++k) {
+        const uint32_t v = seg[k];
+        if ((v >> (XB - 1)) == half) atomicAdd(&h32[v & ((1u << (XB - 1)) - 1u)], 1u);
+    }
+}
+
+template <int XB, int PMAX, int NT>
+__device__ __forceinline__ void wealth_exchange_partition16(const WealthXParams &x, uint32_t p,
                                                             uint32_t t, uint32_t parity_in,
                                                             bool consume, bool produce,
-                                                            int32_t *hist, uint32_t *buf)
+                                                            bool wide, uint32_t *h2,
+                                                            uint32_t *c32, uint32_t *flag)
 {
-    constexpr uint32_t XB = 15, XR = 1u << XB, G = XR / 4096;   // 8 groups per thread
+    constexpr uint32_t XR = 1u << XB;
+    constexpr uint32_t G = XR / (4 * NT);                   // 4-agent groups per thread
+    constexpr uint32_t LPS = 4;                              // lanes per source in the fold
+    constexpr uint32_t SPT = (PMAX + NT / LPS - 1) / (NT / LPS);   // sources per lane
+    static_assert(G >= 1 && XB >= 4 && XB <= 16, "16-bit records");
     const uint32_t tid = threadIdx.x;
     const uint32_t P = x.P;
     const uint32_t groups = groups_of(x.n);
-    // Fold: thread tid takes sources tid, tid + 1024, ... (up to 4).  Their
-    // table entries are loaded before the barrier that orders the histogram
-    // clear, then each source's few records are counted.
+    // Table entries of this partition's sources; the clears happen before
+    // the barrier.
     const uint32_t *tab = x.tab[parity_in];
-    uint32_t e[WX15_PMAX / 1024];
+    uint32_t e[SPT];
 #pragma unroll
-    for (uint32_t c = 0; c < WX15_PMAX / 1024; ++c) {
-        const uint32_t s = c * 1024 + tid;
-        e[c] = consume && s < P ? tab[(size_t)s * P + p] : 0u;
+    for (uint32_t c = 0; c < SPT; ++c) {
+        const uint32_t s = c * (NT / LPS) + tid / LPS;
+        e[c] = consume && s < P ? tab[(size_t)s * P + p] : WX16_EMPTY;
     }
-    for (uint32_t i = tid; i < XR; i += 1024) hist[i] = 0;
+    for (uint32_t i = tid; i < XR / 2; i += NT) h2[i] = 0;
+    for (uint32_t i = tid; i < PMAX + 2; i += NT) c32[i] = 0;
+    if (tid == 0) *flag = 0;
     __syncthreads();
-    if (consume) {
-        const uint32_t *rec = x.rec[parity_in];
-        int32_t *const h = hist - (size_t)p * XR;
+    const uint16_t *rec = (const uint16_t *)x.rec[parity_in];
+    uint32_t wrap = 0;
+    // LPS neighbouring lanes share a source: lane w of them takes the
+    // piece's aligned windows w, w + LPS, ...; their loads fall in the same
+    // lines and are served together.
 #pragma unroll
-        for (uint32_t c = 0; c < WX15_PMAX / 1024; ++c)
-            wealth_fold_source(h, rec + (size_t)(c * 1024 + tid) * XR, e[c] >> 16, e[c] & 0xffffu);
+    for (uint32_t c = 0; c < SPT; ++c) {
+        if (wide || e[c] == WX16_EMPTY) continue;
+        const uint32_t off = e[c] >> 16, end = off + (e[c] & 0xffffu) + 1;
+        const uint16_t *seg = rec + (size_t)(c * (NT / LPS) + tid / LPS) * XR;
+        for (uint32_t k = (off & ~7u) + 8 * (tid % LPS); k < end; k += 8 * LPS)
+            wrap |= wealth_fold16_window<XB>(h2, *(const uint4 *)(seg + k), k, off, end);
     }
+    if (wrap) *flag = 1;
     __syncthreads();
-    uint32_t *pcount = buf;                       // P counts, then P + 1 offsets
-    for (uint32_t i = tid; i <= P; i += 1024) pcount[i] = 0;
-    __syncthreads();
-    uint32_t rcp[G][4], rank[G][4];
+    if (wide || *flag) {               // a counter wrapped (or asked for): 32-bit, by halves
+        for (uint32_t half = 0; half < 2; ++half) {
+            for (uint32_t i = tid; i < XR / 2; i += NT) h2[i] = 0;
+            __syncthreads();
+#pragma unroll
+            for (uint32_t c = 0; c < SPT; ++c)
+                if (e[c] != WX16_EMPTY && tid % LPS == 0)
+                    wealth_fold_wide<XB>(h2, rec + (size_t)(c * (NT / LPS) + tid / LPS) * XR,
+                                         e[c] >> 16, (e[c] & 0xffffu) + 1, half);
+            __syncthreads();
+            for (uint32_t i = tid; i < XR / 8; i += NT) {
+                const uint32_t q = p * (XR / 4) + half * (XR / 8) + i;
+                if (q < groups) {
+                    const int4 W = ((const int4 *)x.w)[q];
+                    ((int4 *)x.w)[q] = make_int4(W.x + (int32_t)h2[4 * i], W.y + (int32_t)h2[4 * i + 1],
+                                                 W.z + (int32_t)h2[4 * i + 2],
+                                                 W.w + (int32_t)h2[4 * i + 3]);
+                }
+            }
+            __syncthreads();
+        }
+        for (uint32_t i = tid; i < XR / 2; i += NT) h2[i] = 0;
+        __syncthreads();
+    }
+    uint32_t rcp[G][4];
 #pragma unroll
     for (uint32_t g = 0; g < G; ++g) {
-        const uint32_t local = g * 1024 + tid;                 // group within the partition
+        const uint32_t local = g * NT + tid;                 // group within the partition
         const uint32_t q = p * (XR / 4) + local;
         int4 V = make_int4(0, 0, 0, 0);
         if (q < groups) {
             const int4 W = ((const int4 *)x.w)[q];
-            V = make_int4(W.x + hist[4 * local], W.y + hist[4 * local + 1],
-                          W.z + hist[4 * local + 2], W.w + hist[4 * local + 3]);
+            const uint2 h = *(const uint2 *)(h2 + 2 * local);
+            V = make_int4(W.x + (int32_t)(h.x & 0xffffu), W.y + (int32_t)(h.x >> 16),
+                          W.z + (int32_t)(h.y & 0xffffu), W.w + (int32_t)(h.y >> 16));
         }
         if (!produce) {
             if (q < groups) ((int4 *)x.w)[q] = V;
@@ -398,34 +492,47 @@ __device__ __forceinline__ void wealth_exchange_partition15(const WealthXParams 
         const int32_t v[4] = {V.x, V.y, V.z, V.w};
         bool d[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            d[j] = q < groups && v[j] > 0 && a + j < x.n;
-            rcp[g][j] = 0xffffffffu;
-        }
-        if (d[0] | d[1]) {
-            const uint4 r = philox(2 * q, t, P_RECIPIENT, x.k0, x.k1);
-            if (d[0]) rcp[g][0] = recipient(r.x, r.y, x.n);
-            if (d[1]) rcp[g][1] = recipient(r.z, r.w, x.n);
-        }
-        if (d[2] | d[3]) {
-            const uint4 r = philox(2 * q + 1, t, P_RECIPIENT, x.k0, x.k1);
-            if (d[2]) rcp[g][2] = recipient(r.x, r.y, x.n);
-            if (d[3]) rcp[g][3] = recipient(r.z, r.w, x.n);
-        }
+        for (int j = 0; j < 4; ++j) d[j] = q < groups && v[j] > 0 && a + j < x.n;
+        // both blocks are drawn whatever the donors (a wavefront nearly always
+        // has a donor in each pair of lanes' agents); no branches
+        const uint4 r0 = philox(2 * q, t, P_RECIPIENT, x.k0, x.k1);
+        rcp[g][0] = d[0] ? recipient(r0.x, r0.y, x.n) : 0xffffffffu;
+        rcp[g][1] = d[1] ? recipient(r0.z, r0.w, x.n) : 0xffffffffu;
+        const uint4 r1 = philox(2 * q + 1, t, P_RECIPIENT, x.k0, x.k1);
+        rcp[g][2] = d[2] ? recipient(r1.x, r1.y, x.n) : 0xffffffffu;
+        rcp[g][3] = d[3] ? recipient(r1.z, r1.w, x.n) : 0xffffffffu;
+        // a non-donor adds 0 to a word of its own lane (no same-word conflicts)
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-            rank[g][j] = d[j] ? atomicAdd(&pcount[rcp[g][j] >> XB], 1u) : 0u;
+            atomicAdd(&c32[d[j] ? rcp[g][j] >> XB : (tid & 63u)], d[j] ? 1u : 0u);
         if (q < groups)
             ((int4 *)x.w)[q] = make_int4(v[0] - d[0], v[1] - d[1], v[2] - d[2], v[3] - d[3]);
+        __builtin_amdgcn_sched_barrier(0);   // one group at a time: fewer live registers
     }
     if (!produce) return;
     __syncthreads();
-    block_exclusive_scan<1024, 5>(pcount, pcount, P + 1);      // counts -> offsets, total last
-    wealth_write_records<G, XB, 1024>(x.rec[parity_in ^ 1u] + (size_t)p * XR, (uint32_t *)hist,
-                                      rcp, rank, pcount, pcount[P]);
+    block_exclusive_scan<NT, (PMAX + NT) / NT>(c32, c32, P + 1);   // entry P: the total
+    const uint32_t n_rec = c32[P];
     uint32_t *tab_out = x.tab[parity_in ^ 1u] + (size_t)p * P;
-    for (uint32_t d = tid; d < P; d += 1024)
-        tab_out[d] = (pcount[d] << 16) | (pcount[d + 1] - pcount[d]);
+    for (uint32_t dd = tid; dd < P; dd += NT) {
+        const uint32_t o = c32[dd], cnt = c32[dd + 1] - o;
+        tab_out[dd] = cnt ? (o << 16) | (cnt - 1) : WX16_EMPTY;
+    }
+    __syncthreads();
+    // place each record at its destination's cursor in the stage (the dead
+    // histogram), then copy the stage out with 16-byte stores; the stage's
+    // words past n_rec are stale and never read
+    uint16_t *stage = (uint16_t *)h2;
+#pragma unroll
+    for (uint32_t g = 0; g < G; ++g)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (rcp[g][j] != 0xffffffffu)
+                stage[atomicAdd(&c32[rcp[g][j] >> XB], 1u)] = (uint16_t)(rcp[g][j] & (XR - 1));
+    __syncthreads();
+    uint16_t *rec_out = (uint16_t *)x.rec[parity_in ^ 1u] + (size_t)p * XR;
+    for (uint32_t i = 8 * tid; i < n_rec; i += 8 * NT)
+        *(uint4 *)(rec_out + i) = *(const uint4 *)(stage + i);
 }
 
 // Small populations: one workgroup runs every step with the wealth column and

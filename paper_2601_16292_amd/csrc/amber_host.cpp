@@ -1044,7 +1044,8 @@ amber_status_t enqueue_steps(amber_pop *p, uint32_t n_steps)
     } else if (r.model == AMBER_WEALTH) {
         int32_t *w = col_i32(p, AMBER_COL_WEALTH);
         const bool exchange = r.xbits != 0 && tu.wealth_form != 1;
-        if (tu.wealth_form == 2 && !exchange)
+        const uint32_t wide = tu.wealth_form == 3 ? 4u : 0u;    // the 32-bit fold throughout
+        if (tu.wealth_form >= 2 && !exchange)
             return fail(AMBER_E_UNSUPPORTED, "the partition-exchange wealth path does not cover "
                                              "%u agents", r.n);
         if (r.n <= wealth_small_max_agents()) {
@@ -1065,13 +1066,13 @@ amber_status_t enqueue_steps(amber_pop *p, uint32_t n_steps)
             x.k1 = r.stream;
             for (uint32_t i = 0; i < n_steps; ++i)
                 HIP_TRY(timed(p, "wealth_exchange", [&] {
-                            return launch_wealth_exchange(x, t0 + i, (i + 1) & 1u, i ? 3u : 2u,
-                                                          r.xbits, st);
+                            return launch_wealth_exchange(x, t0 + i, (i + 1) & 1u,
+                                                          (i ? 3u : 2u) | wide, r.xbits, st);
                         }),
                         "wealth exchange kernel");
             HIP_TRY(timed(p, "wealth_exchange_fold", [&] {
-                        return launch_wealth_exchange(x, t0 + n_steps, (n_steps - 1) & 1u, 1u,
-                                                      r.xbits, st);
+                        return launch_wealth_exchange(x, t0 + n_steps, (n_steps - 1) & 1u,
+                                                      1u | wide, r.xbits, st);
                     }),
                     "wealth exchange fold kernel");
         } else {
@@ -2137,7 +2138,7 @@ amber_status_t amber_set_tuning(amber_pop_t *pop, const amber_tuning_t *t)
         t->max_groups_per_thread != 8)
         return fail(AMBER_E_INVALID, "max_groups_per_thread must be 0, 1, 2, 4 or 8");
     if (t->sir_count > 5) return fail(AMBER_E_INVALID, "sir_count must be in 0 .. 5");
-    if (t->wealth_form > 2) return fail(AMBER_E_INVALID, "wealth_form must be 0, 1 or 2");
+    if (t->wealth_form > 3) return fail(AMBER_E_INVALID, "wealth_form must be 0, 1, 2 or 3");
     if (t->sir_tile != 0 && t->sir_tile != 32 && t->sir_tile != 64)
         return fail(AMBER_E_INVALID, "sir_tile must be 0, 32 or 64");
     if (t->sir_poll != POLL_NOWAIT && t->sir_poll != POLL_OFF && t->sir_poll != POLL_PACED)

@@ -99,7 +99,8 @@ struct Tuning {
     uint32_t sir_count = 0;    // 0 = automatic, 1 = gather 3x3 cells, 2 = box-summed grid,
                                // 3 = exchange (sorted records, per-band counts),
                                // 4 = tiled (tile-sorted working copy, counts in LDS)
-    uint32_t wealth_form = 0;  // 0 = automatic, 1 = atomic scatter, 2 = partition exchange
+    uint32_t wealth_form = 0;  // 0 = automatic, 1 = atomic scatter, 2 = partition exchange,
+                               // 3 = partition exchange with the 32-bit fold
     uint32_t sir_tile = 0;     // tiled mode: tile side 32 or 64 (0 = automatic)
     uint32_t sir_poll = 0;     // gather mode: 0 = poll for the early stop, 1 = never
 };
@@ -208,11 +209,15 @@ uint32_t wealth_small_max_agents();
 // Partition-exchange wealth path: log2 of the partition size for n agents
 // (0 when n is too large for it).  A call of n steps launches mode 2 (take
 // donors) once, mode 3 (fold + take) n-1 times and mode 1 (fold) once, with
-// parity_in = step offset & 1.
+// parity_in = step offset & 1; mode bit 2 makes the 16-bit kernels (2^15 and
+// 2^16 agents per partition) fold with 32-bit counters.
 struct WealthXParams {
     int32_t *w;
-    uint32_t *rec[2];          // P segments of 2^bits recipient ids, per parity
-    uint32_t *tab[2];          // tab[s*P + d] = offset << 16 | count, per parity
+    uint32_t *rec[2];          // P segments of 2^bits records, per parity: recipient ids
+                               // (32-bit), or, for 2^15 and 2^16 agents per partition,
+                               // 16-bit indices within the destination partition
+    uint32_t *tab[2];          // tab[s*P + d] = offset << 16 | count (16-bit kernels:
+                               // offset << 16 | (count - 1), all ones if empty), per parity
     uint32_t n, P, k0, k1;
 };
 uint32_t wealth_exchange_bits(uint32_t n);

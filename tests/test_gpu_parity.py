@@ -342,7 +342,7 @@ def test_block_size_invariance(A, O, model, n, block):
 def test_tuning_validation(A):
     pop = A.Population(A.RANDOM_WALK, 100, L=10)
     for bad in [dict(block=32), dict(block=1088), dict(block=100), dict(sir_form=3),
-                dict(max_groups_per_thread=3), dict(sir_count=6), dict(wealth_form=3),
+                dict(max_groups_per_thread=3), dict(sir_count=6), dict(wealth_form=4),
                 dict(sir_tile=16), dict(sir_tile=48), dict(sir_poll=3)]:
         with pytest.raises(A.AmberError):
             pop.tune(**bad)
@@ -365,15 +365,20 @@ def test_wealth_forms_match_oracle(A, O, n, w0, steps, form):
     assert_same(got, inv, ref, steps)
 
 
-@pytest.mark.parametrize("n,w0,steps,chunks", [((1 << 24) + 12345, 1, 3, [3]),
-                                               ((1 << 25) + 7, 2, 4, [1, 3]),
-                                               (40_000_001, 1, 3, [2, 1])])
-def test_wealth_exchange_above_2p24(A, O, n, w0, steps, chunks):
-    """Partitions of 2^15 agents: more than 1024 partitions (the fold reads
-    its table column in chunks) and the fold-only call boundary."""
-    say(f"case wealth exchange 2^15 partitions n={n} chunks={chunks}")
+@pytest.mark.parametrize("n,w0,steps,chunks,form", [((1 << 24) + 12345, 1, 3, [3], 2),
+                                                    ((1 << 25) + 7, 2, 4, [1, 3], 2),
+                                                    (40_000_001, 1, 3, [2, 1], 2),
+                                                    ((5 << 23) + 1, 1, 2, [2], 2),
+                                                    ((1 << 24) + 12345, 1, 3, [1, 2], 3),
+                                                    ((5 << 23) + 1, 3, 3, [3], 3)])
+def test_wealth_exchange_above_2p24(A, O, n, w0, steps, chunks, form):
+    """Partitions of 2^15 agents (up to 5 * 2^23 agents) and 2^16 agents (above),
+    16-bit records, ragged last partitions, the fold-only call boundary; form
+    3 folds every partition with the 32-bit two-pass counters that a 16-bit
+    counter's wrap would call for."""
+    say(f"case wealth exchange 16-bit kernels n={n} chunks={chunks} form={form}")
     pop = A.Population(A.WEALTH, n, seed=3, stream_id=7, wealth_init=w0)
-    pop.tune(wealth_form=2)
+    pop.tune(wealth_form=form)
     for c in chunks:
         pop.step(c)
     got, inv = pop.read(), pop.invariants()
