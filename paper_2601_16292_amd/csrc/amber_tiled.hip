@@ -269,6 +269,64 @@ __global__ void __launch_bounds__(1024) k_tile_step(TileParams p, StepIO io, uin
         for (uint32_t k = tid; k < RW * RW; k += NT) hist[k] = 0;
         for (uint32_t k = tid; k < nw * 9; k += NT) wcnt[k] = 0;
     }
+    // The previous step's counts (the tile and its ring) and the ring partial
+    // counts around it do not depend on the headers: their loads go out
+    // together with the header loads, the counts into LDS before the
+    // barrier, the first RING_PRE ring words of each thread into registers
+    // (added after the first pass, once every count is in place).
+    constexpr uint32_t RING_PRE = 4;
+    uint32_t ring_v[RING_PRE], ring_dst[RING_PRE];
+    const uint32_t wl = li + 1 == nT ? last : T, wr = ri + 1 == nT ? last : T;
+    const uint32_t hu = uj + 1 == nT ? last : T, hd = dj + 1 == nT ? last : T;
+    const uint32_t ring_total = 2 * (w + 2) + 2 * h + 2 * h + 2 * (w + 2) + 24;
+    if (TRANS) {
+#pragma unroll
+        for (uint32_t i = 0; i < RING_PRE; ++i) {
+            const uint32_t k = tid + i * NT;
+            ring_v[i] = 0;
+            ring_dst[i] = 0;
+            if (k < ring_total) {
+                const RingSeg e = ring_entry<RW>(io.ring_in, p.rs, nT, k, ti, tj, li, ri, uj,
+                                                 dj, w, h, wl, wr, hu, hd);
+                ring_v[i] = *e.src;
+                ring_dst[i] = e.dst;
+            }
+        }
+        // rows by wavefront, CROWS rows' loads in flight before their stores;
+        // a row is at most T + 3 <= 67 cells: lanes take cells lane and
+        // lane + 64
+        static_assert(T + 3 <= 128, "two cells per lane per row");
+        constexpr uint32_t CROWS = 8;
+        const uint32_t *C = io.C_in;
+        int32_t gxa = x0 + (int32_t)lane - 1, gxb = gxa + 64;
+        gxa = gxa < 0 ? gxa + p.L : (gxa >= p.L ? gxa - p.L : gxa);
+        gxb = gxb >= p.L ? gxb - p.L : gxb;
+        const bool has_a = lane < w + 2, has_b = lane + 64 < w + 2;
+        for (uint32_t r0 = wave; r0 < h + 2; r0 += CROWS * nw) {
+            uint32_t va[CROWS], vb[CROWS];
+#pragma unroll
+            for (uint32_t k = 0; k < CROWS; ++k) {
+                const uint32_t ry = r0 + k * nw;
+                va[k] = 0;
+                vb[k] = 0;
+                if (ry < h + 2) {
+                    int32_t gy = y0 + (int32_t)ry - 1;
+                    gy = gy < 0 ? gy + p.L : (gy >= p.L ? gy - p.L : gy);
+                    const uint32_t *row = C + (size_t)gy * (uint32_t)p.L;
+                    if (has_a) va[k] = row[gxa];
+                    if (has_b) vb[k] = row[gxb];
+                }
+            }
+#pragma unroll
+            for (uint32_t k = 0; k < CROWS; ++k) {
+                const uint32_t ry = r0 + k * nw;
+                if (ry < h + 2) {
+                    if (has_a) reg[ry * RW + lane] = va[k];
+                    if (has_b) reg[ry * RW + lane + 64] = vb[k];
+                }
+            }
+        }
+    }
     __syncthreads();
 
     // chunk prefix (every thread) and its check: the chunks must lie inside
@@ -322,20 +380,6 @@ __global__ void __launch_bounds__(1024) k_tile_step(TileParams p, StepIO io, uin
         s_store = store;
         if (tile == 0) *io.ovf_reset = 0;      // overflow allocator of the next launch
     }
-    if (TRANS) {
-        // counts of the tile and its ring, rows by wavefront
-        const uint32_t *C = io.C_in;
-        for (uint32_t ry = wave; ry < h + 2; ry += nw) {
-            int32_t gy = y0 + (int32_t)ry - 1;
-            gy = gy < 0 ? gy + p.L : (gy >= p.L ? gy - p.L : gy);
-            const uint32_t *row = C + (size_t)gy * (uint32_t)p.L;
-            for (uint32_t rx = lane; rx < w + 2; rx += 64) {
-                int32_t gx = x0 + (int32_t)rx - 1;
-                gx = gx < 0 ? gx + p.L : (gx >= p.L ? gx - p.L : gx);
-                reg[ry * RW + rx] = row[gx];
-            }
-        }
-    }
 
     const uint32_t round_cap = NT * STEP_MAXA;
     const bool one = n_in <= round_cap;
@@ -388,11 +432,12 @@ __global__ void __launch_bounds__(1024) k_tile_step(TileParams p, StepIO io, uin
     __syncthreads();
 
     if (TRANS) {
-        // ring partial counts that land on the tile or its ring
-        const uint32_t wl = li + 1 == nT ? last : T, wr = ri + 1 == nT ? last : T;
-        const uint32_t hu = uj + 1 == nT ? last : T, hd = dj + 1 == nT ? last : T;
-        const uint32_t total = 2 * (w + 2) + 2 * h + 2 * h + 2 * (w + 2) + 24;
-        for (uint32_t k = tid; k < total; k += NT) {
+        // ring partial counts that land on the tile or its ring: the words
+        // loaded before the first barrier, then any beyond them
+#pragma unroll
+        for (uint32_t i = 0; i < RING_PRE; ++i)
+            if (ring_v[i]) atomicAdd(&reg[ring_dst[i]], ring_v[i]);
+        for (uint32_t k = tid + RING_PRE * NT; k < ring_total; k += NT) {
             const RingSeg e = ring_entry<RW>(io.ring_in, p.rs, nT, k, ti, tj, li, ri, uj,
                                              dj, w, h, wl, wr, hu, hd);
             const uint32_t v = *e.src;
@@ -455,8 +500,7 @@ __global__ void __launch_bounds__(1024) k_tile_step(TileParams p, StepIO io, uin
     const bool store = s_store != 0;
     const uint32_t fix = tile * p.cap, ovf = s_ovf;
     uint2 *out = io.rec_out;
-    const uint32_t wl = li + 1 == nT ? last : T;   // width of the tile to the left
-    const uint32_t hb = uj + 1 == nT ? last : T;   // height of the tile above
+    const uint32_t hb = hu;                         // height of the tile above
     uint32_t *mine = wbase + wave * 9;
     uint32_t stay_run = mine[STAY];
     uint32_t wsus = 0;                              // susceptible records of this wavefront
