@@ -113,10 +113,13 @@ __device__ __forceinline__ uint32_t move_of(const TileParams &p, uint32_t id, ui
 // Transition of step t_prev for an agent at local (lx, ly) of the tile, with
 // the previous step's counts of the tile and its ring in reg (row stride RW,
 // cell (lx, ly) at (ly + 1) * RW + lx + 1).
+// The first TINF_LDS thresholds are read from an LDS copy (tinf), the rest
+// from the table in memory.
+constexpr uint32_t TINF_LDS = 64;
 template <uint32_t RW>
 __device__ __forceinline__ uint32_t tile_transition(const TileParams &p, const uint32_t *reg,
-                                                    uint32_t id, uint32_t s, uint32_t lx,
-                                                    uint32_t ly, uint32_t t_prev)
+                                                    const uint32_t *tinf, uint32_t id, uint32_t s,
+                                                    uint32_t lx, uint32_t ly, uint32_t t_prev)
 {
     if (s == ST_R) return s;
     uint32_t k = 0;
@@ -128,8 +131,8 @@ __device__ __forceinline__ uint32_t tile_transition(const TileParams &p, const u
     }
     const uint32_t u = word_of(philox(id >> 2, t_prev, P_EPI, p.k0, p.k1), id & 3u);
     if (s == ST_S) {
-        const uint32_t kl = p.table_len - 1;
-        return u < p.t_inf[k < kl ? k : kl] ? (uint32_t)ST_I : (uint32_t)ST_S;
+        const uint32_t kl = p.table_len - 1, kk = k < kl ? k : kl;
+        return u < (kk < TINF_LDS ? tinf[kk] : p.t_inf[kk]) ? (uint32_t)ST_I : (uint32_t)ST_S;
     }
     return u < p.t_rec ? (uint32_t)ST_R : (uint32_t)ST_I;
 }
@@ -232,6 +235,7 @@ __global__ void __launch_bounds__(1024) k_tile_step(TileParams p, StepIO io, uin
     __shared__ uint32_t wbase[MOVE ? MAXW * 9 : 1];// per-wavefront group bases
     __shared__ uint32_t c_start[9], c_fix[9], c_ovf[9], c_cnt[9], gtot[9];
     __shared__ uint32_t s_ovf, s_store, s_sus;
+    __shared__ uint32_t tinf[TRANS ? TINF_LDS : 1];   // first thresholds of the table
     const uint32_t tid = threadIdx.x, NT = blockDim.x;
     const uint32_t lane = tid & 63u, nw = NT >> 6;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wavefront-uniform
@@ -269,6 +273,7 @@ __global__ void __launch_bounds__(1024) k_tile_step(TileParams p, StepIO io, uin
         for (uint32_t k = tid; k < RW * RW; k += NT) hist[k] = 0;
         for (uint32_t k = tid; k < nw * 9; k += NT) wcnt[k] = 0;
     }
+    if (TRANS && tid < TINF_LDS && tid < p.table_len) tinf[tid] = p.t_inf[tid];
     // The previous step's counts (the tile and its ring) and the ring partial
     // counts around it do not depend on the headers: their loads go out
     // together with the header loads, the counts into LDS before the
@@ -347,7 +352,8 @@ __global__ void __launch_bounds__(1024) k_tile_step(TileParams p, StepIO io, uin
     if (!ok && tid == 0)
         __hip_atomic_fetch_or(p.err, ERR_TILE_LISTS, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const uint2 *in = io.rec_in;
-    auto load = [&](uint32_t v) {
+    // slot of entry v of the tile's input (the 9 chunks one after another)
+    auto slot_of = [&](uint32_t v) {
         uint32_t d = STAY, pd = pre[STAY];
         if (v < pre[STAY] || v >= pre[STAY + 1]) {   // a record that moved in (few)
             d = 0;
@@ -359,7 +365,7 @@ __global__ void __launch_bounds__(1024) k_tile_step(TileParams p, StepIO io, uin
                     pd = pre[k];
                 }
         }
-        return in[rec_slot(c_start[d] + (v - pd), p.cap, c_fix[d], c_ovf[d])];
+        return rec_slot(c_start[d] + (v - pd), p.cap, c_fix[d], c_ovf[d]);
     };
 
     if (MOVE && tid == 0) {
@@ -384,15 +390,22 @@ __global__ void __launch_bounds__(1024) k_tile_step(TileParams p, StepIO io, uin
     const uint32_t round_cap = NT * STEP_MAXA;
     const bool one = n_in <= round_cap;
     uint32_t rid[STEP_MAXA], rpk[STEP_MAXA], rmv[STEP_MAXA];
+    // Every slot first, then every load, unconditionally (an entry past the
+    // input reads slot 0 and is never used): the round's loads are then in
+    // flight together.  Loads under a branch each waited for all earlier
+    // ones.
     auto fetch = [&](uint32_t r0) {
+        uint32_t slot[STEP_MAXA];
 #pragma unroll
         for (uint32_t j = 0; j < STEP_MAXA; ++j) {
             const uint32_t v = r0 + j * NT + tid;
-            if (v < n_in) {
-                const uint2 r = load(v);
-                rid[j] = r.x;
-                rpk[j] = r.y;
-            }
+            slot[j] = v < n_in ? slot_of(v) : 0u;
+        }
+#pragma unroll
+        for (uint32_t j = 0; j < STEP_MAXA; ++j) {
+            const uint2 r = in[slot[j]];
+            rid[j] = r.x;
+            rpk[j] = r.y;
         }
     };
 
@@ -471,7 +484,7 @@ __global__ void __launch_bounds__(1024) k_tile_step(TileParams p, StepIO io, uin
                     continue;
                 }
                 uint32_t s = (rpk[j] >> 20) & 3u;
-                if (TRANS) s = tile_transition<RW>(p, reg, rid[j], s, lx, ly, t - 1);
+                if (TRANS) s = tile_transition<RW>(p, reg, tinf, rid[j], s, lx, ly, t - 1);
                 packed[rid[j]] = make_uint2((uint32_t)(x0 + (int32_t)lx) |
                                                 ((uint32_t)(y0 + (int32_t)ly) << 16),
                                             s);
@@ -520,7 +533,7 @@ __global__ void __launch_bounds__(1024) k_tile_step(TileParams p, StepIO io, uin
             if (act) {
                 uint32_t s = (rpk[j] >> 20) & 3u;
                 if (TRANS)
-                    s = tile_transition<RW>(p, reg, rid[j], s, rpk[j] & 1023u,
+                    s = tile_transition<RW>(p, reg, tinf, rid[j], s, rpk[j] & 1023u,
                                             (rpk[j] >> 10) & 1023u, t - 1);
                 sus = s == ST_S;
                 const uint32_t m = rmv[j];
