@@ -782,15 +782,20 @@ __device__ __forceinline__ uint32_t sir_transition4(const SirParams &p,
 #pragma unroll
     for (int j = 0; j < 4; ++j) need |= (st[j] == ST_S && k[j] > 0) || st[j] == ST_I;
     if (!need) return S;
+    // the four thresholds are loaded unconditionally, before the Philox
+    // block, so the loads are in flight together while it is computed
+    const uint32_t k_last = p.table_len - 1;
+    uint32_t thr[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) thr[j] = p.t_inf[k[j] < k_last ? k[j] : k_last];
     const uint4 r = philox(q, t, P_EPI, p.k0, p.k1);
     const uint32_t u[4] = {r.x, r.y, r.z, r.w};
-    const uint32_t k_last = p.table_len - 1;
     uint32_t out = S;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         uint32_t ns = st[j];
         if (st[j] == ST_S && k[j] > 0) {
-            if (u[j] < p.t_inf[k[j] < k_last ? k[j] : k_last]) ns = ST_I;
+            if (u[j] < thr[j]) ns = ST_I;
         } else if (st[j] == ST_I) {
             if (u[j] < p.t_rec) ns = ST_R;
         }
