@@ -369,11 +369,15 @@ def test_wealth_forms_match_oracle(A, O, n, w0, steps, form):
                                                     ((1 << 25) + 7, 2, 4, [1, 3], 2),
                                                     (40_000_001, 1, 3, [2, 1], 2),
                                                     ((5 << 23) + 1, 1, 2, [2], 2),
+                                                    (5 << 23, 2, 2, [2], 2),
+                                                    (1 << 27, 1, 3, [2, 1], 2),
                                                     ((1 << 24) + 12345, 1, 3, [1, 2], 3),
                                                     ((5 << 23) + 1, 3, 3, [3], 3)])
 def test_wealth_exchange_above_2p24(A, O, n, w0, steps, chunks, form):
     """Partitions of 2^15 agents (up to 5 * 2^23 agents) and 2^16 agents (above),
-    16-bit records, ragged last partitions, the fold-only call boundary; form
+    16-bit records, ragged last partitions, both kernels at their most
+    partitions (5 * 2^23 and 2^27 agents, the benchmarked size), the
+    fold-only call boundary; form
     3 folds every partition with the 32-bit two-pass counters that a 16-bit
     counter's wrap would call for."""
     say(f"case wealth exchange 16-bit kernels n={n} chunks={chunks} form={form}")
