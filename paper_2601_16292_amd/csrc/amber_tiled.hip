@@ -222,7 +222,8 @@ __device__ __forceinline__ RingSeg ring_entry(const uint32_t *R, uint32_t rs, ui
 //
 // Output slots: every wavefront counts its records per destination group
 // (pass 1); the counts become per-wavefront bases inside each group, and
-// pass 2 hands out consecutive slots from those bases (ballot ranks).
+// pass 2 hands out consecutive slots from those bases: ballot ranks for the
+// records that stay, LDS atomics for the few that leave.
 // Global loads of one phase are all issued before any of them is used.
 template <uint32_t T, bool TRANS, bool MOVE>
 __global__ void __launch_bounds__(1024) k_tile_step(TileParams p, StepIO io, uint32_t t)
@@ -428,14 +429,8 @@ __global__ void __launch_bounds__(1024) k_tile_step(TileParams p, StepIO io, uin
                                               __HIP_MEMORY_SCOPE_AGENT);
                 }
                 stay += (uint32_t)__popcll(__ballot(act && g == STAY));
-                uint64_t other = __ballot(act && g != STAY);
-                while (other) {
-                    const uint32_t leader = (uint32_t)__builtin_ctzll(other);
-                    const uint32_t k = (uint32_t)__builtin_amdgcn_readlane((int)g, (int)leader);
-                    const uint64_t same = __ballot(act && g == k);
-                    if (lane == leader) mine[k] += (uint32_t)__popcll(same);
-                    other &= ~same;
-                }
+                // the few records that leave the tile: one LDS add each
+                if (act && g != STAY) atomicAdd(&mine[g], 1u);
             }
         }
         if (lane == 0) mine[STAY] = stay;
@@ -549,16 +544,9 @@ __global__ void __launch_bounds__(1024) k_tile_step(TileParams p, StepIO io, uin
             const uint64_t ms = __ballot(act && g == STAY);
             if (act && g == STAY) slot = stay_run + lanes_below(ms);
             stay_run += (uint32_t)__popcll(ms);
-            uint64_t other = __ballot(act && g != STAY);
-            while (other) {
-                const uint32_t leader = (uint32_t)__builtin_ctzll(other);
-                const uint32_t k = (uint32_t)__builtin_amdgcn_readlane((int)g, (int)leader);
-                const uint64_t same = __ballot(act && g == k);
-                const uint32_t b0 = mine[k];
-                if (act && g == k) slot = b0 + lanes_below(same);
-                if (lane == leader) mine[k] = b0 + (uint32_t)__popcll(same);
-                other &= ~same;
-            }
+            // a record that leaves takes the next slot of its wavefront's range
+            // in its group (in the order the LDS grants them)
+            if (act && g != STAY) slot = atomicAdd(&mine[g], 1u);
             if (act && store) out[rec_slot(slot, p.cap, fix, ovf)] = make_uint2(rid[j], pk);
             if (TRANS) wsus += (uint32_t)__popcll(__ballot(sus));
         }
