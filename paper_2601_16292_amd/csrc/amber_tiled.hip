@@ -132,7 +132,12 @@ __device__ __forceinline__ uint32_t tile_transition(const TileParams &p, const u
     const uint32_t u = word_of(philox(id >> 2, t_prev, P_EPI, p.k0, p.k1), id & 3u);
     if (s == ST_S) {
         const uint32_t kl = p.table_len - 1, kk = k < kl ? k : kl;
-        return u < (kk < TINF_LDS ? tinf[kk] : p.t_inf[kk]) ? (uint32_t)ST_I : (uint32_t)ST_S;
+        // an LDS read, and a global one only past the copy (volatile, so that
+        // the two are not merged into one flat load through a chosen pointer,
+        // which waits on both)
+        uint32_t thr = tinf[kk < TINF_LDS ? kk : 0u];
+        if (kk >= TINF_LDS) thr = *(const volatile uint32_t *)(p.t_inf + kk);
+        return u < thr ? (uint32_t)ST_I : (uint32_t)ST_S;
     }
     return u < p.t_rec ? (uint32_t)ST_R : (uint32_t)ST_I;
 }
