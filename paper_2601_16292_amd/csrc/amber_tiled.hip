@@ -280,11 +280,15 @@ __global__ void __launch_bounds__(1024) k_tile_step(TileParams p, StepIO io, uin
         for (uint32_t k = tid; k < nw * 9; k += NT) wcnt[k] = 0;
     }
     if (TRANS && tid < TINF_LDS && tid < p.table_len) tinf[tid] = p.t_inf[tid];
-    // The previous step's counts (the tile and its ring) and the ring partial
-    // counts around it do not depend on the headers: their loads go out
-    // together with the header loads, the counts into LDS before the
-    // barrier, the first RING_PRE ring words of each thread into registers
-    // (added after the first pass, once every count is in place).
+    // Counts of the previous step.  Inside the tile they are the infected
+    // records of the tile's own input (each record carries its position and
+    // its state at the start of that step, which is what was binned), counted
+    // in LDS during the first pass.  On the ring around the tile they come
+    // from memory: the border cells of the neighbouring tiles' grids plus the
+    // ring partial counts that land there.  Neither depends on the headers:
+    // those loads go out together with the header loads, the ring cells into
+    // LDS before the barrier, the first RING_PRE partial words of each thread
+    // into registers (added after the first pass).
     constexpr uint32_t RING_PRE = 4;
     uint32_t ring_v[RING_PRE], ring_dst[RING_PRE];
     const uint32_t wl = li + 1 == nT ? last : T, wr = ri + 1 == nT ? last : T;
@@ -303,40 +307,18 @@ __global__ void __launch_bounds__(1024) k_tile_step(TileParams p, StepIO io, uin
                 ring_dst[i] = e.dst;
             }
         }
-        // rows by wavefront, CROWS rows' loads in flight before their stores;
-        // a row is at most T + 3 <= 67 cells: lanes take cells lane and
-        // lane + 64
-        static_assert(T + 3 <= 128, "two cells per lane per row");
-        constexpr uint32_t CROWS = 8;
         const uint32_t *C = io.C_in;
-        int32_t gxa = x0 + (int32_t)lane - 1, gxb = gxa + 64;
-        gxa = gxa < 0 ? gxa + p.L : (gxa >= p.L ? gxa - p.L : gxa);
-        gxb = gxb >= p.L ? gxb - p.L : gxb;
-        const bool has_a = lane < w + 2, has_b = lane + 64 < w + 2;
-        for (uint32_t r0 = wave; r0 < h + 2; r0 += CROWS * nw) {
-            uint32_t va[CROWS], vb[CROWS];
-#pragma unroll
-            for (uint32_t k = 0; k < CROWS; ++k) {
-                const uint32_t ry = r0 + k * nw;
-                va[k] = 0;
-                vb[k] = 0;
-                if (ry < h + 2) {
-                    int32_t gy = y0 + (int32_t)ry - 1;
-                    gy = gy < 0 ? gy + p.L : (gy >= p.L ? gy - p.L : gy);
-                    const uint32_t *row = C + (size_t)gy * (uint32_t)p.L;
-                    if (has_a) va[k] = row[gxa];
-                    if (has_b) vb[k] = row[gxb];
-                }
-            }
-#pragma unroll
-            for (uint32_t k = 0; k < CROWS; ++k) {
-                const uint32_t ry = r0 + k * nw;
-                if (ry < h + 2) {
-                    if (has_a) reg[ry * RW + lane] = va[k];
-                    if (has_b) reg[ry * RW + lane + 64] = vb[k];
-                }
-            }
+        const uint32_t rsz = ring_size(w, h);
+        for (uint32_t r = tid; r < rsz; r += NT) {
+            int32_t lx, ly;
+            ring_cell(r, w, h, lx, ly);
+            int32_t gx = x0 + lx, gy = y0 + ly;
+            gx = gx < 0 ? gx + p.L : (gx >= p.L ? gx - p.L : gx);
+            gy = gy < 0 ? gy + p.L : (gy >= p.L ? gy - p.L : gy);
+            reg[(uint32_t)(ly + 1) * RW + (uint32_t)(lx + 1)] = C[(size_t)gy * (uint32_t)p.L + gx];
         }
+        for (uint32_t ry = wave; ry < h; ry += nw)
+            for (uint32_t rx = lane; rx < w; rx += 64) reg[(ry + 1) * RW + rx + 1] = 0;
     }
     __syncthreads();
 
@@ -415,6 +397,15 @@ __global__ void __launch_bounds__(1024) k_tile_step(TileParams p, StepIO io, uin
         }
     };
 
+    // an input record infected at the start of the previous step adds one to
+    // its cell of the previous step's counts (positions outside the tile are
+    // a corrupt list, flagged in the first pass, and not counted)
+    auto count_in = [&](uint32_t pk) {
+        const uint32_t lx = pk & 1023u, ly = (pk >> 10) & 1023u;
+        if (((pk >> 20) & 3u) == ST_I && lx < w && ly < h)
+            atomicAdd(&reg[(ly + 1) * RW + lx + 1], 1u);
+    };
+
     if (MOVE) {
         // pass 1: records per destination group and wavefront
         uint32_t *mine = wcnt + wave * 9;
@@ -436,23 +427,38 @@ __global__ void __launch_bounds__(1024) k_tile_step(TileParams p, StepIO io, uin
                 stay += (uint32_t)__popcll(__ballot(act && g == STAY));
                 // the few records that leave the tile: one LDS add each
                 if (act && g != STAY) atomicAdd(&mine[g], 1u);
+                if (TRANS && act) count_in(rpk[j]);
             }
         }
         if (lane == 0) mine[STAY] = stay;
     } else {
-        fetch(0);   // the tail holds its records while the counts come in
+        // the tail counts every round's infected records, then holds the
+        // first round while the ring counts come in
+        for (uint32_t r0 = 0; r0 < n_in; r0 += round_cap) {
+            fetch(r0);
+#pragma unroll
+            for (uint32_t j = 0; j < STEP_MAXA; ++j)
+                if (r0 + j * NT + tid < n_in) count_in(rpk[j]);
+        }
+        if (!one) fetch(0);
     }
     __syncthreads();
 
     if (TRANS) {
-        // ring partial counts that land on the tile or its ring: the words
+        // ring partial counts that land on the ring (those that land inside
+        // the tile are records of its input, already counted): the words
         // loaded before the first barrier, then any beyond them
+        auto on_ring = [&](uint32_t dst) {
+            const uint32_t ry = dst / RW, rx = dst - ry * RW;
+            return ry == 0 || ry > h || rx == 0 || rx > w;
+        };
 #pragma unroll
         for (uint32_t i = 0; i < RING_PRE; ++i)
-            if (ring_v[i]) atomicAdd(&reg[ring_dst[i]], ring_v[i]);
+            if (ring_v[i] && on_ring(ring_dst[i])) atomicAdd(&reg[ring_dst[i]], ring_v[i]);
         for (uint32_t k = tid + RING_PRE * NT; k < ring_total; k += NT) {
             const RingSeg e = ring_entry<RW>(io.ring_in, p.rs, nT, k, ti, tj, li, ri, uj,
                                              dj, w, h, wl, wr, hu, hd);
+            if (!on_ring(e.dst)) continue;
             const uint32_t v = *e.src;
             if (v) atomicAdd(&reg[e.dst], v);
         }
@@ -560,13 +566,23 @@ __global__ void __launch_bounds__(1024) k_tile_step(TileParams p, StepIO io, uin
     __syncthreads();
     if (TRANS && p.scnt && tid == 0) p.scnt[tile] = s_sus;
 
-    // counts of step t: interior to the grid (rows by wavefront), ring to the
-    // tile's ring array
+    // counts of step t: the tile's border cells to the grid (the only ones a
+    // neighbour reads: they lie on its ring), the ring to the tile's ring
+    // array
     uint32_t *C = io.C_out;
-    for (uint32_t ly = wave; ly < h; ly += nw) {
-        uint32_t *row = C + (size_t)((uint32_t)y0 + ly) * (uint32_t)p.L + (uint32_t)x0;
-        const uint32_t *src = hist + (ly + 1) * RW + 1;
-        for (uint32_t lx = lane; lx < w; lx += 64) row[lx] = src[lx];
+    const uint32_t nb = 2 * w + 2 * (h - 2);
+    for (uint32_t b = tid; b < nb; b += NT) {
+        uint32_t lx, ly;
+        if (b < 2 * w) {
+            lx = b < w ? b : b - w;
+            ly = b < w ? 0u : h - 1;
+        } else {
+            const uint32_t c = b - 2 * w;
+            lx = c < h - 2 ? 0u : w - 1;
+            ly = 1 + (c < h - 2 ? c : c - (h - 2));
+        }
+        C[(size_t)((uint32_t)y0 + ly) * (uint32_t)p.L + (uint32_t)x0 + lx] =
+            hist[(ly + 1) * RW + lx + 1];
     }
     uint32_t *R = io.ring_out + (size_t)tile * p.rs;
     const uint32_t rsz = ring_size(w, h);
