@@ -14,16 +14,20 @@
 //  1. The tile's input is 9 chunks of records: for each tile offset
 //     (ddx, ddy), the group that tile (ti - ddx, tj - ddy) sent this way.
 //  2. Infected counts of the previous step on the tile and the one-cell ring
-//     around it go to LDS: the interior counts that each tile stores for its
-//     own cells, plus the ring partial counts of the 9 tiles around (each
-//     tile stores the infected agents it moved onto the ring around it).
+//     around it go to LDS: inside the tile, the infected records of its own
+//     input (a record holds its position after the previous move and its
+//     state at the start of that step); on the ring, the border cells that
+//     each tile stores from its grid plus the ring partial counts of the 9
+//     tiles around (each tile stores the infected agents it moved onto the
+//     ring around it).
 //  3. Per agent: the transition of the previous step from the 3 x 3 sum in
 //     LDS, then the move of this step.  Infected agents are binned into an
 //     LDS histogram of the tile and its ring, and the record goes to the
 //     group of its destination tile inside the tile's output range (one
 //     atomic per tile allocates that range).
-//  4. The histogram's interior is stored to the count grid and its ring to
-//     the tile's ring array, every cell, so nothing is ever cleared.
+//  4. The histogram's border cells are stored to the count grid and its ring
+//     to the tile's ring array, every cell, so nothing is cleared during a
+//     call.
 // With every tile at least 2 cells wide, all agents that can reach a cell
 // within distance 1 of a tile start inside the tile's 3 x 3 block of tiles,
 // which is what steps 1 and 2 read.
