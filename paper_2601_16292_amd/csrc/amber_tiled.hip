@@ -282,6 +282,7 @@ __global__ void __launch_bounds__(1024) k_tile_step(TileParams p, StepIO io, uin
     if (MOVE) {
         for (uint32_t k = tid; k < RW * RW; k += NT) hist[k] = 0;
         for (uint32_t k = tid; k < nw * 9; k += NT) wcnt[k] = 0;
+        if (tid < 9) gtot[tid] = 0;
     }
     if (TRANS && tid < TINF_LDS && tid < p.table_len) tinf[tid] = p.t_inf[tid];
     // Counts of the previous step.  Inside the tile they are the infected
@@ -429,12 +430,19 @@ __global__ void __launch_bounds__(1024) k_tile_step(TileParams p, StepIO io, uin
                                               __HIP_MEMORY_SCOPE_AGENT);
                 }
                 stay += (uint32_t)__popcll(__ballot(act && g == STAY));
-                // the few records that leave the tile: one LDS add each
-                if (act && g != STAY) atomicAdd(&mine[g], 1u);
+                // the few records that leave the tile: one LDS add each, to the
+                // wavefront's count and to the group's total
+                if (act && g != STAY) {
+                    atomicAdd(&mine[g], 1u);
+                    atomicAdd(&gtot[g], 1u);
+                }
                 if (TRANS && act) count_in(rpk[j]);
             }
         }
-        if (lane == 0) mine[STAY] = stay;
+        if (lane == 0) {
+            mine[STAY] = stay;
+            atomicAdd(&gtot[STAY], stay);
+        }
     } else {
         // the tail counts every round's infected records, then holds the
         // first round while the ring counts come in
@@ -467,10 +475,22 @@ __global__ void __launch_bounds__(1024) k_tile_step(TileParams p, StepIO io, uin
             if (v) atomicAdd(&reg[e.dst], v);
         }
     }
-    if (MOVE && tid < 9) {
-        uint32_t tot = 0;
-        for (uint32_t k = 0; k < nw; ++k) tot += wcnt[k * 9 + tid];
-        gtot[tid] = tot;
+    if (MOVE) {
+        // per-wavefront bases inside each group of the tile's list, and the
+        // tile's header
+        if (tid < nw * 9) {
+            const uint32_t k = tid / 9, g = tid - k * 9;
+            uint32_t b = 0;
+            for (uint32_t q = 0; q < g; ++q) b += gtot[q];
+            for (uint32_t q = 0; q < k; ++q) b += wcnt[q * 9 + g];
+            wbase[tid] = b;
+        }
+        if (tid == 0) {
+            uint32_t *H = io.hdr_out + (size_t)tile * TILE_HDR;
+            H[0] = s_ovf;
+            for (int g = 0; g < 9; ++g) H[1 + g] = gtot[g];
+            s_sus = 0;
+        }
     }
     __syncthreads();
 
@@ -502,22 +522,6 @@ __global__ void __launch_bounds__(1024) k_tile_step(TileParams p, StepIO io, uin
         }
         return;
     }
-
-    // per-wavefront bases inside each group of the tile's list
-    if (tid < nw * 9) {
-        const uint32_t k = tid / 9, g = tid - k * 9;
-        uint32_t b = 0;
-        for (uint32_t q = 0; q < g; ++q) b += gtot[q];
-        for (uint32_t q = 0; q < k; ++q) b += wcnt[q * 9 + g];
-        wbase[tid] = b;
-    }
-    if (tid == 0) {
-        uint32_t *H = io.hdr_out + (size_t)tile * TILE_HDR;
-        H[0] = s_ovf;
-        for (int g = 0; g < 9; ++g) H[1 + g] = gtot[g];
-        s_sus = 0;
-    }
-    __syncthreads();
 
     // pass 2: transition, bin, write
     const bool store = s_store != 0;
