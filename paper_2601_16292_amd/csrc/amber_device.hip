@@ -101,9 +101,11 @@ __global__ __launch_bounds__(WEALTH_SMALL_THREADS) void k_wealth_small(
 
 // Partition-exchange wealth step (see wealth_exchange_partition).  mode bit 0:
 // fold the records of the previous step; bit 1: take this step's donors.
+// 2^14-agent partitions (72 KB of LDS) keep within 64 registers so that two
+// workgroups share a CU.
 template <int XB, int PMAX, int NT>
-__global__ __launch_bounds__(NT) void k_wealth_x(WealthXParams x, uint32_t t, uint32_t parity_in,
-                                                 uint32_t mode)
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(XB == 14 ? 8 : 1)))
+void k_wealth_x(WealthXParams x, uint32_t t, uint32_t parity_in, uint32_t mode)
 {
     __shared__ __align__(16) int32_t hist[1u << XB];
     __shared__ uint32_t pcount[PMAX];
@@ -115,9 +117,12 @@ __global__ __launch_bounds__(NT) void k_wealth_x(WealthXParams x, uint32_t t, ui
 
 // The 16-bit form of the exchange (see wealth_exchange_partition16), for
 // partitions of 2^15 and 2^16 agents; mode bit 2 asks for the 32-bit fold.
+// With 2^15-agent partitions (69 KB of LDS) two workgroups share a CU if
+// each wavefront keeps within 64 registers (8 per SIMD): one's fold then
+// runs beside the other's Philox draws.
 template <int XB, int PMAX, int NT>
-__global__ __launch_bounds__(NT) void k_wealth_x16(WealthXParams x, uint32_t t, uint32_t parity_in,
-                                                   uint32_t mode)
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(XB == 15 ? 8 : 1)))
+void k_wealth_x16(WealthXParams x, uint32_t t, uint32_t parity_in, uint32_t mode)
 {
     __shared__ __align__(16) uint32_t h2[1u << (XB - 1)];
     __shared__ uint32_t c32[PMAX + 2];

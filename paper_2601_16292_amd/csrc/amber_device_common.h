@@ -219,27 +219,6 @@ __device__ __forceinline__ uint32_t xcd_partition(uint32_t b, uint32_t P)
 // with a fold-only launch, so the column holds the state at every call
 // boundary.
 
-// Adds records [off, off + cnt) of a source's segment seg (agent ids; h is
-// the histogram shifted by the partition's first id) to the fold histogram.
-// The records are read with aligned 16-byte loads, two per round: a piece of
-// a few records then costs one or two loads, whatever its offset.  seg is
-// 16-byte aligned and off + cnt never passes the segment's end (a multiple
-// of 4 words), so every load stays inside the segment; words outside the
-// piece are read and ignored.
-__device__ __forceinline__ void wealth_fold_source(int32_t *h, const uint32_t *seg, uint32_t off,
-                                                   uint32_t cnt)
-{
-    const uint32_t end = off + cnt;
-    for (uint32_t k = off & ~3u; k < end; k += 8) {
-        const uint4 u0 = *(const uint4 *)(seg + k);
-        const uint4 u1 = k + 4 < end ? *(const uint4 *)(seg + k + 4) : make_uint4(0, 0, 0, 0);
-        const uint32_t v[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
-#pragma unroll
-        for (uint32_t j = 0; j < 8; ++j)
-            if (k + j >= off && k + j < end) atomicAdd(&h[v[j]], 1);
-    }
-}
-
 // Writes the producer's recipient ids to its output segment, grouped by
 // destination: record (g, j) goes to position off[dest] + rank.  The ids are
 // first placed in LDS (stage, at least `total` words, free at this point),
@@ -286,13 +265,49 @@ __device__ __forceinline__ void wealth_exchange_partition(const WealthXParams &x
     const uint32_t e = consume && tid < P ? tab[(size_t)tid * P + p] : 0u;
     for (uint32_t i = tid; i < XR; i += NT) hist[i] = 0;
     __syncthreads();
-    if (consume && tid < P)
-        wealth_fold_source(hist - (size_t)p * XR, x.rec[parity_in] + (size_t)tid * XR, e >> 16,
-                           e & 0xffffu);
+    // Fold: the source's records [off, end) (agent ids; h is the histogram
+    // shifted by the partition's first id), read with aligned 16-byte loads,
+    // two per round, so a piece of a few records costs one or two loads at
+    // any offset.  A segment is 16-byte aligned and a piece never passes its
+    // end (a multiple of 4 words), so every load stays inside it; words
+    // outside the piece are read and ignored.  The recipient draws do not
+    // depend on who gives: they are made while the first window is in
+    // flight.
+    const uint32_t off = e >> 16, end = off + (e & 0xffffu);
+    const uint32_t *seg = x.rec[parity_in] + (size_t)tid * XR;
+    uint32_t k = off & ~3u;
+    const bool first = consume && tid < P && k < end;
+    uint4 u0 = make_uint4(0, 0, 0, 0);
+    if (first) u0 = *(const uint4 *)(seg + k);
+    uint32_t rcp[G][4], rank[G][4];
+    if (produce) {
+#pragma unroll
+        for (uint32_t g = 0; g < G; ++g) {
+            const uint32_t q = p * (XR / 4) + g * NT + tid;
+            const uint4 r0 = philox(2 * q, t, P_RECIPIENT, x.k0, x.k1);
+            const uint4 r1 = philox(2 * q + 1, t, P_RECIPIENT, x.k0, x.k1);
+            rcp[g][0] = recipient(r0.x, r0.y, x.n);
+            rcp[g][1] = recipient(r0.z, r0.w, x.n);
+            rcp[g][2] = recipient(r1.x, r1.y, x.n);
+            rcp[g][3] = recipient(r1.z, r1.w, x.n);
+        }
+    }
+    if (first) {
+        int32_t *h = hist - (size_t)p * XR;
+        for (;;) {
+            const uint4 u1 = k + 4 < end ? *(const uint4 *)(seg + k + 4) : make_uint4(0, 0, 0, 0);
+            const uint32_t v[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
+#pragma unroll
+            for (uint32_t j = 0; j < 8; ++j)
+                if (k + j >= off && k + j < end) atomicAdd(&h[v[j]], 1);
+            k += 8;
+            if (k >= end) break;
+            u0 = *(const uint4 *)(seg + k);
+        }
+    }
     for (uint32_t i = tid; i < P; i += NT) pcount[i] = 0;
     __syncthreads();
     int4 V[G];
-    uint32_t rcp[G][4], rank[G][4];
 #pragma unroll
     for (uint32_t g = 0; g < G; ++g) {
         const uint32_t local = g * NT + tid;                 // group within the partition
@@ -313,17 +328,7 @@ __device__ __forceinline__ void wealth_exchange_partition(const WealthXParams &x
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             d[j] = q < groups && v[j] > 0 && a + j < x.n;
-            rcp[g][j] = 0xffffffffu;
-        }
-        if (d[0] | d[1]) {
-            const uint4 r = philox(2 * q, t, P_RECIPIENT, x.k0, x.k1);
-            if (d[0]) rcp[g][0] = recipient(r.x, r.y, x.n);
-            if (d[1]) rcp[g][1] = recipient(r.z, r.w, x.n);
-        }
-        if (d[2] | d[3]) {
-            const uint4 r = philox(2 * q + 1, t, P_RECIPIENT, x.k0, x.k1);
-            if (d[2]) rcp[g][2] = recipient(r.x, r.y, x.n);
-            if (d[3]) rcp[g][3] = recipient(r.z, r.w, x.n);
+            rcp[g][j] = d[j] ? rcp[g][j] : 0xffffffffu;
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j)
@@ -416,6 +421,10 @@ __device__ __forceinline__ void wealth_exchange_partition16(const WealthXParams 
     constexpr uint32_t G = XR / (4 * NT);                   // 4-agent groups per thread
     constexpr uint32_t LPS = 4;                              // lanes per source in the fold
     constexpr uint32_t SPT = (PMAX + NT / LPS - 1) / (NT / LPS);   // sources per lane
+    // Groups whose recipients are drawn during the fold (the rest in the
+    // produce loop).  Each holds 4 more registers through the fold; with
+    // 2^15-agent partitions two workgroups share a CU only within 64.
+    constexpr uint32_t GF = (XB == 16 ? 3u : 4u) < G ? (XB == 16 ? 3u : 4u) : G;
     static_assert(G >= 1 && XB >= 4 && XB <= 16, "16-bit records");
     const uint32_t tid = threadIdx.x;
     const uint32_t P = x.P;
@@ -432,6 +441,26 @@ __device__ __forceinline__ void wealth_exchange_partition16(const WealthXParams 
     for (uint32_t i = tid; i < XR / 2; i += NT) h2[i] = 0;
     for (uint32_t i = tid; i < PMAX + 2; i += NT) c32[i] = 0;
     if (tid == 0) *flag = 0;
+    // The recipient draws do not depend on who gives, so a thread draws
+    // those of its first GF agent groups while its table and piece loads
+    // are in flight (slot 0 before the barrier, slot c + 1 with source c):
+    // the Philox arithmetic fills the wait on the scattered loads.
+    uint32_t rcp[G][4];
+    auto draw = [&](uint32_t slot) {
+#pragma unroll
+        for (uint32_t g = 0; g < GF; ++g) {
+            if (g * (SPT + 1) / GF != slot) continue;
+            const uint32_t q = p * (XR / 4) + g * NT + tid;
+            const uint4 r0 = philox(2 * q, t, P_RECIPIENT, x.k0, x.k1);
+            const uint4 r1 = philox(2 * q + 1, t, P_RECIPIENT, x.k0, x.k1);
+            rcp[g][0] = recipient(r0.x, r0.y, x.n);
+            rcp[g][1] = recipient(r0.z, r0.w, x.n);
+            rcp[g][2] = recipient(r1.x, r1.y, x.n);
+            rcp[g][3] = recipient(r1.z, r1.w, x.n);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    };
+    if (produce) draw(0);
     __syncthreads();
     const uint16_t *rec = (const uint16_t *)x.rec[parity_in];
     uint32_t wrap = 0;
@@ -440,11 +469,19 @@ __device__ __forceinline__ void wealth_exchange_partition16(const WealthXParams 
     // lines and are served together.
 #pragma unroll
     for (uint32_t c = 0; c < SPT; ++c) {
-        if (wide || e[c] == WX16_EMPTY) continue;
+        const bool has = !wide && e[c] != WX16_EMPTY;
         const uint32_t off = e[c] >> 16, end = off + (e[c] & 0xffffu) + 1;
         const uint16_t *seg = rec + (size_t)(c * (NT / LPS) + tid / LPS) * XR;
-        for (uint32_t k = (off & ~7u) + 8 * (tid % LPS); k < end; k += 8 * LPS)
-            wrap |= wealth_fold16_window<XB>(h2, *(const uint4 *)(seg + k), k, off, end);
+        uint32_t k = (off & ~7u) + 8 * (tid % LPS);
+        const bool first = has && k < end;
+        uint4 u = make_uint4(0, 0, 0, 0);
+        if (first) u = *(const uint4 *)(seg + k);
+        if (produce) draw(c + 1);
+        if (first) {
+            wrap |= wealth_fold16_window<XB>(h2, u, k, off, end);
+            for (k += 8 * LPS; k < end; k += 8 * LPS)
+                wrap |= wealth_fold16_window<XB>(h2, *(const uint4 *)(seg + k), k, off, end);
+        }
     }
     if (wrap) *flag = 1;
     __syncthreads();
@@ -472,7 +509,6 @@ __device__ __forceinline__ void wealth_exchange_partition16(const WealthXParams 
         for (uint32_t i = tid; i < XR / 2; i += NT) h2[i] = 0;
         __syncthreads();
     }
-    uint32_t rcp[G][4];
 #pragma unroll
     for (uint32_t g = 0; g < G; ++g) {
         const uint32_t local = g * NT + tid;                 // group within the partition
@@ -493,14 +529,16 @@ __device__ __forceinline__ void wealth_exchange_partition16(const WealthXParams 
         bool d[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) d[j] = q < groups && v[j] > 0 && a + j < x.n;
-        // both blocks are drawn whatever the donors (a wavefront nearly always
-        // has a donor in each pair of lanes' agents); no branches
-        const uint4 r0 = philox(2 * q, t, P_RECIPIENT, x.k0, x.k1);
-        rcp[g][0] = d[0] ? recipient(r0.x, r0.y, x.n) : 0xffffffffu;
-        rcp[g][1] = d[1] ? recipient(r0.z, r0.w, x.n) : 0xffffffffu;
-        const uint4 r1 = philox(2 * q + 1, t, P_RECIPIENT, x.k0, x.k1);
-        rcp[g][2] = d[2] ? recipient(r1.x, r1.y, x.n) : 0xffffffffu;
-        rcp[g][3] = d[3] ? recipient(r1.z, r1.w, x.n) : 0xffffffffu;
+        if (g >= GF) {
+            const uint4 r0 = philox(2 * q, t, P_RECIPIENT, x.k0, x.k1);
+            const uint4 r1 = philox(2 * q + 1, t, P_RECIPIENT, x.k0, x.k1);
+            rcp[g][0] = recipient(r0.x, r0.y, x.n);
+            rcp[g][1] = recipient(r0.z, r0.w, x.n);
+            rcp[g][2] = recipient(r1.x, r1.y, x.n);
+            rcp[g][3] = recipient(r1.z, r1.w, x.n);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) rcp[g][j] = d[j] ? rcp[g][j] : 0xffffffffu;
         // a non-donor adds 0 to a word of its own lane (no same-word conflicts)
 #pragma unroll
         for (int j = 0; j < 4; ++j)
