@@ -9,7 +9,10 @@ namespace amber {
 // ------------------------------------------------------------------ Philox
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  Multipliers and Weyl
 // key increments as published.  The key lives in SGPRs (wavefront-uniform);
-// each 32x32->64 product is one v_mad_u64_u32.
+// each 32x32->64 product is one v_mad_u64_u32.  From the third round on both
+// words are lane-varying and each three-way XOR is one v_bitop3_b32 (truth
+// table 0x96); in the first two rounds the counter's constant and uniform
+// words leave parts of the XORs to scalar code, so plain XORs stay there.
 constexpr uint32_t PHILOX_M0 = 0xD2511F53u;
 constexpr uint32_t PHILOX_M1 = 0xCD9E8D57u;
 constexpr uint32_t PHILOX_W0 = 0x9E3779B9u;
@@ -23,8 +26,10 @@ __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2,
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)PHILOX_M0 * c0;
         const uint64_t p1 = (uint64_t)PHILOX_M1 * c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        const uint32_t n0 = r < 2 ? (uint32_t)(p1 >> 32) ^ c1 ^ k0
+                                  : __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c1, k0, 0x96);
+        const uint32_t n2 = r < 2 ? (uint32_t)(p0 >> 32) ^ c3 ^ k1
+                                  : __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c3, k1, 0x96);
         c1 = (uint32_t)p1;
         c3 = (uint32_t)p0;
         c0 = n0;

@@ -76,13 +76,16 @@ __device__ __forceinline__ void ring_cell(uint32_t r, uint32_t w, uint32_t h, in
 }
 
 // Word j of a Philox block, by value selects (an indexed read would make the
-// compiler keep the block in memory).
+// compiler keep the block in memory): three bitwise selects m ? a : b, each
+// one v_bitop3_b32 (truth table 0xE4 for operands a, b, m), on the all-ones
+// or zero masks of bits 0 and 1 of j.
 __device__ __forceinline__ uint32_t word_of(uint4 r, uint32_t j)
 {
-    const uint32_t odd = 0u - (j & 1u), high = 0u - ((j >> 1) & 1u);
-    const uint32_t lo = (r.x & ~odd) | (r.y & odd);
-    const uint32_t hi = (r.z & ~odd) | (r.w & odd);
-    return (lo & ~high) | (hi & high);
+    const uint32_t odd = (uint32_t)((int32_t)(j << 31) >> 31);
+    const uint32_t high = (uint32_t)((int32_t)(j << 30) >> 31);
+    const uint32_t lo = __builtin_amdgcn_bitop3_b32(r.y, r.x, odd, 0xE4);
+    const uint32_t hi = __builtin_amdgcn_bitop3_b32(r.w, r.z, odd, 0xE4);
+    return __builtin_amdgcn_bitop3_b32(hi, lo, high, 0xE4);
 }
 
 __device__ __forceinline__ uint32_t lanes_below(uint64_t m)
