@@ -575,6 +575,33 @@ hipError_t launch_init_states(uint8_t *s, uint32_t n, uint32_t i0, hipStream_t s
     return hipGetLastError();
 }
 
+// Words passed by value: kernel arguments are copied when the launch is
+// enqueued, so a small host table reaches the device with no staged copy
+// from pageable memory (which holds the host until the stream drains).
+constexpr uint32_t WRITE_CHUNK = 960;          // 3840 bytes of kernel arguments
+struct WordChunk {
+    uint32_t w[WRITE_CHUNK];
+};
+
+__global__ __launch_bounds__(256) void k_write_words(uint32_t *__restrict__ dst, WordChunk c,
+                                                     uint32_t count)
+{
+    for (uint32_t i = threadIdx.x; i < count; i += blockDim.x) dst[i] = c.w[i];
+}
+
+hipError_t launch_write_words(uint32_t *dst, const uint32_t *src, uint64_t count, hipStream_t st)
+{
+    for (uint64_t o = 0; o < count; o += WRITE_CHUNK) {
+        WordChunk c;
+        const uint32_t k = (uint32_t)(count - o < WRITE_CHUNK ? count - o : WRITE_CHUNK);
+        for (uint32_t i = 0; i < k; ++i) c.w[i] = src[o + i];
+        hipLaunchKernelGGL(k_write_words, dim3(1), dim3(256), 0, st, dst + o, c, k);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 hipError_t launch_zero_words(uint32_t *p, uint64_t words, hipStream_t st)
 {
     const uint64_t quads = words / 4;   // callers pass multiples of 4 words

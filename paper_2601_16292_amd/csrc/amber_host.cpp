@@ -497,6 +497,9 @@ hipError_t poll_events(amber_pop *p)
 }
 
 constexpr uint32_t SIR_POLL = 16;      // body launches between early-stop polls
+// The gather mode's polls come twice as often: the launches still queued
+// when the early stop is seen each cost a launch that does nothing.
+constexpr uint32_t SIR_POLL_GATHER = 8;
 
 // sir_poll values: how a long SIR call learns what the device has reached.
 // NOWAIT reads the pinned words only when the device has already written
@@ -817,13 +820,13 @@ amber_status_t enqueue_sir_gather(amber_pop *p, uint32_t t0, uint32_t n_steps)
     sp.t_last = t0 + n_steps - 1;
     // Early stop: once no susceptible agent is left, one body launch
     // runs the call's remaining steps and announces it in a pinned
-    // word; the later launches would do nothing.  Every SIR_POLL
+    // word; the later launches would do nothing.  Every SIR_POLL_GATHER
     // launches the host reads the word (PACED: after waiting until at
-    // most 2 x SIR_POLL launches are queued) and stops enqueueing once
-    // it holds this call's number.  Results do not depend on where it
+    // most 2 x SIR_POLL_GATHER launches are queued) and stops enqueueing
+    // once it holds this call's number.  Results do not depend on where it
     // stops.
-    const bool watch = tu.sir_poll != POLL_OFF && p->stop_host && n_steps > 2 * SIR_POLL &&
-                       !stream_capturing(st);
+    const bool watch = tu.sir_poll != POLL_OFF && p->stop_host &&
+                       n_steps > 2 * SIR_POLL_GATHER && !stream_capturing(st);
     const bool paced = watch && tu.sir_poll == POLL_PACED;
     if (watch) {
         if (paced) HIP_TRY(poll_events(p), "poll events");
@@ -838,9 +841,9 @@ amber_status_t enqueue_sir_gather(amber_pop *p, uint32_t t0, uint32_t n_steps)
         HIP_TRY(timed(p, "sir_body",
                       [&] { return launch_sir_body(sp, t0 + i, false, tu, st); }),
                 "sir body kernel");
-        if (!watch || i % SIR_POLL != 0) continue;
+        if (!watch || i % SIR_POLL_GATHER != 0) continue;
         if (paced) {
-            const uint32_t k = i / SIR_POLL;
+            const uint32_t k = i / SIR_POLL_GATHER;
             HIP_TRY(hipEventRecord(p->poll_ev[k & 1], st), "poll event record");
             if (k < 2) continue;
             HIP_TRY(hipEventSynchronize(p->poll_ev[(k - 1) & 1]), "poll event synchronize");
@@ -1524,12 +1527,9 @@ amber_status_t init_population(const amber_run_desc_t *desc, const amber_buffers
             if (e == hipSuccess)
                 p->persist_g = sir_persistent_groups_per_thread(rr.n, 8, &p->persist_blocks);
             if (e == hipSuccess && !noalloc) e = stop_words().take(&p->stop_host, &p->stop_dev);
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(ws_ptr(p, rr.off_table), rr.t_inf.data(),
-                                   rr.t_inf.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
-                                   p->stream);
-            // the table's host copy lives in the handle, which outlives the
-            // upload (amber_release waits for the stream)
+            if (e == hipSuccess)     // by kernel arguments: the host does not wait
+                e = launch_write_words((uint32_t *)ws_ptr(p, rr.off_table), rr.t_inf.data(),
+                                       rr.t_inf.size(), p->stream);
         }
     }
     if (e != hipSuccess) return bail(hip_fail(e, "init kernels"));

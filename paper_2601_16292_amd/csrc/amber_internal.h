@@ -111,6 +111,8 @@ hipError_t launch_init_positions(int32_t *x, int32_t *y, uint32_t n, int32_t L,
                                  uint32_t k0, uint32_t k1, hipStream_t st);
 hipError_t launch_init_states(uint8_t *s, uint32_t n, uint32_t i0, hipStream_t st);
 hipError_t launch_zero_words(uint32_t *p, uint64_t words, hipStream_t st);
+// Copies count host words to dst through kernel arguments (no host wait).
+hipError_t launch_write_words(uint32_t *dst, const uint32_t *src, uint64_t count, hipStream_t st);
 
 // View primitives on arbitrary columns (amber_views.hip).
 union ViewValue {

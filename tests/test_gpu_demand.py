@@ -147,7 +147,7 @@ def test_early_stop_of_a_long_call(A, O, poll):
             first_none = t
             break
         ref.step(1)
-    assert first_none is not None and first_none + 3 + 2 * 16 < steps - 1
+    assert first_none is not None and first_none + 3 + 2 * 8 < steps - 1
     ref.step(steps - first_none)
     pop = A.Population(A.SIR, n, L=L, seed=11, stream_id=3, beta=beta, gamma=gamma)
     pop.tune(sir_form=A.SIR_PIPELINED, sir_count=A.COUNT_GATHER, sir_poll=poll)
@@ -158,8 +158,8 @@ def test_early_stop_of_a_long_call(A, O, poll):
     pop.release()
     if poll == A.POLL_PACED:
         # the launch running the remaining steps is first_none + 3; polls come
-        # every 16 launches, waiting for the launch 16 back
-        assert body <= first_none + 3 + 2 * 16, body
+        # every 8 launches, waiting for the launch 8 back
+        assert body <= first_none + 3 + 2 * 8, body
     elif poll == A.POLL_OFF:
         assert body == steps - 1
     else:
