@@ -13,6 +13,9 @@
 // One launch per step, one workgroup per tile:
 //  1. The tile's input is 9 chunks of records: for each tile offset
 //     (ddx, ddy), the group that tile (ti - ddx, tj - ddy) sent this way.
+//     A tile's list holds its own stayers first, so the input's first
+//     entries are its stay chunk and the chunk search is for the few
+//     records that moved in.
 //  2. Infected counts of the previous step on the tile and the one-cell ring
 //     around it go to LDS: inside the tile, the infected records of its own
 //     input (a record holds its position after the previous move and its
@@ -86,6 +89,19 @@ __device__ __forceinline__ uint32_t word_of(uint4 r, uint32_t j)
     const uint32_t lo = __builtin_amdgcn_bitop3_b32(r.y, r.x, odd, 0xE4);
     const uint32_t hi = __builtin_amdgcn_bitop3_b32(r.w, r.z, odd, 0xE4);
     return __builtin_amdgcn_bitop3_b32(hi, lo, high, 0xE4);
+}
+
+// A tile's record list holds its nine groups in the order STAY, 0, 1, 2, 3,
+// 5, 6, 7, 8 (group_rank gives a group's place, group_at the group in a
+// place): the records that stayed come first, so an input entry below the
+// stay count needs no chunk search.
+__device__ __forceinline__ uint32_t group_rank(uint32_t g)
+{
+    return g == STAY ? 0u : (g < STAY ? g + 1 : g);
+}
+__device__ __forceinline__ uint32_t group_at(uint32_t k)
+{
+    return k == 0 ? STAY : (k <= STAY ? k - 1 : k);
 }
 
 __device__ __forceinline__ uint32_t lanes_below(uint64_t m)
@@ -274,7 +290,7 @@ __global__ void __launch_bounds__(1024) k_tile_step(TileParams p, StepIO io, uin
         uint32_t off = 0, cnt = 0;
 #pragma unroll
         for (uint32_t g = 0; g < 9; ++g) {
-            off += g < tid ? hv[1 + g] : 0u;
+            off += group_rank(g) < group_rank(tid) ? hv[1 + g] : 0u;
             cnt = g == tid ? hv[1 + g] : cnt;
         }
         c_start[tid] = off;
@@ -336,9 +352,10 @@ __global__ void __launch_bounds__(1024) k_tile_step(TileParams p, StepIO io, uin
     bool ok = true;
     pre[0] = 0;
 #pragma unroll
-    for (uint32_t d = 0; d < 9; ++d) {
+    for (uint32_t k = 0; k < 9; ++k) {           // entry order: the chunks in group order
+        const uint32_t d = group_at(k);
         const uint32_t c = c_cnt[d], st = c_start[d];
-        pre[d + 1] = pre[d] + c;
+        pre[k + 1] = pre[k] + c;
         ok = ok && c <= p.n && st <= p.n - c;
         if (ok && c && st + c > p.cap)     // the chunk reaches the overflow range
             ok = c_ovf[d] >= p.ovf0 && c_ovf[d] - p.ovf0 <= p.n - (st + c - p.cap);
@@ -348,16 +365,15 @@ __global__ void __launch_bounds__(1024) k_tile_step(TileParams p, StepIO io, uin
     if (!ok && tid == 0)
         __hip_atomic_fetch_or(p.err, ERR_TILE_LISTS, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const uint2 *in = io.rec_in;
-    // slot of entry v of the tile's input (the 9 chunks one after another)
+    // slot of entry v of the tile's input (the 9 chunks one after another,
+    // in list order: the stay chunk first)
     auto slot_of = [&](uint32_t v) {
-        uint32_t d = STAY, pd = pre[STAY];
-        if (v < pre[STAY] || v >= pre[STAY + 1]) {   // a record that moved in (few)
-            d = 0;
-            pd = 0;
+        uint32_t d = STAY, pd = 0;
+        if (v >= pre[1]) {                          // a record that moved in (few)
 #pragma unroll
             for (uint32_t k = 1; k < 9; ++k)
                 if (v >= pre[k]) {
-                    d = k;
+                    d = group_at(k);
                     pd = pre[k];
                 }
         }
@@ -484,7 +500,7 @@ __global__ void __launch_bounds__(1024) k_tile_step(TileParams p, StepIO io, uin
         if (tid < nw * 9) {
             const uint32_t k = tid / 9, g = tid - k * 9;
             uint32_t b = 0;
-            for (uint32_t q = 0; q < g; ++q) b += gtot[q];
+            for (uint32_t q = 0; q < 9; ++q) b += group_rank(q) < group_rank(g) ? gtot[q] : 0u;
             for (uint32_t q = 0; q < k; ++q) b += wcnt[q * 9 + g];
             wbase[tid] = b;
         }
