@@ -956,8 +956,11 @@ __device__ __forceinline__ void sir_tail_group(const SirParams &p, uint32_t q, u
 // counts of step j-3: 1 = targeted binning (sir_targeted), 2 = no
 // susceptible agent left, 0 = neither.  Launch j-1 marks iff F_j = 1 and
 // launch j bins on marked cells iff F_j = 1, so the two always agree;
-// F_0 = F_1 = F_2 = 0.  Every count that is read is exact; counts nobody
-// reads are not produced.
+// F_0 = F_1 = F_2 = 0, except after a tiled segment of the same call: the
+// tiled mode's last launch then marks map 0 for the head and sets F_0 =
+// F_1 = 1, and the head's bookkeeping F_2 = 1 (any F_j = 1 is exact as
+// long as the marks of launch j-1 cover the cells read at step j).  Every
+// count that is read is exact; counts nobody reads are not produced.
 //
 // Susceptible agents never come back, so once F_j = 2 no count is read
 // again in the call, and F stays 2.  The agents' remaining steps are then
@@ -991,7 +994,8 @@ __device__ __forceinline__ uint32_t *sir_counts_of(const SirParams &p, uint32_t 
 __device__ __forceinline__ void sir_demand_book(const SirParams &p, uint32_t i)
 {
     if (threadIdx.x < 64) {
-        uint32_t flag = 0;
+        // launch 0: F_2 follows F_0 (1 only after a tiled segment)
+        uint32_t flag = i == 0 && p.nsi[NSI_FLAGS] == 1u ? 1u : 0u;
         if (i >= 1) {
             const uint32_t *c = sir_counts_of(p, i - 1);
             uint32_t a = c[threadIdx.x * NSI_STRIDE];
@@ -1255,6 +1259,8 @@ __device__ __forceinline__ void sir_head_demand(const SirParams &p, uint32_t q, 
 {
     zero_quads((uint32_t *)p.dmap[2], p.dquads, q, threads);
     if (p.cside) zero_quads((uint32_t *)coarse_of(p, p.dmap[2]), coarse_quads(p), q, threads);
+    // F_0 and F_1 are 0 unless a tiled segment of the call handed over
+    const uint32_t mode = sir_demand_modes(p, 0) & 3u;
     uint32_t S = 0;
     if (q < p.groups) {
         int4 X = load_nt4(p.x, q);
@@ -1263,7 +1269,7 @@ __device__ __forceinline__ void sir_head_demand(const SirParams &p, uint32_t q, 
         sir_move4(p, q, t, X, Y);
         store_nt4(p.x, q, X);
         store_nt4(p.y, q, Y);
-        sir_bin_mark4(p, grid_of(p, t), q, t, S, X, Y, 0u, nullptr, nullptr);
+        sir_bin_mark4(p, grid_of(p, t), q, t, S, X, Y, mode, p.dmap[0], p.dmap[1]);
     }
     sir_count_states(p, 0, q, S, q < p.groups, s_wc, block);
 }

@@ -926,6 +926,17 @@ amber_status_t enqueue_sir_tiled(amber_pop *p, uint32_t t0, uint32_t n_steps, bo
             break;
         }
     }
+    if (k < n_steps) {
+        // the gather segment's head bins on marks the column write-back
+        // makes (see k_tile_unpack and sir_demand_book)
+        const SirParams sp = sir_params(p, t0 + k);
+        tp.mark = sp.dmap[0];
+        tp.mark_cside = sp.cside;
+        const uint64_t cells = (uint64_t)r.L * r.L;
+        tp.mark_coarse = sp.dmap[0] + ((cells + 255) & ~255ull);
+        tp.mark_t = t0 + k;
+        tp.mark_flags = sp.nsi + NSI_FLAGS;
+    }
     HIP_TRY(timed(p, "sir_tile_tail", [&] { return launch_sir_tile_step(tp, t0, k, k, blk, st); }),
             "sir tile step kernel");
     // the two count grids it used go back to zero, as the other modes expect

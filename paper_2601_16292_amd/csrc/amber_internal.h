@@ -284,6 +284,17 @@ struct TileParams {
     uint32_t *err;             // sticky device error word: bit ERR_TILE_LISTS
     uint32_t *scnt;            // body launches: susceptible agents per tile after the
                                // transition (NULL: not counted)
+    // Hand-off to a gather segment (tiled, then gather): when mark is set,
+    // the launch that writes the columns back also marks, for every
+    // susceptible agent, the 3 x 3 block around its position after the move
+    // of step mark_t in demand map mark (and in its coarse map when
+    // mark_cside != 0), and sets the gather segment's first two
+    // targeted-binning flags (mark_flags[0] and [1]) to 1.
+    uint8_t *mark;
+    uint8_t *mark_coarse;
+    uint32_t mark_cside;
+    uint32_t mark_t;
+    uint32_t *mark_flags;
 };
 // Bits of the sticky device error word at ERR_FLAG_OFFSET.
 constexpr uint32_t ERR_BARRIER = 1u;      // a persistent-form barrier wait gave up

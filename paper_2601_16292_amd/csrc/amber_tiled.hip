@@ -743,29 +743,65 @@ __global__ void __launch_bounds__(1024) k_tile_scatter(TileParams p)
 
 // Columns from the tail's packed words (agent order): one thread per 4
 // agents; a last partial group writes only its agents below n.  x and y fit
-// 16 bits since L*L < 2^31.
+// 16 bits since L*L < 2^31.  With p.mark set (a gather segment follows) it
+// also marks the cells its susceptible agents read at step p.mark_t: the
+// gather segment's first launch then bins only infected agents on marked
+// cells, as its later launches do (see sir_body_demand).
 __global__ void __launch_bounds__(256) k_tile_unpack(const uint2 *__restrict__ packed,
-                                                     int32_t *__restrict__ x,
-                                                     int32_t *__restrict__ y,
-                                                     uint8_t *__restrict__ s, uint32_t n)
+                                                     TileParams p)
 {
     const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t a = 4 * q;
+    const uint32_t n = p.n;
     if (a >= n) return;
+    if (p.mark && q == 0) {
+        p.mark_flags[0] = 1u;
+        p.mark_flags[1] = 1u;
+    }
+    int32_t xs[4] = {0, 0, 0, 0}, ys[4] = {0, 0, 0, 0};
+    uint32_t ss[4] = {ST_R, ST_R, ST_R, ST_R};
     if (a + 4 <= n) {
         const uint4 u0 = ((const uint4 *)packed)[2 * q], u1 = ((const uint4 *)packed)[2 * q + 1];
-        ((int4 *)x)[q] = make_int4((int32_t)(u0.x & 0xffffu), (int32_t)(u0.z & 0xffffu),
-                                   (int32_t)(u1.x & 0xffffu), (int32_t)(u1.z & 0xffffu));
-        ((int4 *)y)[q] = make_int4((int32_t)(u0.x >> 16), (int32_t)(u0.z >> 16),
-                                   (int32_t)(u1.x >> 16), (int32_t)(u1.z >> 16));
-        ((uint32_t *)s)[q] = u0.y | (u0.w << 8) | (u1.y << 16) | (u1.w << 24);
-        return;
+        xs[0] = (int32_t)(u0.x & 0xffffu);
+        xs[1] = (int32_t)(u0.z & 0xffffu);
+        xs[2] = (int32_t)(u1.x & 0xffffu);
+        xs[3] = (int32_t)(u1.z & 0xffffu);
+        ys[0] = (int32_t)(u0.x >> 16);
+        ys[1] = (int32_t)(u0.z >> 16);
+        ys[2] = (int32_t)(u1.x >> 16);
+        ys[3] = (int32_t)(u1.z >> 16);
+        ss[0] = u0.y;
+        ss[1] = u0.w;
+        ss[2] = u1.y;
+        ss[3] = u1.w;
+        ((int4 *)p.x)[q] = make_int4(xs[0], xs[1], xs[2], xs[3]);
+        ((int4 *)p.y)[q] = make_int4(ys[0], ys[1], ys[2], ys[3]);
+        ((uint32_t *)p.s)[q] = ss[0] | (ss[1] << 8) | (ss[2] << 16) | (ss[3] << 24);
+    } else {
+        for (uint32_t j = 0; a + j < n; ++j) {
+            const uint2 u = packed[a + j];
+            xs[j] = (int32_t)(u.x & 0xffffu);
+            ys[j] = (int32_t)(u.x >> 16);
+            ss[j] = u.y;
+            p.x[a + j] = xs[j];
+            p.y[a + j] = ys[j];
+            p.s[a + j] = (uint8_t)u.y;
+        }
     }
-    for (uint32_t j = 0; a + j < n; ++j) {
-        const uint2 u = packed[a + j];
-        x[a + j] = (int32_t)(u.x & 0xffffu);
-        y[a + j] = (int32_t)(u.x >> 16);
-        s[a + j] = (uint8_t)u.y;
+    if (!p.mark) return;
+    bool any = false;
+#pragma unroll
+    for (uint32_t j = 0; j < 4; ++j) any |= a + j < n && ss[j] == ST_S;
+    if (!any) return;
+    const uint4 r = philox(q, p.mark_t, P_MOVE, p.k0, p.k1);
+    const uint32_t u[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+    for (uint32_t j = 0; j < 4; ++j) {
+        if (a + j >= n || ss[j] != ST_S) continue;
+        int32_t x2 = xs[j], y2 = ys[j];
+        moore_move(u[j], p.L, x2, y2);
+        mark_demand(p.mark, p.L, x2, y2);
+        if (p.mark_cside) mark_coarse(p.mark_coarse, p.mark_cside, p.L, x2, y2);
     }
 }
 
@@ -792,7 +828,7 @@ hipError_t step_launch(const TileParams &p, uint32_t t, uint32_t gen, uint32_t p
     if (e != hipSuccess || phase != 2) return e;
     const uint32_t groups = (p.n + 3) / 4;
     hipLaunchKernelGGL(k_tile_unpack, dim3((groups + 255) / 256), dim3(256), 0, st, io.rec_out,
-                       p.x, p.y, p.s, p.n);
+                       p);
     return hipGetLastError();
 }
 
