@@ -778,7 +778,9 @@ __global__ void __launch_bounds__(256) k_tile_unpack(const uint2 *__restrict__ p
         ((int4 *)p.y)[q] = make_int4(ys[0], ys[1], ys[2], ys[3]);
         ((uint32_t *)p.s)[q] = ss[0] | (ss[1] << 8) | (ss[2] << 16) | (ss[3] << 24);
     } else {
-        for (uint32_t j = 0; a + j < n; ++j) {
+#pragma unroll
+        for (uint32_t j = 0; j < 4; ++j) {      // constant indices: the arrays stay in registers
+            if (a + j >= n) continue;
             const uint2 u = packed[a + j];
             xs[j] = (int32_t)(u.x & 0xffffu);
             ys[j] = (int32_t)(u.x >> 16);
