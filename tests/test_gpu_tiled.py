@@ -174,6 +174,8 @@ SWITCH_CASES = [
     (40000, 200, (1, 12), (1, 200), 0, [50, 110], 2),       # tiled call, then a switch
     (40000, 200, (1, 12), (1, 200), 0, [160], 1),           # no polls: tiled throughout
     (40000, 200, (1, 12), (1, 200), 0, [50, 110], 0),       # switch only if the count is there
+    (40000, 200, (9, 10), (1, 200), 20000, [120], 2),       # no susceptible agent left at the switch
+    (40000, 200, (1, 200), (1, 200), 30000, [34], 2),       # one gather step after the switch
 ]
 
 
@@ -224,7 +226,9 @@ def test_tiled_then_gather_matches_oracle(A, O, n, L, beta, gamma, i0, chunks, p
         assert paced_bodies <= times["sir_tile_body"][0] <= all_bodies, times
     else:
         assert times["sir_tile_body"][0] == bodies, (times, bodies)
-        assert ("sir_body" in times and times["sir_body"][0] > 0) == (switches > 0), times
+        # a switch starts a gather segment with its head (a one-step segment
+        # has no body launch)
+        assert ("sir_head" in times and times["sir_head"][0] > 0) == (switches > 0), times
     assert_same(pop, ref, sum(chunks))
     pop.release()
 
