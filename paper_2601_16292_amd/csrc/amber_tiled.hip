@@ -180,12 +180,12 @@ struct StepIO {
     uint32_t *ovf_reset;       // allocator the previous launch used: back to zero
 };
 
-// Region entry (row stride RW) that ring entry k of the 9-tile neighbourhood
-// adds to, and the ring word it reads, for the tile (ti, tj) of size w x h.
-// Entries: the tile's own ring (2(w+2) + 2h), the facing column of the left
-// and right tiles (h each), the facing row of the tiles above and below
-// (w + 2 each), then 24 single cells near the corners.  Any other ring cell
-// of a neighbour lies outside the tile and its ring.
+// Ring entry k of the 9-tile neighbourhood: the ring word it reads and the
+// region entry (row stride RW) it adds to, for the tile (ti, tj) of size
+// w x h.  Only words that count cells on the tile's ring are listed (the
+// cells inside the tile are counted from its own input records): the tile's
+// own ring (2(w+2) + 2h words), then 24 single words of the 8 neighbours'
+// rings, each a ring cell next to one of the tile's corners.
 struct RingSeg {
     const uint32_t *src;
     uint32_t dst;
@@ -205,39 +205,37 @@ __device__ __forceinline__ RingSeg ring_entry(const uint32_t *R, uint32_t rs, ui
         ring_cell(k, w, h, lx, ly);
         return {ring(ti, tj) + k, (uint32_t)(ly + 1) * RW + (uint32_t)(lx + 1)};
     }
-    uint32_t q = k - n_self;
-    if (q < h) return {ring(li, tj) + 2 * (wl + 2) + h + q, (q + 1) * RW + 1};
-    q -= h;
-    if (q < h) return {ring(ri, tj) + 2 * (wr + 2) + q, (q + 1) * RW + w};
-    q -= h;
-    if (q < w + 2) return {ring(ti, uj) + w + 2 + q, RW + q};
-    q -= w + 2;
-    if (q < w + 2) return {ring(ti, dj) + q, h * RW + q};
-    q -= w + 2;
     const uint32_t b = (h + 1) * RW;        // bottom ring row
-    switch (q) {
-    case 0: return {ring(li, tj) + wl, 0};
-    case 1: return {ring(li, tj) + wl + 1, 1};
-    case 2: return {ring(li, tj) + wl + 2 + wl, b};
-    case 3: return {ring(li, tj) + wl + 2 + wl + 1, b + 1};
-    case 4: return {ring(ri, tj), w};
-    case 5: return {ring(ri, tj) + 1, w + 1};
-    case 6: return {ring(ri, tj) + wr + 2, b + w};
-    case 7: return {ring(ri, tj) + wr + 3, b + w + 1};
-    case 8: return {ring(ti, uj) + 2 * (w + 2) + hu - 1, 0};
-    case 9: return {ring(ti, uj) + 2 * (w + 2) + 2 * hu - 1, w + 1};
-    case 10: return {ring(ti, dj) + 2 * (w + 2), b};
-    case 11: return {ring(ti, dj) + 2 * (w + 2) + hd, b + w + 1};
-    case 12: return {ring(li, uj) + wl + 2 + wl + 1, RW + 1};
-    case 13: return {ring(li, uj) + wl + 2 + wl, RW};
-    case 14: return {ring(li, uj) + 2 * (wl + 2) + 2 * hu - 1, 1};
-    case 15: return {ring(ri, uj) + wr + 2, RW + w};
-    case 16: return {ring(ri, uj) + wr + 3, RW + w + 1};
-    case 17: return {ring(ri, uj) + 2 * (wr + 2) + hu - 1, w};
-    case 18: return {ring(li, dj) + wl + 1, h * RW + 1};
-    case 19: return {ring(li, dj) + wl, h * RW};
-    case 20: return {ring(li, dj) + 2 * (wl + 2) + hd, b + 1};
-    case 21: return {ring(ri, dj), h * RW + w};
+    switch (k - n_self) {
+    // the tile above: the two ends of the row below it; the tile below: of
+    // the row above it
+    case 0: return {ring(ti, uj) + w + 2, RW};
+    case 1: return {ring(ti, uj) + 2 * w + 3, RW + w + 1};
+    case 2: return {ring(ti, dj), h * RW};
+    case 3: return {ring(ti, dj) + w + 1, h * RW + w + 1};
+    // the tiles left and right: the cells of their top and bottom ring rows
+    // next to the tile
+    case 4: return {ring(li, tj) + wl, 0};
+    case 5: return {ring(li, tj) + wl + 1, 1};
+    case 6: return {ring(li, tj) + wl + 2 + wl, b};
+    case 7: return {ring(li, tj) + wl + 2 + wl + 1, b + 1};
+    case 8: return {ring(ri, tj), w};
+    case 9: return {ring(ri, tj) + 1, w + 1};
+    case 10: return {ring(ri, tj) + wr + 2, b + w};
+    case 11: return {ring(ri, tj) + wr + 3, b + w + 1};
+    // the tiles above and below: the cells of their side ring columns next
+    // to the tile
+    case 12: return {ring(ti, uj) + 2 * (w + 2) + hu - 1, 0};
+    case 13: return {ring(ti, uj) + 2 * (w + 2) + 2 * hu - 1, w + 1};
+    case 14: return {ring(ti, dj) + 2 * (w + 2), b};
+    case 15: return {ring(ti, dj) + 2 * (w + 2) + hd, b + w + 1};
+    // the four diagonal tiles: their ring cells on this tile's ring
+    case 16: return {ring(li, uj) + wl + 2 + wl, RW};
+    case 17: return {ring(li, uj) + 2 * (wl + 2) + 2 * hu - 1, 1};
+    case 18: return {ring(ri, uj) + wr + 3, RW + w + 1};
+    case 19: return {ring(ri, uj) + 2 * (wr + 2) + hu - 1, w};
+    case 20: return {ring(li, dj) + wl, h * RW};
+    case 21: return {ring(li, dj) + 2 * (wl + 2) + hd, b + 1};
     case 22: return {ring(ri, dj) + 1, h * RW + w + 1};
     default: return {ring(ri, dj) + 2 * (wr + 2), b + w};
     }
@@ -309,7 +307,8 @@ __global__ void __launch_bounds__(1024) k_tile_step(TileParams p, StepIO io, uin
     // its state at the start of that step, which is what was binned), counted
     // in LDS during the first pass.  On the ring around the tile they come
     // from memory: the border cells of the neighbouring tiles' grids plus the
-    // ring partial counts that land there.  Neither depends on the headers:
+    // ring partial counts of the 9 tiles that land there (ring_entry).
+    // Neither depends on the headers:
     // those loads go out together with the header loads, the ring cells into
     // LDS before the barrier, the first RING_PRE partial words of each thread
     // into registers (added after the first pass).
@@ -317,7 +316,7 @@ __global__ void __launch_bounds__(1024) k_tile_step(TileParams p, StepIO io, uin
     uint32_t ring_v[RING_PRE], ring_dst[RING_PRE];
     const uint32_t wl = li + 1 == nT ? last : T, wr = ri + 1 == nT ? last : T;
     const uint32_t hu = uj + 1 == nT ? last : T, hd = dj + 1 == nT ? last : T;
-    const uint32_t ring_total = 2 * (w + 2) + 2 * h + 2 * h + 2 * (w + 2) + 24;
+    const uint32_t ring_total = 2 * (w + 2) + 2 * h + 24;
     if (TRANS) {
 #pragma unroll
         for (uint32_t i = 0; i < RING_PRE; ++i) {
@@ -476,20 +475,14 @@ __global__ void __launch_bounds__(1024) k_tile_step(TileParams p, StepIO io, uin
     __syncthreads();
 
     if (TRANS) {
-        // ring partial counts that land on the ring (those that land inside
-        // the tile are records of its input, already counted): the words
-        // loaded before the first barrier, then any beyond them
-        auto on_ring = [&](uint32_t dst) {
-            const uint32_t ry = dst / RW, rx = dst - ry * RW;
-            return ry == 0 || ry > h || rx == 0 || rx > w;
-        };
+        // ring partial counts: the words loaded before the first barrier,
+        // then any beyond them
 #pragma unroll
         for (uint32_t i = 0; i < RING_PRE; ++i)
-            if (ring_v[i] && on_ring(ring_dst[i])) atomicAdd(&reg[ring_dst[i]], ring_v[i]);
+            if (ring_v[i]) atomicAdd(&reg[ring_dst[i]], ring_v[i]);
         for (uint32_t k = tid + RING_PRE * NT; k < ring_total; k += NT) {
             const RingSeg e = ring_entry<RW>(io.ring_in, p.rs, nT, k, ti, tj, li, ri, uj,
                                              dj, w, h, wl, wr, hu, hd);
-            if (!on_ring(e.dst)) continue;
             const uint32_t v = *e.src;
             if (v) atomicAdd(&reg[e.dst], v);
         }
