@@ -670,7 +670,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(runs and replicates are independent; see the sharding design notes). "
               "Use --gpus 1.", file=sys.stderr)
         sys.exit(2)

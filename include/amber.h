@@ -80,7 +80,7 @@ typedef enum {
     AMBER_E_NOMEM = -2,        /* host allocation failed / workspace too small */
     AMBER_E_DEVICE = -3,       /* a HIP call failed                          */
     AMBER_E_STATE = -4,        /* handle misuse (released, mixed devices)    */
-    AMBER_E_UNSUPPORTED = -5   /* valid but outside what this build supports */
+    AMBER_E_UNSUPPORTED = -5   /* valid but outside what the library supports */
 } amber_status_t;
 
 typedef enum {
