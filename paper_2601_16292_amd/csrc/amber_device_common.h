@@ -1174,8 +1174,11 @@ __device__ __forceinline__ void sir_bin_mark4(const SirParams &p, uint32_t *__re
 // one lane per consecutive step, and each agent takes the first of its m
 // draws that hits.  A group then needs a draw only while it holds an
 // infected agent, and the wavefront runs about as many rounds as the sum of
-// those draws over 64.  Returns the bits of the agents still infected.
-// Every lane of the wavefront must call it.
+// those draws over 64.  While more than 32 groups draw, m would be 1 and the
+// sharing would only move each group's draw to another lane: each lane then
+// draws its own group's next step, with none of the lane exchanges.  Returns
+// the bits of the agents still infected.  Every lane of the wavefront must
+// call it.
 __device__ __forceinline__ uint32_t sir_recover_wave(const SirParams &p, uint32_t q, uint32_t inf,
                                                      uint32_t u0, uint32_t u1)
 {
@@ -1187,6 +1190,15 @@ __device__ __forceinline__ uint32_t sir_recover_wave(const SirParams &p, uint32_
         const uint64_t A = __ballot(active);
         if (A == 0) break;
         const uint32_t na = (uint32_t)__popcll(A);
+        if (na > 32) {                                          // wavefront-uniform
+            if (active) {
+                const uint4 r = philox(q, u1 + 1 - left, P_EPI, p.k0, p.k1);
+                inf &= ~((r.x < p.t_rec ? 1u : 0u) | (r.y < p.t_rec ? 2u : 0u) |
+                         (r.z < p.t_rec ? 4u : 0u) | (r.w < p.t_rec ? 8u : 0u));
+                left -= 1;
+            }
+            continue;
+        }
         const uint32_t m = 64u / na;                            // lanes per group
         // rank of the active lanes 0 .. na-1 in lane order (the inactive ones
         // after them), and lane_of[r] = the lane of rank r
